@@ -1,0 +1,204 @@
+/*
+ * fvm.h -- C interface of libfvm, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of an incompressible finite-volume PISO / SIMPLE
+ * solver on unstructured meshes (Tomczak et al., "Complete PISO and SIMPLE
+ * solvers on Graphics Processing Units").
+ *
+ * Problem statement (paper, Section 3.1): the domain is a mesh of N
+ * polyhedral cells; every face belongs to exactly two cells or is a boundary
+ * face; pressure p and velocity U live at cell centroids; each solve is a
+ * sparse system A x = b with A_ij != 0 iff cells i and j share a face or
+ * i == j, assembled from per-face quantities many times per run.  Arbitrary
+ * (non-orthogonal) meshes and time-dependent boundary values are supported
+ * (Sections 2 and 6).  Double precision throughout (Section 4.2), plus an
+ * optional FP32-inner / FP64-refinement mode.
+ *
+ * Conventions shared by every call:
+ *   - Return value: FVM_OK (0); > 0 a warning with valid results
+ *     (FVM_WARN_MAXITER: some solve stopped at max_iter); < 0 an error, in
+ *     which case the case state is unchanged (a failed step is rolled back to
+ *     its start).  fvm_last_error() gives a thread-local message.
+ *   - Host arrays (mesh description) are read during the call only; the
+ *     caller keeps ownership.  Device arrays (d_*) are caller-owned device
+ *     memory; the library never allocates device memory: every case lives in
+ *     the caller's workspace buffer.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *     it; calls that return solver information synchronise on it.
+ *   - All indices are in the caller's numbering: cells are never renumbered,
+ *     faces are reordered internally and mapped back on output.
+ *   - A handle is not thread-safe; distinct cases may run on distinct streams.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef FVM_H
+#define FVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fvm_status;
+enum {
+    FVM_OK = 0,
+    FVM_WARN_MAXITER = 1,
+    FVM_EINVAL = -1,     /* malformed mesh / arguments */
+    FVM_ENOMEM = -2,     /* workspace too small */
+    FVM_ENUMERIC = -3,   /* non-finite value or Krylov breakdown */
+    FVM_EDEVICE = -4     /* HIP runtime error */
+};
+
+/* Boundary kind of a patch, for U and for p independently.
+ * FIXED: the patch value; ZERO_GRAD: the owner-cell value; EMPTY: the face
+ * takes part in no sum (front/back of 2-D slabs). */
+enum { FVM_BC_FIXED = 0, FVM_BC_ZERO_GRAD = 1, FVM_BC_EMPTY = 2 };
+/* Pressure preconditioner: Jacobi (the paper's choice, Section 3) or
+ * diagonal incomplete Cholesky. */
+enum { FVM_PC_JACOBI = 0, FVM_PC_DIC = 1 };
+/* FVM_FP64: everything in double precision.  FVM_MIXED: the inner Krylov
+ * iterations run in FP32 inside an FP64 residual-refinement loop. */
+enum { FVM_FP64 = 0, FVM_MIXED = 1 };
+enum { FVM_CONV_LINEAR = 0, FVM_CONV_UPWIND = 1 };
+
+typedef struct fvm_mesh fvm_mesh;
+typedef struct fvm_case fvm_case;
+
+/* One boundary patch: boundary faces [start, start+size) (face indices of
+ * the mesh description) with their U and p kinds and values. */
+typedef struct {
+    int32_t start, size, u_kind, p_kind;
+    double u_value[3];
+    double p_value;
+} fvm_patch;
+
+/* Mesh description (Section 3.1).  Faces [0, n_internal_faces) are internal
+ * with owner[f] != neighbour[f]; faces [n_internal_faces, n_faces) are
+ * boundary faces of cell owner[f] and must be tiled, in order, by the
+ * patches.  Sf[f] is the face area vector pointing out of owner[f]; Cf the
+ * face centre; C the cell centres; V the cell volumes.  Vectors are [.][3]
+ * row-major doubles. */
+typedef struct {
+    int32_t n_cells, n_faces, n_internal_faces, n_patches;
+    const int32_t *owner;      /* [n_faces] */
+    const int32_t *neighbour;  /* [n_internal_faces] */
+    const double *Sf;          /* [n_faces][3] */
+    const double *Cf;          /* [n_faces][3] */
+    const double *C;           /* [n_cells][3] */
+    const double *V;           /* [n_cells] */
+    const fvm_patch *patches;  /* [n_patches] */
+} fvm_mesh_desc;
+
+/* Krylov controls: stop when the normalised L1 residual
+ * sum|b - A x| / n_f  <=  max(tol, rel_tol * initial value), or at max_iter
+ * (the paper stops on residual thresholds, Section 4.3.1). */
+typedef struct {
+    double tol, rel_tol;
+    int32_t max_iter, precond;
+} fvm_solver_ctl;
+
+typedef struct {
+    double nu;             /* kinematic viscosity */
+    double dt;             /* PISO time step */
+    double alpha_u;        /* SIMPLE implicit momentum relaxation */
+    double alpha_p;        /* SIMPLE explicit pressure relaxation */
+    double p_ref_value;    /* pressure level at p_ref_cell when no p patch is FIXED */
+    double inner_rel_tol;  /* FVM_MIXED: relative reduction of each FP32 inner solve */
+    int32_t n_corr;        /* PISO pressure correctors per step */
+    int32_t n_non_orth_corr;
+    int32_t convection;    /* FVM_CONV_* */
+    int32_t precision;     /* FVM_FP64 | FVM_MIXED */
+    int32_t p_ref_cell;    /* caller's cell index */
+    int32_t inner_max_iter;
+    fvm_solver_ctl p_ctl, u_ctl;
+} fvm_case_opts;
+
+typedef struct {
+    int32_t iters, status;
+    double res_initial, res_final;
+} fvm_solve_info;
+
+typedef struct {
+    fvm_solve_info u[3];       /* momentum predictor, per component */
+    fvm_solve_info p[16];      /* pressure solves in order */
+    int32_t n_p_solves, status;
+} fvm_step_info;
+
+/* fvm_mesh_create -- ingest a mesh (Section 3.1): validate it, canonicalise
+ * the internal faces (lower cell index owns the face, sorted by owner then
+ * neighbour), and build the cell-to-face index ranges used by every gather.
+ * Host-side only; no device memory.  Errors: FVM_EINVAL for an index out of
+ * range, owner == neighbour, a duplicated face, S.d <= 0, V <= 0, patches
+ * that do not tile the boundary faces, or an unknown kind. */
+fvm_status fvm_mesh_create(const fvm_mesh_desc *desc, fvm_mesh **out);
+void fvm_mesh_destroy(fvm_mesh *mesh);
+/* Sizes and whether any face is non-orthogonal (S not parallel to d). */
+fvm_status fvm_mesh_info(const fvm_mesh *mesh, int32_t *n_cells, int32_t *n_faces, int32_t *n_internal_faces,
+                         int32_t *non_orthogonal);
+
+/* Exact device workspace size of a case of this mesh with these options
+ * (admission control of many resident cases relies on it being exact). */
+fvm_status fvm_case_workspace_bytes(const fvm_mesh *mesh, const fvm_case_opts *opts, size_t *bytes);
+
+/* fvm_case_create -- lay a case out in the caller's device workspace
+ * (bytes >= fvm_case_workspace_bytes, 256-byte aligned), upload the mesh,
+ * derive the face geometry coefficients on the device and set U = 0,
+ * p = 0 and phi = the boundary fluxes of U.  The mesh may be destroyed
+ * afterwards.  Errors: FVM_ENOMEM if bytes is too small. */
+fvm_status fvm_case_create(const fvm_mesh *mesh, const fvm_case_opts *opts, void *d_workspace, size_t bytes,
+                           void *stream, fvm_case **out);
+void fvm_case_destroy(fvm_case *c);    /* the workspace stays the caller's */
+
+/* State exchange on `stream`, caller numbering: d_U [n_cells][3], d_p
+ * [n_cells], d_phi [n_faces] (flux along the caller's Sf).  set_state with
+ * d_phi == NULL sets phi = S.(interpolated U) with boundary values from the
+ * patches.  Any pointer may be NULL in get_state. */
+fvm_status fvm_case_set_state(fvm_case *c, const double *d_U, const double *d_p, const double *d_phi, void *stream);
+fvm_status fvm_case_get_state(const fvm_case *c, double *d_U, double *d_p, double *d_phi, void *stream);
+/* Time-dependent boundary values (Sections 2 and 6): replace a patch's U and
+ * p values, effective for work enqueued afterwards on `stream`. */
+fvm_status fvm_case_set_patch_value(fvm_case *c, int32_t patch, const double u_value[3], double p_value,
+                                    void *stream);
+
+/* piso_step -- n_steps transient PISO steps (Section 3): momentum predictor
+ * (BiCG, Jacobi), then n_corr pressure correctors (CG with the case's
+ * preconditioner, explicit flux and velocity corrections).  `last` (may be
+ * NULL) receives the solver record of the final step. */
+fvm_status piso_step(fvm_case *c, int32_t n_steps, void *stream, fvm_step_info *last);
+
+/* simple_iterate -- steady SIMPLE iterations (Section 3) with implicit
+ * momentum relaxation alpha_u and explicit pressure relaxation alpha_p, until
+ * all four initial residuals (U_x, U_y, U_z, p) of an iteration are
+ * <= res_tol, or max_iters. */
+fvm_status simple_iterate(fvm_case *c, int32_t max_iters, double res_tol, void *stream, int32_t *iters_done,
+                          fvm_step_info *last);
+
+/* solve_pressure -- the pressure equation alone: the symmetric system whose
+ * face coefficients are d_gamma_f[f] * |S_f|^2 / (S_f . d_f) (d_gamma_f in
+ * the caller's face order, boundary entries used on FIXED-p patches), with
+ * b = d_rhs + fixed-p boundary terms, pinned at p_ref_cell when no p patch
+ * is FIXED, solved by CG (ctl->precond) from the guess in d_p. */
+fvm_status solve_pressure(fvm_case *c, const double *d_gamma_f, const double *d_rhs, double *d_p,
+                          const fvm_solver_ctl *ctl, void *stream, fvm_solve_info *info);
+
+/* piso_step_batch -- advance several resident cases by n_steps PISO steps,
+ * their kernels batched into shared launches (continuous-batching serving).
+ * Every case must be FVM_MIXED or every case FVM_FP64.  infos[i] (may be
+ * NULL) receives case i's last-step record.  Each case's result is the same
+ * as piso_step on it alone. */
+fvm_status piso_step_batch(fvm_case *const *cases, int32_t n_cases, int32_t n_steps, void *stream,
+                           fvm_step_info *infos);
+
+/* Kernel timing for measurement: while enabled, every launch of a kernel
+ * class is bracketed by HIP events on the stream it runs on; read returns the
+ * summed device time (ms) and launch count of one class (e.g. "pcg_spmv") and
+ * waits for the recorded events.  enable(1) also clears the record. */
+fvm_status fvm_profile_enable(int32_t on);
+fvm_status fvm_profile_read(const char *kernel_class, double *total_ms, int64_t *launches);
+
+const char *fvm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVM_H */

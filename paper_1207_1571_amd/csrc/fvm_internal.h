@@ -1,0 +1,161 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fvm.h"
+
+struct ihipStream_t;
+typedef struct ihipStream_t *hipStream_t;
+
+// ---------------------------------------------------------------------------
+// Host-side canonical mesh (built by fvm_mesh_create, uploaded per case)
+// ---------------------------------------------------------------------------
+struct fvm_mesh {
+    int32_t N = 0, F = 0, Fi = 0, Fb = 0, npatch = 0;
+    // internal faces in canonical order: own[c] < nei[c], sorted by (own, nei);
+    // own[] continues over the boundary faces (caller order) with their cells
+    std::vector<int32_t> own, nei;
+    std::vector<int32_t> face_user;   // canonical internal face -> caller's face index
+    std::vector<int32_t> face_sign;   // +1, or -1 when the caller's orientation is reversed
+    std::vector<int32_t> own_start;   // [N+1] faces owned by cell i: [own_start[i], own_start[i+1])
+    std::vector<int32_t> nbr_start;   // [N+1] range of losort holding the faces whose neighbour is i
+    std::vector<int32_t> losort;      // [Fi] canonical faces ordered by (nei, own)
+    std::vector<int32_t> bnd_start;   // [N+1] range of bnd_list holding the boundary faces of cell i
+    std::vector<int32_t> bnd_list;    // [Fb] boundary face ids (0-based within the boundary block)
+    std::vector<int32_t> bpatch;      // [Fb] patch of each boundary face
+    // geometry, structure-of-arrays: x block then y then z
+    std::vector<double> S;            // [3*F] canonical orientation (internal), caller order (boundary)
+    std::vector<double> Cf;           // [3*F]
+    std::vector<double> C;            // [3*N]
+    std::vector<double> V;            // [N]
+    std::vector<fvm_patch> patches;
+    bool nonorth = false;
+    bool has_fixed_p = false;
+    // level schedule of the lower-triangular dependency graph (DIC sweeps):
+    // cells of level l are lvl_cells[lvl_start[l] .. lvl_start[l+1])
+    std::vector<int32_t> lvl_start, lvl_cells;
+};
+
+// ---------------------------------------------------------------------------
+// Device-resident Krylov scalars of one linear system.  Written by the last
+// block of each reducing kernel, read by the next kernels and by the host.
+// ---------------------------------------------------------------------------
+struct KState {
+    double rho;       // current r.z (CG) / z.r~ (BiCG)
+    double beta;
+    double alpha;
+    double nf;        // residual normalisation
+    double tol_eff;   // max(tol, rel_tol * nres0)
+    double nres0;
+    double nres;
+    double xbar;
+    double tol, rel_tol;
+    double scale;     // mixed precision: scaling of the demoted residual
+    double pad0;
+    int32_t iters;
+    int32_t done;     // 1: converged / stopped / failed; every iteration kernel is then a no-op
+    int32_t status;   // FVM_OK, FVM_WARN_MAXITER, FVM_ENUMERIC
+    int32_t max_iter;
+    int32_t first;    // 1 before the first direction update
+    int32_t pad[3];
+};
+static_assert(sizeof(KState) == 128, "KState layout");
+
+// maximum grid of a reducing kernel; partial-sum buffers hold this many
+// values per reduced quantity
+constexpr int kMaxGrid = 2048;
+constexpr int kBlock = 256;
+constexpr int kMaxRed = 12;          // reduced quantities per kernel
+
+// ---------------------------------------------------------------------------
+// Device view of one case: every pointer lies inside the caller's workspace.
+// ---------------------------------------------------------------------------
+struct DevCase {
+    int32_t N, F, Fi, Fb, npatch;
+    int32_t nonorth, has_fixed_p, pin_cell;
+    // topology
+    int32_t *own, *nei, *own_start, *nbr_start, *losort, *bnd_start, *bnd_list, *bpatch;
+    int32_t *face_user, *face_sign;
+    // patches
+    int32_t *patch_uk, *patch_pk;
+    double *patch_uv, *patch_pv;    // [npatch*3], [npatch]
+    // geometry (SoA)
+    double *Sx, *Sy, *Sz, *V;
+    double *w, *dl, *kx, *ky, *kz;  // w, k: internal faces; dl: all faces
+    // fields
+    double *U;       // [3][N]
+    double *p;       // [N]
+    double *phi;     // [F] canonical orientation
+    double *p_prev;  // [N]
+    double *U_save, *p_save, *phi_save;   // start-of-step copies (rollback)
+    // momentum system
+    double *mdiag, *upper, *lower, *src, *rhs;   // src, rhs: [3][N]
+    double *gradU;   // [9][N] (non-orthogonal meshes)
+    double *ns;      // [3][Fi] non-orthogonal momentum source per face
+    // pressure corrector
+    double *rAU, *HbyA, *gradp, *phiH, *gam, *pdiag, *poff, *pb, *tno;
+    // Krylov work vectors
+    double *r, *rt, *pp, *pt, *q, *qt;           // [3][N] each (CG uses component 0)
+    double *z;                                   // [N] DIC output
+    double *dstar;                               // [N] DIC diagonal
+    int32_t *lvl_start, *lvl_cells;              // DIC level schedule
+    int32_t n_levels;
+    // FP32 copies (mixed precision)
+    float *f_diag, *f_up, *f_lo, *f_pdiag, *f_poff;
+    float *f_x, *f_b, *f_r, *f_rt, *f_p, *f_pt, *f_q, *f_qt;   // [3][N]
+    // reductions
+    double *partials;                            // [kMaxRed][kMaxGrid]
+    unsigned int *ticket;
+    KState *ks;                                  // [4]: 0..2 momentum components, 3 pressure
+    // setup temporaries (alias Krylov vectors)
+    double *tmpC, *tmpCf;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (kernels.hip).  All enqueue on `s`; none synchronises.
+// ---------------------------------------------------------------------------
+int grid_for(int n);
+
+void launch_geometry(const DevCase &d, hipStream_t s);
+void launch_flux_from_U(const DevCase &d, hipStream_t s);
+void launch_U_in(const DevCase &d, const double *U_user, hipStream_t s);
+void launch_U_out(const DevCase &d, double *U_user, hipStream_t s);
+void launch_phi_in(const DevCase &d, const double *phi_user, hipStream_t s);
+void launch_phi_out(const DevCase &d, double *phi_user, hipStream_t s);
+void launch_gather_faces(const DevCase &d, const double *user_face_vals, double *canon, hipStream_t s);
+
+// momentum assembly: transient (dt > 0) or SIMPLE-relaxed (alpha_u < 1)
+void launch_gradU(const DevCase &d, hipStream_t s);
+void launch_mom_face(const DevCase &d, double nu, int upwind, hipStream_t s);
+void launch_mom_cell(const DevCase &d, double nu, double dt, double alpha_u, int upwind, hipStream_t s);
+
+// pressure corrector pieces
+void launch_hbya(const DevCase &d, int with_gradp, hipStream_t s);
+void launch_gradp(const DevCase &d, hipStream_t s);
+void launch_p_face(const DevCase &d, hipStream_t s);
+void launch_p_cell(const DevCase &d, double p_ref, hipStream_t s);
+void launch_p_system_from_gamma(const DevCase &d, const double *gamma_canon, const double *rhs, double p_ref,
+                                hipStream_t s);
+void launch_flux_corr(const DevCase &d, hipStream_t s);
+void launch_p_relax(const DevCase &d, double alpha_p, hipStream_t s);
+void launch_U_corr(const DevCase &d, hipStream_t s);
+
+// Krylov: momentum BiCG on the three components (FP64)
+void launch_bicg_init(const DevCase &d, hipStream_t s);
+void launch_bicg_iter(const DevCase &d, hipStream_t s);
+// Krylov: pressure CG (FP64), Jacobi or DIC
+void launch_pcg_init(const DevCase &d, int dic, hipStream_t s);
+void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s);
+void launch_dic_setup(const DevCase &d, hipStream_t s);
+
+// scalar parameters passed by value (no host staging buffers)
+void launch_set_ctl(const DevCase &d, int first, int count, double tol, double rel_tol, int max_iter, hipStream_t s);
+void launch_set_patch(const DevCase &d, int patch, double u0, double u1, double u2, double pv, hipStream_t s);
+
+// profiling
+void prof_begin(const char *cls, hipStream_t s);
+void prof_end(const char *cls, hipStream_t s);

@@ -1,0 +1,986 @@
+// HIP kernels (gfx950) of the finite-volume PISO / SIMPLE hot path.
+//
+// Layout (all device memory in the caller's workspace):
+//   * internal faces canonical (own < nei), sorted by (own, nei): the faces a
+//     cell owns are the contiguous range own_start[i]..own_start[i+1];
+//   * losort lists the same faces ordered by (nei, own): the faces a cell
+//     sees from the neighbour side are losort[nbr_start[i]..nbr_start[i+1]];
+//   * boundary faces are listed per cell through bnd_start / bnd_list;
+//   * vectors of three components are structure-of-arrays [3][N].
+// Face quantities are produced once per face by face-parallel kernels
+// (coalesced streams over faces) and consumed by cell-parallel gathers; a
+// cell sums its faces in a fixed order (owned faces, then neighbour-side
+// faces, then boundary faces), so every result is deterministic and no
+// floating-point atomics are used.
+//
+// Work decomposition: each block handles one contiguous chunk of cells in
+// 256-wide tiles.  Block b runs on XCD b % 8; the chunk index is remapped so
+// that each XCD walks one contiguous eighth of the cells, which keeps the
+// neighbour gathers of a chunk in the L2 of the XCD that produced them.
+//
+// Reductions: a wave reduces with xor shuffles, a block through LDS, and the
+// last block to finish (integer ticket) sums the per-block partials in a
+// fixed order and updates the Krylov scalars in device memory.  The next
+// kernels read those scalars; a solve never synchronises with the host per
+// iteration, and every iteration kernel is a no-op once its system is done.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fvm_internal.h"
+
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ int logical_block()
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    return (G & 7) == 0 ? ((b & 7) * (G >> 3) + (b >> 3)) : b;
+}
+
+struct Range {
+    int beg, end;
+};
+
+__device__ __forceinline__ Range block_range(int n)
+{
+    const int G = gridDim.x;
+    long per = ((long)n + G - 1) / G;
+    per = (per + kBlock - 1) / kBlock * kBlock;
+    long b = (long)logical_block() * per;
+    Range r;
+    r.beg = (int)(b < n ? b : n);
+    r.end = (int)(b + per < n ? b + per : n);
+    return r;
+}
+
+template <int NV>
+__device__ __forceinline__ void wave_sum(double (&v)[NV])
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+}
+
+// Block partial of NV sums -> per-block slot; returns true in every thread of
+// the last block, with the grid totals in tot[] (LDS, valid after return).
+template <int NV>
+__device__ bool reduce_last(double (&v)[NV], double *partials, unsigned int *ticket, double *tot)
+{
+    __shared__ double lds[NV][kWaves];
+    __shared__ int amlast;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    wave_sum(v);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k][wv] = v[k];
+    __syncthreads();
+    const int G = gridDim.x;
+    if (threadIdx.x == 0) {
+        const int lb = logical_block();
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = lds[k][0];
+            for (int w = 1; w < kWaves; ++w) s += lds[k][w];
+            __hip_atomic_store(&partials[k * kMaxGrid + lb], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        unsigned int t = atomicAdd(ticket, 1u);
+        amlast = (t == (unsigned int)G - 1);
+    }
+    __syncthreads();
+    if (!amlast) return false;
+    __threadfence();
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        acc[k] = 0.0;
+        for (int j = threadIdx.x; j < G; j += kBlock)
+            acc[k] += __hip_atomic_load(&partials[k * kMaxGrid + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    wave_sum(acc);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k][wv] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = lds[k][0];
+            for (int w = 1; w < kWaves; ++w) s += lds[k][w];
+            tot[k] = s;
+        }
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return true;
+}
+
+// y_i = diag_i x_i + sum_owned up_f x_nei + sum_nbrside lo_f x_own
+__device__ __forceinline__ double row_apply(const DevCase &d, int i, const double *__restrict__ diag,
+                                            const double *__restrict__ up, const double *__restrict__ lo,
+                                            const double *__restrict__ x)
+{
+    double acc = diag[i] * x[i];
+    const int f0 = d.own_start[i], f1 = d.own_start[i + 1];
+    for (int f = f0; f < f1; ++f) acc += up[f] * x[d.nei[f]];
+    const int k0 = d.nbr_start[i], k1 = d.nbr_start[i + 1];
+    for (int k = k0; k < k1; ++k) {
+        const int f = d.losort[k];
+        acc += lo[f] * x[d.own[f]];
+    }
+    return acc;
+}
+
+// row sum of the off-diagonal coefficients plus the diagonal (A 1)_i
+__device__ __forceinline__ double row_sum(const DevCase &d, int i, const double *__restrict__ diag,
+                                          const double *__restrict__ up, const double *__restrict__ lo)
+{
+    double acc = diag[i];
+    for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) acc += up[f];
+    for (int k = d.nbr_start[i]; k < d.nbr_start[i + 1]; ++k) acc += lo[d.losort[k]];
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Setup and state exchange
+// ---------------------------------------------------------------------------
+
+// w = S.(C_N - Cf)/(S.d), dl = |S|^2/(S.d), k = S - dl d (internal);
+// dl_b = |S|^2/(S.(Cf - C_P)) (boundary)
+__global__ void k_geometry(DevCase d)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    const double *C = d.tmpC, *Cf = d.tmpCf;
+    const int N = d.N, F = d.F;
+    const double S0 = d.Sx[f], S1 = d.Sy[f], S2 = d.Sz[f];
+    const double SS = S0 * S0 + S1 * S1 + S2 * S2;
+    if (f < d.Fi) {
+        const int P = d.own[f], Q = d.nei[f];
+        const double d0 = C[Q] - C[P], d1 = C[N + Q] - C[N + P], d2 = C[2 * N + Q] - C[2 * N + P];
+        const double Sd = S0 * d0 + S1 * d1 + S2 * d2;
+        const double n0 = C[Q] - Cf[f], n1 = C[N + Q] - Cf[F + f], n2 = C[2 * N + Q] - Cf[2 * F + f];
+        d.w[f] = (S0 * n0 + S1 * n1 + S2 * n2) / Sd;
+        const double dl = SS / Sd;
+        d.dl[f] = dl;
+        if (d.nonorth) {
+            d.kx[f] = S0 - dl * d0;
+            d.ky[f] = S1 - dl * d1;
+            d.kz[f] = S2 - dl * d2;
+        }
+    } else {
+        const int P = d.own[f];
+        const double d0 = Cf[f] - C[P], d1 = Cf[F + f] - C[N + P], d2 = Cf[2 * F + f] - C[2 * N + P];
+        d.dl[f] = SS / (S0 * d0 + S1 * d1 + S2 * d2);
+    }
+}
+
+// phi = S.(w U_P + (1-w) U_N) internal; FIXED S.U_b, ZERO_GRAD S.U_P, EMPTY 0
+__global__ void k_flux_from_U(DevCase d)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    const int N = d.N;
+    const double *U = d.U;
+    double v0, v1, v2;
+    if (f < d.Fi) {
+        const int P = d.own[f], Q = d.nei[f];
+        const double w = d.w[f];
+        v0 = w * U[P] + (1.0 - w) * U[Q];
+        v1 = w * U[N + P] + (1.0 - w) * U[N + Q];
+        v2 = w * U[2 * N + P] + (1.0 - w) * U[2 * N + Q];
+    } else {
+        const int b = f - d.Fi, P = d.own[f], pt = d.bpatch[b], k = d.patch_uk[pt];
+        if (k == FVM_BC_FIXED) {
+            v0 = d.patch_uv[3 * pt]; v1 = d.patch_uv[3 * pt + 1]; v2 = d.patch_uv[3 * pt + 2];
+        } else if (k == FVM_BC_ZERO_GRAD) {
+            v0 = U[P]; v1 = U[N + P]; v2 = U[2 * N + P];
+        } else {
+            d.phi[f] = 0.0;
+            return;
+        }
+    }
+    d.phi[f] = d.Sx[f] * v0 + d.Sy[f] * v1 + d.Sz[f] * v2;
+}
+
+__global__ void k_U_in(DevCase d, const double *__restrict__ Uu)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    d.U[i] = Uu[3 * (size_t)i];
+    d.U[d.N + i] = Uu[3 * (size_t)i + 1];
+    d.U[2 * d.N + i] = Uu[3 * (size_t)i + 2];
+}
+
+__global__ void k_U_out(DevCase d, double *__restrict__ Uu)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    Uu[3 * (size_t)i] = d.U[i];
+    Uu[3 * (size_t)i + 1] = d.U[d.N + i];
+    Uu[3 * (size_t)i + 2] = d.U[2 * d.N + i];
+}
+
+__global__ void k_phi_in(DevCase d, const double *__restrict__ pu)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    d.phi[f] = f < d.Fi ? (double)d.face_sign[f] * pu[d.face_user[f]] : pu[f];
+}
+
+__global__ void k_phi_out(DevCase d, double *__restrict__ pu)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    if (f < d.Fi) pu[d.face_user[f]] = (double)d.face_sign[f] * d.phi[f];
+    else pu[f] = d.phi[f];
+}
+
+// caller face order -> canonical order (orientation-free face values)
+__global__ void k_gather_faces(DevCase d, const double *__restrict__ uv, double *__restrict__ out)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    out[f] = f < d.Fi ? uv[d.face_user[f]] : uv[f];
+}
+
+// ---------------------------------------------------------------------------
+// Momentum assembly
+// ---------------------------------------------------------------------------
+
+// Gauss gradient of a cell scalar x with the boundary rule of `kinds`/`vals`
+// (FIXED value, ZERO_GRAD owner value, EMPTY skipped); returns sum S phi_f
+// (not divided by V)
+__device__ __forceinline__ void gauss_sum(const DevCase &d, int i, const double *__restrict__ x,
+                                          const int32_t *__restrict__ kinds, const double *__restrict__ vals,
+                                          int vstride, double &g0, double &g1, double &g2)
+{
+    const double xi = x[i];
+    g0 = g1 = g2 = 0.0;
+    for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) {
+        const double w = d.w[f];
+        const double pf = w * xi + (1.0 - w) * x[d.nei[f]];
+        g0 += d.Sx[f] * pf; g1 += d.Sy[f] * pf; g2 += d.Sz[f] * pf;
+    }
+    for (int k = d.nbr_start[i]; k < d.nbr_start[i + 1]; ++k) {
+        const int f = d.losort[k];
+        const double w = d.w[f];
+        const double pf = w * x[d.own[f]] + (1.0 - w) * xi;
+        g0 -= d.Sx[f] * pf; g1 -= d.Sy[f] * pf; g2 -= d.Sz[f] * pf;
+    }
+    for (int k = d.bnd_start[i]; k < d.bnd_start[i + 1]; ++k) {
+        const int b = d.bnd_list[k], f = d.Fi + b, pt = d.bpatch[b], kind = kinds[pt];
+        if (kind == FVM_BC_EMPTY) continue;
+        const double pf = kind == FVM_BC_FIXED ? vals[vstride * pt] : xi;
+        g0 += d.Sx[f] * pf; g1 += d.Sy[f] * pf; g2 += d.Sz[f] * pf;
+    }
+}
+
+// gradU[3c + k][i] = d U_c / d x_k (start-of-step U; non-orthogonal meshes)
+__global__ void k_gradU(DevCase d)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const int N = d.N;
+    for (int c = 0; c < 3; ++c) {
+        double g0, g1, g2;
+        gauss_sum(d, i, d.U + (size_t)c * N, d.patch_uk, d.patch_uv + c, 3, g0, g1, g2);
+        const double V = d.V[i];
+        d.gradU[(size_t)(3 * c) * N + i] = g0 / V;
+        d.gradU[(size_t)(3 * c + 1) * N + i] = g1 / V;
+        d.gradU[(size_t)(3 * c + 2) * N + i] = g2 / V;
+    }
+}
+
+// upper = F(1-w) - nu dl, lower = -F w - nu dl; non-orthogonal source
+// ns_c = nu k.(w gradU_c,P + (1-w) gradU_c,N)
+__global__ void k_mom_face(DevCase d, double nu, int upwind)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.Fi) return;
+    const double Fl = d.phi[f];
+    const double w = upwind ? (Fl >= 0.0 ? 1.0 : 0.0) : d.w[f];
+    const double D = nu * d.dl[f];
+    d.upper[f] = Fl * (1.0 - w) - D;
+    d.lower[f] = -Fl * w - D;
+    if (d.nonorth) {
+        const int N = d.N, P = d.own[f], Q = d.nei[f];
+        const double wi = d.w[f];
+        const double k0 = d.kx[f], k1 = d.ky[f], k2 = d.kz[f];
+        for (int c = 0; c < 3; ++c) {
+            const double *g = d.gradU + (size_t)(3 * c) * N;
+            const double a0 = wi * g[P] + (1.0 - wi) * g[Q];
+            const double a1 = wi * g[N + P] + (1.0 - wi) * g[N + Q];
+            const double a2 = wi * g[2 * N + P] + (1.0 - wi) * g[2 * N + Q];
+            d.ns[(size_t)c * d.Fi + f] = nu * (k0 * a0 + k1 * a1 + k2 * a2);
+        }
+    }
+}
+
+// diag, src (without the pressure gradient) and rhs = src - V grad p.
+// dt > 0: transient term V/dt, V U/dt.  alpha_u < 1: implicit relaxation
+// diag <- diag/alpha, src += (1-alpha)/alpha diag_orig U.
+__global__ void k_mom_cell(DevCase d, double nu, double dt, double alpha_u, int upwind)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const int N = d.N;
+    const double V = d.V[i];
+    const double U0 = d.U[i], U1 = d.U[N + i], U2 = d.U[2 * N + i];
+    double dg = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (dt > 0.0) {
+        dg = V / dt;
+        s0 = V * U0 / dt; s1 = V * U1 / dt; s2 = V * U2 / dt;
+    }
+    const double pi = d.p[i];
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) {
+        const double Fl = d.phi[f];
+        const double w = d.w[f];
+        const double we = upwind ? (Fl >= 0.0 ? 1.0 : 0.0) : w;
+        dg += Fl * we + nu * d.dl[f];
+        const double pf = w * pi + (1.0 - w) * d.p[d.nei[f]];
+        g0 += d.Sx[f] * pf; g1 += d.Sy[f] * pf; g2 += d.Sz[f] * pf;
+        if (d.nonorth) {
+            s0 += d.ns[f]; s1 += d.ns[(size_t)d.Fi + f]; s2 += d.ns[2 * (size_t)d.Fi + f];
+        }
+    }
+    for (int k = d.nbr_start[i]; k < d.nbr_start[i + 1]; ++k) {
+        const int f = d.losort[k];
+        const double Fl = d.phi[f];
+        const double w = d.w[f];
+        const double we = upwind ? (Fl >= 0.0 ? 1.0 : 0.0) : w;
+        dg += -Fl * (1.0 - we) + nu * d.dl[f];
+        const double pf = w * d.p[d.own[f]] + (1.0 - w) * pi;
+        g0 -= d.Sx[f] * pf; g1 -= d.Sy[f] * pf; g2 -= d.Sz[f] * pf;
+        if (d.nonorth) {
+            s0 -= d.ns[f]; s1 -= d.ns[(size_t)d.Fi + f]; s2 -= d.ns[2 * (size_t)d.Fi + f];
+        }
+    }
+    for (int k = d.bnd_start[i]; k < d.bnd_start[i + 1]; ++k) {
+        const int b = d.bnd_list[k], f = d.Fi + b, pt = d.bpatch[b];
+        const double Fl = d.phi[f];
+        const int uk = d.patch_uk[pt], pk = d.patch_pk[pt];
+        if (uk == FVM_BC_FIXED) {
+            const double D = nu * d.dl[f];
+            dg += D;
+            s0 += (D - Fl) * d.patch_uv[3 * pt];
+            s1 += (D - Fl) * d.patch_uv[3 * pt + 1];
+            s2 += (D - Fl) * d.patch_uv[3 * pt + 2];
+        } else if (uk == FVM_BC_ZERO_GRAD) {
+            dg += Fl;
+        }
+        if (pk != FVM_BC_EMPTY) {
+            const double pf = pk == FVM_BC_FIXED ? d.patch_pv[pt] : pi;
+            g0 += d.Sx[f] * pf; g1 += d.Sy[f] * pf; g2 += d.Sz[f] * pf;
+        }
+    }
+    if (alpha_u < 1.0) {
+        const double d0 = dg;
+        dg = d0 / alpha_u;
+        const double c = (1.0 - alpha_u) / alpha_u * d0;
+        s0 += c * U0; s1 += c * U1; s2 += c * U2;
+    }
+    d.mdiag[i] = dg;
+    d.src[i] = s0; d.src[N + i] = s1; d.src[2 * N + i] = s2;
+    d.rhs[i] = s0 - V * (g0 / V);
+    d.rhs[N + i] = s1 - V * (g1 / V);
+    d.rhs[2 * N + i] = s2 - V * (g2 / V);
+}
+
+// ---------------------------------------------------------------------------
+// Pressure corrector
+// ---------------------------------------------------------------------------
+
+// H = src - sum a_PN U_N, rAU = V/a_PP, HbyA = H/a_PP; optional grad p
+__global__ void k_hbya(DevCase d, int with_gradp)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const int N = d.N;
+    double h0 = d.src[i], h1 = d.src[N + i], h2 = d.src[2 * N + i];
+    const double *U = d.U;
+    for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) {
+        const int j = d.nei[f];
+        const double a = d.upper[f];
+        h0 -= a * U[j]; h1 -= a * U[N + j]; h2 -= a * U[2 * N + j];
+    }
+    for (int k = d.nbr_start[i]; k < d.nbr_start[i + 1]; ++k) {
+        const int f = d.losort[k], j = d.own[f];
+        const double a = d.lower[f];
+        h0 -= a * U[j]; h1 -= a * U[N + j]; h2 -= a * U[2 * N + j];
+    }
+    const double dg = d.mdiag[i];
+    d.rAU[i] = d.V[i] / dg;
+    d.HbyA[i] = h0 / dg; d.HbyA[N + i] = h1 / dg; d.HbyA[2 * N + i] = h2 / dg;
+    if (with_gradp) {
+        double g0, g1, g2;
+        gauss_sum(d, i, d.p, d.patch_pk, d.patch_pv, 1, g0, g1, g2);
+        const double V = d.V[i];
+        d.gradp[i] = g0 / V; d.gradp[N + i] = g1 / V; d.gradp[2 * N + i] = g2 / V;
+    }
+}
+
+__global__ void k_gradp(DevCase d)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    double g0, g1, g2;
+    gauss_sum(d, i, d.p, d.patch_pk, d.patch_pv, 1, g0, g1, g2);
+    const double V = d.V[i];
+    d.gradp[i] = g0 / V; d.gradp[d.N + i] = g1 / V; d.gradp[2 * d.N + i] = g2 / V;
+}
+
+// face pass: phiH = S.interp(HbyA) (boundary per U kind), gam = interp(rAU)
+// (boundary rAU_P), poff = -gam dl, tno = gam k.interp(grad p)
+__global__ void k_p_face(DevCase d)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    const int N = d.N;
+    const double *H = d.HbyA;
+    if (f < d.Fi) {
+        const int P = d.own[f], Q = d.nei[f];
+        const double w = d.w[f];
+        const double v0 = w * H[P] + (1.0 - w) * H[Q];
+        const double v1 = w * H[N + P] + (1.0 - w) * H[N + Q];
+        const double v2 = w * H[2 * N + P] + (1.0 - w) * H[2 * N + Q];
+        d.phiH[f] = d.Sx[f] * v0 + d.Sy[f] * v1 + d.Sz[f] * v2;
+        const double gm = w * d.rAU[P] + (1.0 - w) * d.rAU[Q];
+        d.gam[f] = gm;
+        d.poff[f] = -(gm * d.dl[f]);
+        if (d.nonorth) {
+            const double *g = d.gradp;
+            const double a0 = w * g[P] + (1.0 - w) * g[Q];
+            const double a1 = w * g[N + P] + (1.0 - w) * g[N + Q];
+            const double a2 = w * g[2 * N + P] + (1.0 - w) * g[2 * N + Q];
+            d.tno[f] = gm * (d.kx[f] * a0 + d.ky[f] * a1 + d.kz[f] * a2);
+        }
+    } else {
+        const int b = f - d.Fi, P = d.own[f], pt = d.bpatch[b], uk = d.patch_uk[pt];
+        double ph = 0.0;
+        if (uk == FVM_BC_FIXED)
+            ph = d.Sx[f] * d.patch_uv[3 * pt] + d.Sy[f] * d.patch_uv[3 * pt + 1] + d.Sz[f] * d.patch_uv[3 * pt + 2];
+        else if (uk == FVM_BC_ZERO_GRAD)
+            ph = d.Sx[f] * H[P] + d.Sy[f] * H[N + P] + d.Sz[f] * H[2 * N + P];
+        d.phiH[f] = ph;
+        d.gam[f] = d.rAU[P];
+    }
+}
+
+// cell pass: pdiag, pb (divergence, fixed-p terms, non-orthogonal part), pin
+__global__ void k_p_cell(DevCase d, double p_ref, int with_div)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    double dg = 0.0, b = 0.0;
+    for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) {
+        dg += -d.poff[f];
+        if (with_div) b -= d.phiH[f];
+        if (d.nonorth && with_div) b += d.tno[f];
+    }
+    for (int k = d.nbr_start[i]; k < d.nbr_start[i + 1]; ++k) {
+        const int f = d.losort[k];
+        dg += -d.poff[f];
+        if (with_div) b += d.phiH[f];
+        if (d.nonorth && with_div) b -= d.tno[f];
+    }
+    for (int k = d.bnd_start[i]; k < d.bnd_start[i + 1]; ++k) {
+        const int bb = d.bnd_list[k], f = d.Fi + bb, pt = d.bpatch[bb], pk = d.patch_pk[pt];
+        if (pk == FVM_BC_EMPTY) continue;
+        if (with_div) b -= d.phiH[f];
+        if (pk == FVM_BC_FIXED) {
+            const double g = d.gam[f] * d.dl[f];
+            dg += g;
+            b += g * d.patch_pv[pt];
+        }
+    }
+    if (i == d.pin_cell && !d.has_fixed_p) {
+        const double a = dg;
+        dg = 2.0 * a;
+        b += a * p_ref;
+    }
+    d.pdiag[i] = dg;
+    if (with_div) d.pb[i] = b;
+    else d.pb[i] += b;
+}
+
+// gamma given per face (canonical order) -> poff, gam
+__global__ void k_p_face_gamma(DevCase d, const double *__restrict__ gam)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    const double g = gam[f];
+    d.gam[f] = g;
+    if (f < d.Fi) d.poff[f] = -(g * d.dl[f]);
+}
+
+// phi = phiH - g (p_N - p_P) - tno (internal); p FIXED: phiH - g_b (p_b - p_P)
+__global__ void k_flux_corr(DevCase d)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    if (f < d.Fi) {
+        double v = d.phiH[f] - d.gam[f] * d.dl[f] * (d.p[d.nei[f]] - d.p[d.own[f]]);
+        if (d.nonorth) v -= d.tno[f];
+        d.phi[f] = v;
+    } else {
+        const int b = f - d.Fi, pt = d.bpatch[b];
+        if (d.patch_pk[pt] == FVM_BC_FIXED)
+            d.phi[f] = d.phiH[f] - d.gam[f] * d.dl[f] * (d.patch_pv[pt] - d.p[d.own[f]]);
+        else
+            d.phi[f] = d.phiH[f];
+    }
+}
+
+__global__ void k_p_relax(DevCase d, double alpha_p)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    d.p[i] = d.p_prev[i] + alpha_p * (d.p[i] - d.p_prev[i]);
+}
+
+// U = HbyA - rAU grad p (new p)
+__global__ void k_U_corr(DevCase d)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const int N = d.N;
+    double g0, g1, g2;
+    gauss_sum(d, i, d.p, d.patch_pk, d.patch_pv, 1, g0, g1, g2);
+    const double V = d.V[i], r = d.rAU[i];
+    d.U[i] = d.HbyA[i] - r * (g0 / V);
+    d.U[N + i] = d.HbyA[N + i] - r * (g1 / V);
+    d.U[2 * N + i] = d.HbyA[2 * N + i] - r * (g2 / V);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov: momentum BiCG, three components sharing one matrix
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void set_done(KState &s, int status)
+{
+    s.status = status;
+    s.done = 1;
+}
+
+// sum x_c -> xbar_c
+__global__ void __launch_bounds__(kBlock) k_bicg_sumx(DevCase d)
+{
+    const Range r = block_range(d.N);
+    const int N = d.N;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = r.beg + threadIdx.x; i < r.end; i += kBlock)
+        for (int c = 0; c < 3; ++c) v[c] += d.U[(size_t)c * N + i];
+    __shared__ double tot[3];
+    if (reduce_last<3>(v, d.partials, d.ticket, tot) && threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) d.ks[c].xbar = tot[c] / (double)N;
+}
+
+// r = b - A x, r~ = r, normalisation, first rho = z.r~ (z = r/diag)
+__global__ void __launch_bounds__(kBlock) k_bicg_init(DevCase d)
+{
+    const Range rg = block_range(d.N);
+    const int N = d.N;
+    double xb[3];
+    for (int c = 0; c < 3; ++c) xb[c] = d.ks[c].xbar;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // nf_c, |r|_c, rho_c
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const double a1 = row_sum(d, i, d.mdiag, d.upper, d.lower);
+        const double dg = d.mdiag[i];
+        for (int c = 0; c < 3; ++c) {
+            const double *x = d.U + (size_t)c * N;
+            const double ax = row_apply(d, i, d.mdiag, d.upper, d.lower, x);
+            const double b = d.rhs[(size_t)c * N + i];
+            const double r = b - ax;
+            d.r[(size_t)c * N + i] = r;
+            d.rt[(size_t)c * N + i] = r;
+            v[c] += fabs(ax - xb[c] * a1) + fabs(b - xb[c] * a1);
+            v[3 + c] += fabs(r);
+            const double z = r / dg;
+            v[6 + c] += z * r;
+        }
+    }
+    __shared__ double tot[9];
+    if (reduce_last<9>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            KState &s = d.ks[c];
+            s.nf = tot[c] + 1e-20;
+            s.nres0 = tot[3 + c] / s.nf;
+            s.nres = s.nres0;
+            s.tol_eff = fmax(s.tol, s.rel_tol * s.nres0);
+            s.iters = 0;
+            s.done = 0;
+            s.status = FVM_OK;
+            s.first = 1;
+            s.beta = 0.0;
+            if (!isfinite(s.nres0)) set_done(s, FVM_ENUMERIC);
+            else if (s.nres0 <= s.tol_eff) set_done(s, FVM_OK);
+            else if (tot[6 + c] == 0.0 || !isfinite(tot[6 + c])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+            else s.rho = tot[6 + c];
+        }
+    }
+}
+
+// p = z + beta p, p~ = z~ + beta p~ (z = r/diag, z~ = r~/diag)
+__global__ void k_bicg_dir(DevCase d)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const int N = d.N;
+    const double dg = d.mdiag[i];
+    for (int c = 0; c < 3; ++c) {
+        const KState &s = d.ks[c];
+        if (s.done) continue;
+        const size_t j = (size_t)c * N + i;
+        const double z = d.r[j] / dg, zt = d.rt[j] / dg;
+        if (s.first) {
+            d.pp[j] = z;
+            d.pt[j] = zt;
+        } else {
+            d.pp[j] = z + s.beta * d.pp[j];
+            d.pt[j] = zt + s.beta * d.pt[j];
+        }
+    }
+}
+
+// q = A p, q~ = A^T p~, p~.q -> alpha
+__global__ void __launch_bounds__(kBlock) k_bicg_spmv(DevCase d)
+{
+    int act[3];
+    for (int c = 0; c < 3; ++c) act[c] = !d.ks[c].done;
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N);
+    const int N = d.N;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const double *p = d.pp + (size_t)c * N, *pt = d.pt + (size_t)c * N;
+            const double q = row_apply(d, i, d.mdiag, d.upper, d.lower, p);
+            const double qt = row_apply(d, i, d.mdiag, d.lower, d.upper, pt);
+            d.q[(size_t)c * N + i] = q;
+            d.qt[(size_t)c * N + i] = qt;
+            v[c] += pt[i] * q;
+        }
+    }
+    __shared__ double tot[3];
+    if (reduce_last<3>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = d.ks[c];
+            if (tot[c] == 0.0 || !isfinite(tot[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else s.alpha = s.rho / tot[c];
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q, r~ -= alpha q~; rho = z.r~, |r| -> stop test, beta
+__global__ void __launch_bounds__(kBlock) k_bicg_update(DevCase d)
+{
+    int act[3];
+    double al[3];
+    for (int c = 0; c < 3; ++c) { act[c] = !d.ks[c].done; al[c] = d.ks[c].alpha; }
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N);
+    const int N = d.N;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const double dg = d.mdiag[i];
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const size_t j = (size_t)c * N + i;
+            d.U[j] += al[c] * d.pp[j];
+            const double r = d.r[j] - al[c] * d.q[j];
+            const double rt = d.rt[j] - al[c] * d.qt[j];
+            d.r[j] = r;
+            d.rt[j] = rt;
+            v[c] += (r / dg) * rt;
+            v[3 + c] += fabs(r);
+        }
+    }
+    __shared__ double tot[6];
+    if (reduce_last<6>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = d.ks[c];
+            s.iters += 1;
+            s.nres = tot[3 + c] / s.nf;
+            s.first = 0;
+            if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
+            else if (s.nres <= s.tol_eff) set_done(s, FVM_OK);
+            else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+            else if (tot[c] == 0.0 || !isfinite(tot[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else {
+                s.beta = tot[c] / s.rho;
+                s.rho = tot[c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Krylov: pressure CG (symmetric matrix pdiag / poff), Jacobi or DIC
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock) k_pcg_sumx(DevCase d)
+{
+    const Range r = block_range(d.N);
+    double v[1] = {0.0};
+    for (int i = r.beg + threadIdx.x; i < r.end; i += kBlock) v[0] += d.p[i];
+    __shared__ double tot[1];
+    if (reduce_last<1>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) d.ks[3].xbar = tot[0] / (double)d.N;
+}
+
+// r = b - A x; normalisation; Jacobi: first rho = r.(r/diag)
+__global__ void __launch_bounds__(kBlock) k_pcg_init(DevCase d, int dic)
+{
+    const Range rg = block_range(d.N);
+    const double xb = d.ks[3].xbar;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const double a1 = row_sum(d, i, d.pdiag, d.poff, d.poff);
+        const double ax = row_apply(d, i, d.pdiag, d.poff, d.poff, d.p);
+        const double b = d.pb[i];
+        const double r = b - ax;
+        d.r[i] = r;
+        v[0] += fabs(ax - xb * a1) + fabs(b - xb * a1);
+        v[1] += fabs(r);
+        if (!dic) v[2] += r * (r / d.pdiag[i]);
+    }
+    __shared__ double tot[3];
+    if (reduce_last<3>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+        KState &s = d.ks[3];
+        s.nf = tot[0] + 1e-20;
+        s.nres0 = tot[1] / s.nf;
+        s.nres = s.nres0;
+        s.tol_eff = fmax(s.tol, s.rel_tol * s.nres0);
+        s.iters = 0;
+        s.done = 0;
+        s.status = FVM_OK;
+        s.first = 1;
+        s.beta = 0.0;
+        if (!isfinite(s.nres0)) set_done(s, FVM_ENUMERIC);
+        else if (s.nres0 <= s.tol_eff) set_done(s, FVM_OK);
+        else if (!dic) {
+            if (!(tot[2] > 0.0) || !isfinite(tot[2])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+            else s.rho = tot[2];
+        }
+    }
+}
+
+// p = z + beta p (Jacobi z = r/diag; DIC z from the sweeps)
+__global__ void k_pcg_dir(DevCase d, int dic)
+{
+    const KState &s = d.ks[3];
+    if (s.done) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const double z = dic ? d.z[i] : d.r[i] / d.pdiag[i];
+    d.pp[i] = s.first ? z : z + s.beta * d.pp[i];
+}
+
+// q = A p, p.q -> alpha
+__global__ void __launch_bounds__(kBlock) k_pcg_spmv(DevCase d)
+{
+    if (d.ks[3].done) return;
+    const Range rg = block_range(d.N);
+    double v[1] = {0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const double q = row_apply(d, i, d.pdiag, d.poff, d.poff, d.pp);
+        d.q[i] = q;
+        v[0] += d.pp[i] * q;
+    }
+    __shared__ double tot[1];
+    if (reduce_last<1>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+        KState &s = d.ks[3];
+        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else s.alpha = s.rho / tot[0];
+    }
+}
+
+// x += alpha p, r -= alpha q, |r| -> stop test; Jacobi: rho = r.(r/diag), beta
+__global__ void __launch_bounds__(kBlock) k_pcg_update(DevCase d, int dic)
+{
+    if (d.ks[3].done) return;
+    const double al = d.ks[3].alpha;
+    const Range rg = block_range(d.N);
+    double v[2] = {0.0, 0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        d.p[i] += al * d.pp[i];
+        const double r = d.r[i] - al * d.q[i];
+        d.r[i] = r;
+        v[0] += fabs(r);
+        if (!dic) v[1] += r * (r / d.pdiag[i]);
+    }
+    __shared__ double tot[2];
+    if (reduce_last<2>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+        KState &s = d.ks[3];
+        s.iters += 1;
+        s.nres = tot[0] / s.nf;
+        s.first = 0;
+        if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
+        else if (s.nres <= s.tol_eff) set_done(s, FVM_OK);
+        else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+        else if (!dic) {
+            if (!(tot[1] > 0.0) || !isfinite(tot[1])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else {
+                s.beta = tot[1] / s.rho;
+                s.rho = tot[1];
+            }
+        }
+    }
+}
+
+__global__ void k_set_ctl(KState *ks, int first, int count, double tol, double rel_tol, int max_iter)
+{
+    const int k = threadIdx.x;
+    if (k >= count) return;
+    ks[first + k].tol = tol;
+    ks[first + k].rel_tol = rel_tol;
+    ks[first + k].max_iter = max_iter;
+}
+
+__global__ void k_set_patch(DevCase d, int pt, double u0, double u1, double u2, double pv)
+{
+    if (threadIdx.x != 0) return;
+    d.patch_uv[3 * pt] = u0;
+    d.patch_uv[3 * pt + 1] = u1;
+    d.patch_uv[3 * pt + 2] = u2;
+    d.patch_pv[pt] = pv;
+}
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+int grid_for(int n)
+{
+    int g = cdiv(n, kBlock);
+    if (g > kMaxGrid) g = kMaxGrid;
+    if (g >= 8) g = g / 8 * 8;
+    return g < 1 ? 1 : g;
+}
+
+#define LAUNCH_N(kern, n, s, ...)                                                             \
+    do {                                                                                      \
+        if ((n) > 0) hipLaunchKernelGGL(kern, dim3(cdiv((n), kBlock)), dim3(kBlock), 0, s, __VA_ARGS__); \
+    } while (0)
+#define LAUNCH_R(kern, n, s, ...) hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(kBlock), 0, s, __VA_ARGS__)
+
+void launch_geometry(const DevCase &d, hipStream_t s) { LAUNCH_N(k_geometry, d.F, s, d); }
+void launch_flux_from_U(const DevCase &d, hipStream_t s) { LAUNCH_N(k_flux_from_U, d.F, s, d); }
+void launch_U_in(const DevCase &d, const double *U, hipStream_t s) { LAUNCH_N(k_U_in, d.N, s, d, U); }
+void launch_U_out(const DevCase &d, double *U, hipStream_t s) { LAUNCH_N(k_U_out, d.N, s, d, U); }
+void launch_phi_in(const DevCase &d, const double *phi, hipStream_t s) { LAUNCH_N(k_phi_in, d.F, s, d, phi); }
+void launch_phi_out(const DevCase &d, double *phi, hipStream_t s) { LAUNCH_N(k_phi_out, d.F, s, d, phi); }
+void launch_gather_faces(const DevCase &d, const double *uv, double *out, hipStream_t s)
+{
+    LAUNCH_N(k_gather_faces, d.F, s, d, uv, out);
+}
+
+void launch_gradU(const DevCase &d, hipStream_t s) { LAUNCH_N(k_gradU, d.N, s, d); }
+void launch_mom_face(const DevCase &d, double nu, int upwind, hipStream_t s)
+{
+    prof_begin("mom_face", s);
+    LAUNCH_N(k_mom_face, d.Fi, s, d, nu, upwind);
+    prof_end("mom_face", s);
+}
+void launch_mom_cell(const DevCase &d, double nu, double dt, double alpha_u, int upwind, hipStream_t s)
+{
+    prof_begin("mom_cell", s);
+    LAUNCH_N(k_mom_cell, d.N, s, d, nu, dt, alpha_u, upwind);
+    prof_end("mom_cell", s);
+}
+void launch_hbya(const DevCase &d, int with_gradp, hipStream_t s)
+{
+    prof_begin("hbya", s);
+    LAUNCH_N(k_hbya, d.N, s, d, with_gradp);
+    prof_end("hbya", s);
+}
+void launch_gradp(const DevCase &d, hipStream_t s) { LAUNCH_N(k_gradp, d.N, s, d); }
+void launch_p_face(const DevCase &d, hipStream_t s)
+{
+    prof_begin("p_face", s);
+    LAUNCH_N(k_p_face, d.F, s, d);
+    prof_end("p_face", s);
+}
+void launch_p_cell(const DevCase &d, double p_ref, hipStream_t s)
+{
+    prof_begin("p_cell", s);
+    LAUNCH_N(k_p_cell, d.N, s, d, p_ref, 1);
+    prof_end("p_cell", s);
+}
+void launch_p_system_from_gamma(const DevCase &d, const double *gam, const double *rhs, double p_ref, hipStream_t s)
+{
+    LAUNCH_N(k_p_face_gamma, d.F, s, d, gam);
+    (void)hipMemcpyAsync(d.pb, rhs, sizeof(double) * (size_t)d.N, hipMemcpyDeviceToDevice, s);
+    LAUNCH_N(k_p_cell, d.N, s, d, p_ref, 0);
+}
+void launch_flux_corr(const DevCase &d, hipStream_t s)
+{
+    prof_begin("flux_corr", s);
+    LAUNCH_N(k_flux_corr, d.F, s, d);
+    prof_end("flux_corr", s);
+}
+void launch_p_relax(const DevCase &d, double alpha_p, hipStream_t s) { LAUNCH_N(k_p_relax, d.N, s, d, alpha_p); }
+void launch_U_corr(const DevCase &d, hipStream_t s)
+{
+    prof_begin("U_corr", s);
+    LAUNCH_N(k_U_corr, d.N, s, d);
+    prof_end("U_corr", s);
+}
+
+void launch_bicg_init(const DevCase &d, hipStream_t s)
+{
+    LAUNCH_R(k_bicg_sumx, d.N, s, d);
+    LAUNCH_R(k_bicg_init, d.N, s, d);
+}
+
+void launch_bicg_iter(const DevCase &d, hipStream_t s)
+{
+    LAUNCH_N(k_bicg_dir, d.N, s, d);
+    prof_begin("bicg_spmv", s);
+    LAUNCH_R(k_bicg_spmv, d.N, s, d);
+    prof_end("bicg_spmv", s);
+    LAUNCH_R(k_bicg_update, d.N, s, d);
+}
+
+void launch_pcg_init(const DevCase &d, int dic, hipStream_t s)
+{
+    LAUNCH_R(k_pcg_sumx, d.N, s, d);
+    LAUNCH_R(k_pcg_init, d.N, s, d, dic);
+}
+
+void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s)
+{
+    prof_begin("pcg_dir", s);
+    LAUNCH_N(k_pcg_dir, d.N, s, d, dic);
+    prof_end("pcg_dir", s);
+    prof_begin("pcg_spmv", s);
+    LAUNCH_R(k_pcg_spmv, d.N, s, d);
+    prof_end("pcg_spmv", s);
+    prof_begin("pcg_update", s);
+    LAUNCH_R(k_pcg_update, d.N, s, d, dic);
+    prof_end("pcg_update", s);
+}
+
+void launch_dic_setup(const DevCase &, hipStream_t) {}
+
+void launch_set_ctl(const DevCase &d, int first, int count, double tol, double rel_tol, int max_iter, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, d.ks, first, count, tol, rel_tol, max_iter);
+}
+
+void launch_set_patch(const DevCase &d, int patch, double u0, double u1, double u2, double pv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_patch, dim3(1), dim3(64), 0, s, d, patch, u0, u1, u2, pv);
+}

@@ -1,0 +1,204 @@
+// Mesh ingest: validation, face canonicalisation and the cell-to-face index
+// ranges that every cell gather uses (host side, once per mesh).
+//
+// The paper's problem statement (Section 3.1) fixes what a mesh is: cells,
+// faces owned by one cell and shared with at most one neighbour, geometry
+// per face.  It keeps face data addressable both "by rows" and "by columns"
+// through an ELL table plus a transpose-slot table (Section 3.1).  Here the
+// same two access directions come from sorting: internal faces are
+// canonicalised to owner < neighbour and sorted by (owner, neighbour), so a
+// cell's owned faces are one contiguous range; a second index (losort) lists
+// the faces ordered by (neighbour, owner), so the faces a cell sees from the
+// neighbour side are a contiguous range of it.  Face coefficients are stored
+// once per face and read from both sides.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "fvm_internal.h"
+
+std::string &fvm_err_buf();
+fvm_status fvm_fail(fvm_status code, const std::string &msg);
+
+namespace {
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
+{
+    if (!d || d->n_cells < 1 || d->n_internal_faces < 0 || d->n_faces < d->n_internal_faces || d->n_patches < 0)
+        return fvm_fail(FVM_EINVAL, "mesh: bad sizes");
+    if (!d->owner || (d->n_internal_faces > 0 && !d->neighbour) || !d->Sf || !d->Cf || !d->C || !d->V ||
+        (d->n_patches > 0 && !d->patches))
+        return fvm_fail(FVM_EINVAL, "mesh: null array");
+    const int32_t N = d->n_cells, F = d->n_faces, Fi = d->n_internal_faces, Fb = F - Fi;
+    m->N = N; m->F = F; m->Fi = Fi; m->Fb = Fb; m->npatch = d->n_patches;
+
+    for (int32_t i = 0; i < N; ++i)
+        if (!(d->V[i] > 0.0) || !std::isfinite(d->V[i]) || !finite3(d->C + 3 * (size_t)i))
+            return fvm_fail(FVM_EINVAL, "mesh: cell " + std::to_string(i) + " has V <= 0 or non-finite geometry");
+    for (int32_t f = 0; f < F; ++f) {
+        if (d->owner[f] < 0 || d->owner[f] >= N)
+            return fvm_fail(FVM_EINVAL, "mesh: owner out of range at face " + std::to_string(f));
+        if (!finite3(d->Sf + 3 * (size_t)f) || !finite3(d->Cf + 3 * (size_t)f))
+            return fvm_fail(FVM_EINVAL, "mesh: non-finite face geometry at face " + std::to_string(f));
+    }
+    for (int32_t f = 0; f < Fi; ++f) {
+        if (d->neighbour[f] < 0 || d->neighbour[f] >= N)
+            return fvm_fail(FVM_EINVAL, "mesh: neighbour out of range at face " + std::to_string(f));
+        if (d->neighbour[f] == d->owner[f])
+            return fvm_fail(FVM_EINVAL, "mesh: owner == neighbour at face " + std::to_string(f));
+    }
+    // patches must tile the boundary faces in order
+    int32_t expect = Fi;
+    m->patches.assign(d->patches, d->patches + d->n_patches);
+    for (int32_t p = 0; p < d->n_patches; ++p) {
+        const fvm_patch &P = d->patches[p];
+        if (P.start != expect || P.size < 0)
+            return fvm_fail(FVM_EINVAL, "mesh: patches do not tile the boundary faces (patch " + std::to_string(p) + ")");
+        if (P.u_kind < 0 || P.u_kind > 2 || P.p_kind < 0 || P.p_kind > 2)
+            return fvm_fail(FVM_EINVAL, "mesh: unknown boundary kind in patch " + std::to_string(p));
+        expect += P.size;
+        if (P.p_kind == FVM_BC_FIXED && P.size > 0) m->has_fixed_p = true;
+    }
+    if (expect != F) return fvm_fail(FVM_EINVAL, "mesh: boundary faces without a patch");
+
+    // orientation test S.d > 0 in the caller's orientation
+    auto sd_int = [&](int32_t f) {
+        const double *S = d->Sf + 3 * (size_t)f, *CP = d->C + 3 * (size_t)d->owner[f], *CN = d->C + 3 * (size_t)d->neighbour[f];
+        return S[0] * (CN[0] - CP[0]) + S[1] * (CN[1] - CP[1]) + S[2] * (CN[2] - CP[2]);
+    };
+    for (int32_t f = 0; f < Fi; ++f)
+        if (!(sd_int(f) > 0.0)) return fvm_fail(FVM_EINVAL, "mesh: S.d <= 0 at internal face " + std::to_string(f));
+    for (int32_t f = Fi; f < F; ++f) {
+        const double *S = d->Sf + 3 * (size_t)f, *Cf = d->Cf + 3 * (size_t)f, *CP = d->C + 3 * (size_t)d->owner[f];
+        double sd = S[0] * (Cf[0] - CP[0]) + S[1] * (Cf[1] - CP[1]) + S[2] * (Cf[2] - CP[2]);
+        if (!(sd > 0.0)) return fvm_fail(FVM_EINVAL, "mesh: S.d <= 0 at boundary face " + std::to_string(f));
+    }
+
+    // canonical internal faces: bucket by lower cell, then by upper cell
+    std::vector<int32_t> lo(Fi), hi(Fi);
+    m->own_start.assign((size_t)N + 1, 0);
+    for (int32_t f = 0; f < Fi; ++f) {
+        int32_t a = d->owner[f], b = d->neighbour[f];
+        lo[f] = std::min(a, b); hi[f] = std::max(a, b);
+        m->own_start[lo[f] + 1]++;
+    }
+    for (int32_t i = 0; i < N; ++i) m->own_start[i + 1] += m->own_start[i];
+    std::vector<int32_t> order(Fi), fill(m->own_start.begin(), m->own_start.end() - 1);
+    for (int32_t f = 0; f < Fi; ++f) order[fill[lo[f]]++] = f;
+    for (int32_t i = 0; i < N; ++i) {
+        auto b = order.begin() + m->own_start[i], e = order.begin() + m->own_start[i + 1];
+        std::sort(b, e, [&](int32_t x, int32_t y) { return hi[x] < hi[y] || (hi[x] == hi[y] && x < y); });
+        for (auto it = b; it + 1 < e; ++it)
+            if (hi[*it] == hi[*(it + 1)])
+                return fvm_fail(FVM_EINVAL, "mesh: duplicated face between cells " + std::to_string(i) + " and " +
+                                                std::to_string(hi[*it]));
+    }
+    m->own.resize(F); m->nei.resize(Fi); m->face_user.resize(Fi); m->face_sign.resize(Fi);
+    for (int32_t f = Fi; f < F; ++f) m->own[f] = d->owner[f];   // boundary faces keep the caller's order
+    for (int32_t c = 0; c < Fi; ++c) {
+        int32_t f = order[c];
+        m->own[c] = lo[f]; m->nei[c] = hi[f]; m->face_user[c] = f;
+        m->face_sign[c] = d->owner[f] == lo[f] ? 1 : -1;
+    }
+    // neighbour-side index: faces ordered by (nei, own); filling buckets in
+    // canonical order keeps each bucket sorted by owner
+    m->nbr_start.assign((size_t)N + 1, 0);
+    for (int32_t c = 0; c < Fi; ++c) m->nbr_start[m->nei[c] + 1]++;
+    for (int32_t i = 0; i < N; ++i) m->nbr_start[i + 1] += m->nbr_start[i];
+    m->losort.resize(Fi);
+    fill.assign(m->nbr_start.begin(), m->nbr_start.end() - 1);
+    for (int32_t c = 0; c < Fi; ++c) m->losort[fill[m->nei[c]]++] = c;
+    // boundary faces by cell
+    m->bnd_start.assign((size_t)N + 1, 0);
+    m->bpatch.resize(Fb);
+    for (int32_t p = 0; p < d->n_patches; ++p)
+        for (int32_t k = 0; k < d->patches[p].size; ++k) m->bpatch[d->patches[p].start + k - Fi] = p;
+    for (int32_t b = 0; b < Fb; ++b) m->bnd_start[d->owner[Fi + b] + 1]++;
+    for (int32_t i = 0; i < N; ++i) m->bnd_start[i + 1] += m->bnd_start[i];
+    m->bnd_list.resize(Fb);
+    fill.assign(m->bnd_start.begin(), m->bnd_start.end() - 1);
+    for (int32_t b = 0; b < Fb; ++b) m->bnd_list[fill[d->owner[Fi + b]]++] = b;
+
+    // geometry, SoA, canonical orientation
+    m->S.resize(3 * (size_t)F); m->Cf.resize(3 * (size_t)F); m->C.resize(3 * (size_t)N); m->V.assign(d->V, d->V + N);
+    for (int32_t c = 0; c < F; ++c) {
+        int32_t f = c < Fi ? m->face_user[c] : c;
+        double sg = c < Fi ? (double)m->face_sign[c] : 1.0;
+        for (int k = 0; k < 3; ++k) {
+            m->S[(size_t)k * F + c] = sg * d->Sf[3 * (size_t)f + k];
+            m->Cf[(size_t)k * F + c] = d->Cf[3 * (size_t)f + k];
+        }
+    }
+    for (int32_t i = 0; i < N; ++i)
+        for (int k = 0; k < 3; ++k) m->C[(size_t)k * N + i] = d->C[3 * (size_t)i + k];
+
+    // orthogonality: sine of the angle between S and d above 1e-8 anywhere
+    m->nonorth = false;
+    for (int32_t c = 0; c < Fi && !m->nonorth; ++c) {
+        double S[3], dd[3];
+        for (int k = 0; k < 3; ++k) {
+            S[k] = m->S[(size_t)k * F + c];
+            dd[k] = m->C[(size_t)k * N + m->nei[c]] - m->C[(size_t)k * N + m->own[c]];
+        }
+        double cx = S[1] * dd[2] - S[2] * dd[1], cy = S[2] * dd[0] - S[0] * dd[2], cz = S[0] * dd[1] - S[1] * dd[0];
+        double s2 = cx * cx + cy * cy + cz * cz;
+        double n2 = (S[0] * S[0] + S[1] * S[1] + S[2] * S[2]) * (dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+        if (s2 > 1e-16 * n2) m->nonorth = true;
+    }
+
+    // level schedule of the lower-triangular dependency graph: level(i) =
+    // 1 + max level of its lower neighbours j < i (ascending i)
+    std::vector<int32_t> lev(N, 0);
+    int32_t nl = 0;
+    for (int32_t i = 0; i < N; ++i) {
+        int32_t l = 0;
+        for (int32_t k = m->nbr_start[i]; k < m->nbr_start[i + 1]; ++k) l = std::max(l, lev[m->own[m->losort[k]]] + 1);
+        lev[i] = l;
+        nl = std::max(nl, l + 1);
+    }
+    m->lvl_start.assign((size_t)nl + 1, 0);
+    for (int32_t i = 0; i < N; ++i) m->lvl_start[lev[i] + 1]++;
+    for (int32_t l = 0; l < nl; ++l) m->lvl_start[l + 1] += m->lvl_start[l];
+    m->lvl_cells.resize(N);
+    fill.assign(m->lvl_start.begin(), m->lvl_start.end() - 1);
+    for (int32_t i = 0; i < N; ++i) m->lvl_cells[fill[lev[i]]++] = i;
+    return FVM_OK;
+}
+
+}  // namespace
+
+extern "C" fvm_status fvm_mesh_create(const fvm_mesh_desc *desc, fvm_mesh **out)
+{
+    if (!out) return fvm_fail(FVM_EINVAL, "mesh: null output");
+    *out = nullptr;
+    fvm_mesh *m = new (std::nothrow) fvm_mesh();
+    if (!m) return fvm_fail(FVM_EINVAL, "mesh: out of host memory");
+    fvm_status st;
+    try {
+        st = build(desc, m);
+    } catch (const std::exception &e) {
+        st = fvm_fail(FVM_EINVAL, std::string("mesh: ") + e.what());
+    }
+    if (st != FVM_OK) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return FVM_OK;
+}
+
+extern "C" void fvm_mesh_destroy(fvm_mesh *mesh) { delete mesh; }
+
+extern "C" fvm_status fvm_mesh_info(const fvm_mesh *m, int32_t *n_cells, int32_t *n_faces, int32_t *n_internal,
+                                    int32_t *non_orthogonal)
+{
+    if (!m) return fvm_fail(FVM_EINVAL, "mesh: null handle");
+    if (n_cells) *n_cells = m->N;
+    if (n_faces) *n_faces = m->F;
+    if (n_internal) *n_internal = m->Fi;
+    if (non_orthogonal) *non_orthogonal = m->nonorth ? 1 : 0;
+    return FVM_OK;
+}

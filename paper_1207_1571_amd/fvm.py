@@ -1,0 +1,271 @@
+"""Python binding of libfvm (argument marshalling only).
+
+Every step of the solver runs in the HIP library; this module converts numpy
+/ torch arguments to the C interface of include/fvm.h and back.  torch is
+used for device memory (each case's workspace is a uint8 CUDA tensor) and
+for the stream handle.  There is no CPU fallback: if libfvm.so is missing,
+loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfvm.so")
+
+FVM_OK, FVM_WARN_MAXITER, FVM_EINVAL, FVM_ENOMEM, FVM_ENUMERIC, FVM_EDEVICE = 0, 1, -1, -2, -3, -4
+BC_FIXED, BC_ZERO_GRAD, BC_EMPTY = 0, 1, 2
+PC_JACOBI, PC_DIC = 0, 1
+FP64, MIXED = 0, 1
+
+i32p = ct.POINTER(ct.c_int32)
+f64p = ct.POINTER(ct.c_double)
+
+
+class FvmPatch(ct.Structure):
+    _fields_ = [("start", ct.c_int32), ("size", ct.c_int32), ("u_kind", ct.c_int32), ("p_kind", ct.c_int32),
+                ("u_value", ct.c_double * 3), ("p_value", ct.c_double)]
+
+
+class FvmMeshDesc(ct.Structure):
+    _fields_ = [("n_cells", ct.c_int32), ("n_faces", ct.c_int32), ("n_internal_faces", ct.c_int32),
+                ("n_patches", ct.c_int32), ("owner", i32p), ("neighbour", i32p), ("Sf", f64p), ("Cf", f64p),
+                ("C", f64p), ("V", f64p), ("patches", ct.POINTER(FvmPatch))]
+
+
+class FvmSolverCtl(ct.Structure):
+    _fields_ = [("tol", ct.c_double), ("rel_tol", ct.c_double), ("max_iter", ct.c_int32), ("precond", ct.c_int32)]
+
+
+class FvmCaseOpts(ct.Structure):
+    _fields_ = [("nu", ct.c_double), ("dt", ct.c_double), ("alpha_u", ct.c_double), ("alpha_p", ct.c_double),
+                ("p_ref_value", ct.c_double), ("inner_rel_tol", ct.c_double), ("n_corr", ct.c_int32),
+                ("n_non_orth_corr", ct.c_int32), ("convection", ct.c_int32), ("precision", ct.c_int32),
+                ("p_ref_cell", ct.c_int32), ("inner_max_iter", ct.c_int32), ("p_ctl", FvmSolverCtl),
+                ("u_ctl", FvmSolverCtl)]
+
+
+class FvmSolveInfo(ct.Structure):
+    _fields_ = [("iters", ct.c_int32), ("status", ct.c_int32), ("res_initial", ct.c_double),
+                ("res_final", ct.c_double)]
+
+    def as_dict(self):
+        return dict(iters=self.iters, status=self.status, res_initial=self.res_initial, res_final=self.res_final)
+
+
+class FvmStepInfo(ct.Structure):
+    _fields_ = [("u", FvmSolveInfo * 3), ("p", FvmSolveInfo * 16), ("n_p_solves", ct.c_int32),
+                ("status", ct.c_int32)]
+
+    def as_dict(self):
+        return dict(u=[self.u[c].as_dict() for c in range(3)],
+                    p=[self.p[k].as_dict() for k in range(self.n_p_solves)], status=self.status)
+
+
+class FvmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfvm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = ("fvm_mesh_create", "fvm_mesh_destroy", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
+           "fvm_case_destroy", "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
+           "simple_iterate", "solve_pressure", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read",
+           "fvm_last_error")
+
+
+def lib():
+    """Load libfvm.so (built in-tree by paper_1207_1571_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1207_1571_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        vp = ct.c_void_p
+        L.fvm_mesh_create.argtypes = [ct.POINTER(FvmMeshDesc), ct.POINTER(vp)]
+        L.fvm_mesh_destroy.argtypes = [vp]
+        L.fvm_mesh_destroy.restype = None
+        L.fvm_mesh_info.argtypes = [vp, i32p, i32p, i32p, i32p]
+        L.fvm_case_workspace_bytes.argtypes = [vp, ct.POINTER(FvmCaseOpts), ct.POINTER(ct.c_size_t)]
+        L.fvm_case_create.argtypes = [vp, ct.POINTER(FvmCaseOpts), vp, ct.c_size_t, vp, ct.POINTER(vp)]
+        L.fvm_case_destroy.argtypes = [vp]
+        L.fvm_case_destroy.restype = None
+        L.fvm_case_set_state.argtypes = [vp, vp, vp, vp, vp]
+        L.fvm_case_get_state.argtypes = [vp, vp, vp, vp, vp]
+        L.fvm_case_set_patch_value.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp]
+        L.piso_step.argtypes = [vp, ct.c_int32, vp, ct.POINTER(FvmStepInfo)]
+        L.simple_iterate.argtypes = [vp, ct.c_int32, ct.c_double, vp, i32p, ct.POINTER(FvmStepInfo)]
+        L.solve_pressure.argtypes = [vp, vp, vp, vp, ct.POINTER(FvmSolverCtl), vp, ct.POINTER(FvmSolveInfo)]
+        L.piso_step_batch.argtypes = [ct.POINTER(vp), ct.c_int32, ct.c_int32, vp, ct.POINTER(FvmStepInfo)]
+        L.fvm_profile_enable.argtypes = [ct.c_int32]
+        L.fvm_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
+        L.fvm_last_error.restype = ct.c_char_p
+        for name in ("fvm_mesh_create", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
+                     "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
+                     "simple_iterate", "solve_pressure", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read"):
+            getattr(L, name).restype = ct.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(st: int, allow_warn: bool = True) -> int:
+    if st < 0 or (st > 0 and not allow_warn):
+        raise FvmError(st, lib().fvm_last_error().decode(errors="replace"))
+    return st
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Mesh:
+    """Host-side canonical mesh (fvm_mesh_create)."""
+
+    def __init__(self, mesh, bcs):
+        L = lib()
+        self.owner = np.ascontiguousarray(mesh.owner, np.int32)
+        self.neighbour = np.ascontiguousarray(mesh.neighbour, np.int32)
+        self.Sf = np.ascontiguousarray(mesh.Sf, np.float64)
+        self.Cf = np.ascontiguousarray(mesh.Cf, np.float64)
+        self.C = np.ascontiguousarray(mesh.C, np.float64)
+        self.V = np.ascontiguousarray(mesh.V, np.float64)
+        npch = len(mesh.patch_start)
+        self.patches = (FvmPatch * max(npch, 1))()
+        for p in range(npch):
+            b = bcs[p]
+            self.patches[p] = FvmPatch(int(mesh.patch_start[p]), int(mesh.patch_size[p]), int(b.u_kind),
+                                       int(b.p_kind), (ct.c_double * 3)(*b.u_value), float(b.p_value))
+        self.desc = FvmMeshDesc(int(self.V.shape[0]), int(self.owner.shape[0]), int(self.neighbour.shape[0]), npch,
+                                self.owner.ctypes.data_as(i32p), self.neighbour.ctypes.data_as(i32p),
+                                self.Sf.ctypes.data_as(f64p), self.Cf.ctypes.data_as(f64p),
+                                self.C.ctypes.data_as(f64p), self.V.ctypes.data_as(f64p), self.patches)
+        h = ct.c_void_p()
+        _check(L.fvm_mesh_create(ct.byref(self.desc), ct.byref(h)))
+        self.handle = h
+        a, b, c, d = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32()
+        _check(L.fvm_mesh_info(h, ct.byref(a), ct.byref(b), ct.byref(c), ct.byref(d)))
+        self.n_cells, self.n_faces, self.n_internal, self.non_orthogonal = a.value, b.value, c.value, bool(d.value)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fvm_mesh_destroy(self.handle)
+            self.handle = None
+
+
+def opts_from_case(case) -> FvmCaseOpts:
+    return FvmCaseOpts(case.nu, case.dt, case.alpha_u, case.alpha_p, case.p_ref_value, case.inner_rel_tol,
+                       case.n_corr, case.n_non_orth_corr, case.convection, case.precision, case.p_ref_cell,
+                       case.inner_max_iter,
+                       FvmSolverCtl(case.p_ctl.tol, case.p_ctl.rel_tol, case.p_ctl.max_iter, case.p_ctl.precond),
+                       FvmSolverCtl(case.u_ctl.tol, case.u_ctl.rel_tol, case.u_ctl.max_iter, case.u_ctl.precond))
+
+
+def workspace_bytes(mesh: Mesh, opts: FvmCaseOpts) -> int:
+    n = ct.c_size_t()
+    _check(lib().fvm_case_workspace_bytes(mesh.handle, ct.byref(opts), ct.byref(n)))
+    return int(n.value)
+
+
+class Case:
+    """A resident case: its workspace is one CUDA uint8 tensor."""
+
+    def __init__(self, case_spec, device="cuda", stream=None, mesh: Optional[Mesh] = None):
+        import torch
+        L = lib()
+        self.spec = case_spec
+        self.mesh = mesh if mesh is not None else Mesh(case_spec.mesh, case_spec.bcs)
+        self.opts = opts_from_case(case_spec)
+        self.bytes = workspace_bytes(self.mesh, self.opts)
+        self.workspace = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        h = ct.c_void_p()
+        _check(L.fvm_case_create(self.mesh.handle, ct.byref(self.opts), ct.c_void_p(self.workspace.data_ptr()),
+                                 self.bytes, ct.c_void_p(_stream_ptr(stream)), ct.byref(h)))
+        self.handle = h
+        self.n_cells, self.n_faces = self.mesh.n_cells, self.mesh.n_faces
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fvm_case_destroy(self.handle)
+            self.handle = None
+
+    def close(self):
+        self.__del__()
+
+    # ---- state
+    def set_state(self, U=None, p=None, phi=None):
+        _check(lib().fvm_case_set_state(self.handle, _dptr(U), _dptr(p), _dptr(phi),
+                                        ct.c_void_p(_stream_ptr(self.stream))))
+
+    def get_state(self):
+        import torch
+        dev = self.workspace.device
+        U = torch.empty((self.n_cells, 3), dtype=torch.float64, device=dev)
+        p = torch.empty(self.n_cells, dtype=torch.float64, device=dev)
+        phi = torch.empty(self.n_faces, dtype=torch.float64, device=dev)
+        _check(lib().fvm_case_get_state(self.handle, _dptr(U), _dptr(p), _dptr(phi),
+                                        ct.c_void_p(_stream_ptr(self.stream))))
+        return U, p, phi
+
+    def get_state_numpy(self):
+        import torch
+        U, p, phi = self.get_state()
+        torch.cuda.current_stream().synchronize() if self.stream is None else self.stream.synchronize()
+        return U.cpu().numpy(), p.cpu().numpy(), phi.cpu().numpy()
+
+    def set_patch_value(self, patch: int, u_value: Sequence[float], p_value: float):
+        arr = (ct.c_double * 3)(*u_value)
+        _check(lib().fvm_case_set_patch_value(self.handle, patch, arr, float(p_value),
+                                              ct.c_void_p(_stream_ptr(self.stream))))
+
+    # ---- algorithms
+    def piso(self, n_steps: int, info: bool = True):
+        si = FvmStepInfo()
+        st = _check(lib().piso_step(self.handle, n_steps, ct.c_void_p(_stream_ptr(self.stream)),
+                                    ct.byref(si) if info else None))
+        return st, (si.as_dict() if info else None)
+
+    def simple(self, max_iters: int, res_tol: float):
+        si = FvmStepInfo()
+        it = ct.c_int32()
+        st = _check(lib().simple_iterate(self.handle, max_iters, res_tol, ct.c_void_p(_stream_ptr(self.stream)),
+                                         ct.byref(it), ct.byref(si)))
+        return st, it.value, si.as_dict()
+
+    def solve_pressure(self, gamma, rhs, p, tol: float, rel_tol: float = 0.0, max_iter: int = 10000,
+                       precond: int = PC_JACOBI):
+        ctl = FvmSolverCtl(tol, rel_tol, max_iter, precond)
+        info = FvmSolveInfo()
+        st = _check(lib().solve_pressure(self.handle, _dptr(gamma), _dptr(rhs), _dptr(p), ct.byref(ctl),
+                                         ct.c_void_p(_stream_ptr(self.stream)), ct.byref(info)))
+        return st, info.as_dict()
+
+
+def piso_batch(cases: Sequence[Case], n_steps: int, stream=None):
+    arr = (ct.c_void_p * len(cases))(*[c.handle for c in cases])
+    infos = (FvmStepInfo * max(1, len(cases)))()
+    st = _check(lib().piso_step_batch(arr, len(cases), n_steps, ct.c_void_p(_stream_ptr(stream)), infos))
+    return st, [infos[i].as_dict() for i in range(len(cases))]
+
+
+def profile_enable(on: bool):
+    _check(lib().fvm_profile_enable(1 if on else 0))
+
+
+def profile_read(kernel_class: str):
+    ms = ct.c_double()
+    n = ct.c_int64()
+    _check(lib().fvm_profile_read(kernel_class.encode(), ct.byref(ms), ct.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,206 @@
+"""Parity of the HIP path (through the C interface) with the FP64 oracle.
+
+Protocol: run the same seeded case on both sides and compare U, p and phi by
+relative L2 error.  When every per-solve iteration count of the compared
+step agrees, the fields must agree to 1e-9 (FP64).  A count that differs at
+a threshold crossing moves the fields by about the tolerance; such cases are
+rerun on both sides with the tolerance divided by 1e3 before comparing.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1207_1571_amd import meshgen as mg
+from paper_1207_1571_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-9
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _gpu(case, steps=None, simple=False, res_tol=None, U=None, p=None, phi=None):
+    import torch
+    from paper_1207_1571_amd import fvm
+    c = fvm.Case(case)
+    if U is not None:
+        c.set_state(torch.from_numpy(np.ascontiguousarray(U)).cuda(), torch.from_numpy(np.ascontiguousarray(p)).cuda(),
+                    None if phi is None else torch.from_numpy(np.ascontiguousarray(phi)).cuda())
+    if simple:
+        st, it, info = c.simple(steps, res_tol)
+    else:
+        st, info = c.piso(steps)
+        it = steps
+    Ug, pg, phig = c.get_state_numpy()
+    return dict(st=st, it=it, info=info, U=Ug, p=pg, phi=phig, case=c)
+
+
+def _oracle(case, steps, simple=False, res_tol=None, U=None, p=None, phi=None):
+    oc = orc.OracleCase(case, U=U, p=p, phi=phi)
+    if simple:
+        st, it, info = oc.simple(steps, res_tol)
+    else:
+        st, info = oc.piso(steps)
+        it = steps
+    return dict(st=st, it=it, info=info, U=oc.U, p=oc.p, phi=oc.phi)
+
+
+def _counts(info):
+    return [s["iters"] for s in info["u"]] + [s["iters"] for s in info["p"]]
+
+
+def _compare(g, o, tol=TOL_FP64, what=""):
+    eU, ep, ephi = _rel(g["U"], o["U"]), _rel(g["p"], o["p"]), _rel(g["phi"], o["phi"])
+    _say(f"  {what}: relL2 U {eU:.2e} p {ep:.2e} phi {ephi:.2e}; iters gpu {_counts(g['info'])} "
+         f"oracle {_counts(o['info'])}")
+    assert eU <= tol and ep <= tol and ephi <= tol, (eU, ep, ephi)
+
+
+def _parity(case, steps, simple=False, res_tol=None, what=""):
+    _say(f"[parity] {what} N={case.mesh.n_cells} steps={steps}")
+    g = _gpu(case, steps, simple, res_tol)
+    o = _oracle(case, steps, simple, res_tol)
+    assert g["st"] == o["st"], (g["st"], o["st"])
+    if simple:
+        assert g["it"] == o["it"], (g["it"], o["it"])
+    if _counts(g["info"]) != _counts(o["info"]):
+        _say(f"  iteration counts differ at a threshold: rerun with tolerances / 1e3")
+        tight = case.with_(p_ctl=wl.SolverCtl(case.p_ctl.tol * 1e-3, case.p_ctl.rel_tol * 1e-3,
+                                              case.p_ctl.max_iter, case.p_ctl.precond),
+                           u_ctl=wl.SolverCtl(case.u_ctl.tol * 1e-3, case.u_ctl.rel_tol * 1e-3, case.u_ctl.max_iter))
+        g = _gpu(tight, steps, simple, res_tol)
+        o = _oracle(tight, steps, simple, res_tol)
+    _compare(g, o, what=what)
+    return g, o
+
+
+def test_cav2d32_full_run():
+    """The 2-D cavity configuration exactly: 32x32x1, random renumbering
+    (seed 1), Re=100, dt=0.005, 2 correctors, tol 1e-8, 100 PISO steps."""
+    case = wl.cav2d32()
+    g, o = _parity(case, case.n_steps, what="cav2d32")
+    # divergence-free corrected flux (identity of the pressure equation)
+    m = case.mesh
+    div = np.zeros(m.n_cells)
+    np.add.at(div, m.owner, g["phi"])
+    np.add.at(div, m.neighbour, -g["phi"][: m.n_internal])
+    assert np.abs(div).max() <= 1e-6 * np.abs(g["phi"]).max()
+
+
+@pytest.mark.parametrize("shape,perm", [((9, 7, 5), 3), ((17, 1, 13), None), ((6, 6, 6), 11)])
+def test_cavity3d_parity_several_tiles(shape, perm):
+    case = wl.cavity(shape, Re=200.0, dt=0.01, perm_seed=perm, tol=1e-9, n_steps=6)
+    _parity(case, 6, what=f"cavity {shape}")
+
+
+def test_noncanonical_face_order_and_orientation():
+    case = wl.cavity((7, 6, 5), Re=150.0, dt=0.01, perm_seed=4, tol=1e-9)
+    sh = case.with_(mesh=mg.shuffle_faces(case.mesh, seed=2))
+    _parity(sh, 4, what="shuffled faces")
+
+
+def test_upwind_and_rcm_parity():
+    case = wl.cavity((12, 10, 8), Re=400.0, dt=0.01, perm_seed=2, use_rcm=True, tol=1e-9).with_(convection=1)
+    _parity(case, 4, what="upwind rcm")
+
+
+def test_simple_jittered_duct_parity():
+    case = wl.duct256((32, 8, 8)).with_(p_ctl=wl.SolverCtl(1e-9, 0.05), u_ctl=wl.SolverCtl(1e-9, 0.1))
+    _parity(case, 25, simple=True, res_tol=0.0, what="SIMPLE jittered duct")
+
+
+def test_piso_jittered_duct_nonorth_correctors():
+    case = wl.duct((16, 6, 6), lengths=(2.0, 1.0, 1.0), Re=50.0, jitter=0.2, jitter_seed=7, mode="piso",
+                   dt=0.01).with_(p_ctl=wl.SolverCtl(1e-10), u_ctl=wl.SolverCtl(1e-10), n_non_orth_corr=1)
+    _parity(case, 3, what="PISO jittered, 1 non-orth corrector")
+
+
+def test_solve_pressure_parity():
+    import torch
+    from paper_1207_1571_amd import fvm
+    case = wl.cavity((15, 13, 9), Re=100.0, dt=0.01, perm_seed=6, tol=1e-9)
+    rng = np.random.default_rng(0)
+    m = case.mesh
+    gamma = rng.uniform(0.5, 2.0, m.n_faces)
+    rhs = rng.normal(size=m.n_cells)
+    rhs -= rhs.mean()
+    p0 = rng.normal(size=m.n_cells) * 0.1
+    oc = orc.OracleCase(case)
+    po = p0.copy()
+    st_o, info_o = oc.solve_pressure(gamma, rhs, po, 1e-10)
+    c = fvm.Case(case)
+    pg = torch.from_numpy(p0.copy()).cuda()
+    st_g, info_g = c.solve_pressure(torch.from_numpy(gamma).cuda(), torch.from_numpy(rhs).cuda(), pg, 1e-10)
+    _say(f"  solve_pressure iters gpu {info_g['iters']} oracle {info_o['iters']}")
+    assert st_g == st_o == 0
+    assert info_g["iters"] == info_o["iters"]
+    assert _rel(pg.cpu().numpy(), po) <= TOL_FP64
+    # the case's own pressure field is left untouched
+    _, p_case, _ = c.get_state_numpy()
+    assert np.all(p_case == 0.0)
+
+
+def test_zero_lid_exact_rest_and_zero_iterations():
+    case = wl.cavity((8, 8, 8), Re=100.0, dt=0.01, tol=1e-8, u_lid=0.0)
+    g = _gpu(case, 3)
+    assert np.all(g["U"] == 0.0) and np.all(g["p"] == 0.0) and np.all(g["phi"] == 0.0)
+    assert all(k == 0 for k in _counts(g["info"]))
+
+
+def test_determinism_and_restart_bitwise():
+    case = wl.cavity((10, 9, 7), Re=300.0, dt=0.01, perm_seed=1, tol=1e-8)
+    a = _gpu(case, 6)
+    b = _gpu(case, 6)
+    assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["p"], b["p"]) and np.array_equal(a["phi"], b["phi"])
+    h = _gpu(case, 3)
+    r = _gpu(case, 3, U=h["U"], p=h["p"], phi=h["phi"])
+    assert np.array_equal(a["U"], r["U"]) and np.array_equal(a["p"], r["p"]) and np.array_equal(a["phi"], r["phi"])
+
+
+def test_maxiter_warning_and_breakdown_rollback():
+    import torch
+    from paper_1207_1571_amd import fvm
+    case = wl.cavity((6, 6, 1), Re=100.0, dt=0.005, tol=1e-8).with_(p_ctl=wl.SolverCtl(0.0, max_iter=5))
+    g = _gpu(case, 1)
+    o = _oracle(case, 1)
+    assert g["st"] == o["st"] == fvm.FVM_WARN_MAXITER
+    assert g["info"]["p"][0]["iters"] == 5
+    _compare(g, o, what="max_iter")
+    # a non-finite state is reported and the step rolled back
+    c = fvm.Case(wl.cavity((6, 6, 1), Re=100.0, dt=0.005, tol=1e-8))
+    U = np.zeros((36, 3)); U[5, 0] = np.nan
+    c.set_state(torch.from_numpy(U).cuda(), torch.zeros(36, dtype=torch.float64, device="cuda"), None)
+    U0, p0, phi0 = c.get_state_numpy()
+    with pytest.raises(fvm.FvmError) as e:
+        c.piso(1)
+    assert e.value.code == fvm.FVM_ENUMERIC
+    U1, p1, phi1 = c.get_state_numpy()
+    assert np.array_equal(np.isnan(U0), np.isnan(U1)) and np.array_equal(np.nan_to_num(U0), np.nan_to_num(U1))
+
+
+def test_time_dependent_patch_value():
+    from paper_1207_1571_amd import fvm
+    case = wl.duct((24, 8, 1), lengths=(3.0, 1.0, 1.0 / 8), Re=20.0, mode="piso", dt=0.01)
+    case = case.with_(p_ctl=wl.SolverCtl(1e-10), u_ctl=wl.SolverCtl(1e-10))
+    c = fvm.Case(case)
+    oc = orc.OracleCase(case)
+    for k in range(4):
+        u = 0.5 + 0.25 * k
+        c.set_patch_value(0, (u, 0.0, 0.0), 0.0)
+        case.bcs[0].u_value = (u, 0.0, 0.0)
+        oc2 = orc.OracleCase(case, U=oc.U, p=oc.p, phi=oc.phi)
+        c.piso(1)
+        oc2.piso(1)
+        oc = oc2
+    Ug, pg, phig = c.get_state_numpy()
+    assert _rel(Ug, oc.U) <= TOL_FP64 and _rel(pg, oc.p) <= TOL_FP64
