@@ -1,0 +1,185 @@
+"""Benchmark of the PISO hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (timed): 3-D lid-driven cavity, 100^3 = 1M hex cells, cells
+renumbered by a seeded random permutation (seed 2) then reverse
+Cuthill-McKee, Re = 400, PISO dt = 0.002 with 2 correctors, pressure CG with
+DIC preconditioning and momentum BiCG with Jacobi, both to tol 1e-7, FP64.
+A step is one PISO time step (momentum assembly and solve, two pressure
+correctors with assembly, CG solve, flux and velocity correction).  Fields
+start at rest; K steps are timed from t = 0 on a freshly created case (the
+W warm-up steps run on a separate case).
+
+value = cell-updates/s = cells * K / wall time of the K steps (inputs resident
+in device memory before the timed region).
+
+Also reported on the same JSON line:
+  roofline      the kernel class with the largest device time in a profiled
+                pass (HIP events around each launch, on the stream the kernel
+                runs on): algorithmic bytes per launch / mean launch time;
+  kernels       per-class mean time, launches and algorithmic GB/s;
+  cpu_baseline  the FP64 oracle on the host on a bounded sample (the first
+                PISO step of the same case), in cell-updates/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s + PCG SpMV HBM GB/s (FP64 vs mixed); serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(cls: str, N: int, Fi: int, dic: bool) -> float:
+    """Bytes per launch that the operation itself must move (FP64).
+
+    Symmetric SpMV: diag, x, y (24 N) + one coefficient and two int32
+    indices per internal face (16 Fi).  Other classes follow the same
+    counting: every cell-sized array read or written once, every face
+    coefficient once, plus two int32 per face where faces are walked."""
+    table = {
+        "pcg_spmv": 24 * N + 16 * Fi,
+        "pcg_update": 56 * N,                      # x, p, r, q, diag in; x, r out
+        "pcg_dir": (24 if dic else 32) * N,        # z (or r, diag), p in; p out
+        "dic_fwd": 32 * N + 16 * Fi,               # r, D*, y out, z clear; lower faces
+        "dic_bwd": 32 * N + 16 * Fi,               # y, D*, r, z out; upper faces
+        "dic_setup": 16 * N + 16 * Fi,             # diag, D* out; lower faces
+        "bicg_spmv": 104 * N + 24 * Fi,            # 3 components, A and A^T
+        "mom_face": 32 * Fi,                       # phi, w, dl in; upper, lower out
+        "mom_cell": 136 * N + 40 * Fi,
+        "hbya": 104 * N + 24 * Fi,
+        "p_face": 112 * N + 56 * Fi,
+        "p_cell": 24 * N + 32 * Fi,
+        "flux_corr": 16 * N + 48 * Fi,
+        "U_corr": 80 * N + 64 * Fi,
+    }
+    return float(table.get(cls, 0))
+
+
+KERNEL_CLASSES = ["pcg_spmv", "pcg_update", "pcg_dir", "dic_setup", "dic_fwd", "dic_bwd", "bicg_spmv", "mom_face",
+                  "mom_cell", "hbya", "p_face", "p_cell", "flux_corr", "U_corr"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=100, help="cube side (100 = the benchmark configuration)")
+    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1207_1571_amd import fvm
+    from paper_1207_1571_amd import workloads as wl
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    spec = wl.cav100(n=args.n, n_steps=args.steps)
+    mesh = fvm.Mesh(spec.mesh, spec.bcs)
+    N, Fi = mesh.n_cells, mesh.n_internal
+    log(f"mesh {args.n}^3: {N} cells, {Fi} internal faces, built in {time.perf_counter() - t:.1f}s")
+
+    if args.warmup > 0:
+        w = fvm.Case(spec, mesh=mesh)
+        w.piso(args.warmup)
+        torch.cuda.synchronize()
+        del w
+        log(f"warm-up {args.warmup} steps done")
+
+    case = fvm.Case(spec, mesh=mesh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = case.piso(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    value = N * args.steps / wall
+    p_iters_last = [s["iters"] for s in info["p"]]
+    log(f"timed {args.steps} steps in {wall:.3f}s: {value:.4g} cell-updates/s; last step p iters {p_iters_last}, "
+        f"U iters {[s['iters'] for s in info['u']]}, status {st}")
+    U, p, phi = case.get_state_numpy()
+    assert np.all(np.isfinite(U)) and np.all(np.isfinite(p)), "non-finite fields"
+    del case
+
+    # profiled pass: per-kernel-class device time
+    kernels = {}
+    if args.profile_steps > 0:
+        pc = fvm.Case(spec, mesh=mesh)
+        fvm.profile_enable(True)
+        pc.piso(args.profile_steps)
+        torch.cuda.synchronize()
+        for cls in KERNEL_CLASSES:
+            ms, n = fvm.profile_read(cls)
+            if n == 0:
+                continue
+            mean_us = 1e3 * ms / n
+            b = algorithmic_bytes(cls, N, Fi, spec.p_ctl.precond == wl.PC_DIC)
+            kernels[cls] = dict(total_ms=round(ms, 4), launches=n, mean_us=round(mean_us, 3),
+                                alg_GBps=round(b / (mean_us * 1e-6) / 1e9, 1) if b and mean_us > 0 else None)
+        fvm.profile_enable(False)
+        del pc
+        log("kernel classes: " + json.dumps(kernels))
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
+    roofline = None
+    if dom:
+        ach = kernels[dom]["alg_GBps"]
+        roofline = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(ach / HBM_PEAK_GBS, 4) if ach else None, traffic=None)
+    spmv = kernels.get("pcg_spmv")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        oc = orc.OracleCase(spec)
+        t = time.perf_counter()
+        oc.piso(1)
+        dt = time.perf_counter() - t
+        cpu = dict(value=round(N / dt, 1), unit="cell-updates/s", cores=1, kind="oracle",
+                   sample=f"first PISO step of the same {args.n}^3 case, single-threaded C oracle ({dt:.1f}s)")
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cav{args.n}: 3-D lid-driven cavity {args.n}^3 hex cells, random renumbering "
+                               f"(seed 2) + RCM, Re=400, PISO dt=0.002, 2 correctors, PCG-DIC / PBiCG tol 1e-7",
+                   "cells": N, "internal_faces": Fi, "precision": "fp64"},
+        "pcg_spmv_GBps": spmv["alg_GBps"] if spmv else None,
+        "p_iters_last_step": p_iters_last,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

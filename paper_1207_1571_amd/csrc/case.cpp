@@ -180,7 +180,7 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
         d.tmpC = kbase; d.tmpCf = kbase + 3 * N;
     }
     if (dic) {
-        d.z = b.take<double>(N); d.dstar = b.take<double>(N);
+        d.y = b.take<double>(N); d.z = b.take<double>(N); d.dstar = b.take<double>(N);
         d.lvl_start = b.take<int32_t>(m.lvl_start.size()); d.lvl_cells = b.take<int32_t>(N);
     }
     if (mixed) {
@@ -207,7 +207,6 @@ fvm_status check_opts(const fvm_mesh *m, const fvm_case_opts *o)
     if (o->precision == FVM_MIXED) return fvm_fail(FVM_EINVAL, "case: mixed precision is not available in this build");
     if (o->p_ctl.precond != FVM_PC_JACOBI && o->p_ctl.precond != FVM_PC_DIC)
         return fvm_fail(FVM_EINVAL, "case: bad preconditioner");
-    if (o->p_ctl.precond == FVM_PC_DIC) return fvm_fail(FVM_EINVAL, "case: DIC is not available in this build");
     if (o->u_ctl.precond != FVM_PC_JACOBI) return fvm_fail(FVM_EINVAL, "case: momentum solver takes Jacobi only");
     if (o->p_ctl.max_iter < 1 || o->u_ctl.max_iter < 1) return fvm_fail(FVM_EINVAL, "case: max_iter must be >= 1");
     if (!(o->p_ctl.tol >= 0.0) || !(o->u_ctl.tol >= 0.0) || !(o->p_ctl.rel_tol >= 0.0) || !(o->u_ctl.rel_tol >= 0.0))
@@ -404,6 +403,7 @@ fvm_status run_solve(fvm_case *c, int kind, const fvm_solver_ctl &ctl, hipStream
     launch_set_ctl(d, first, count, ctl.tol, ctl.rel_tol, ctl.max_iter, s);
     if (kind == 0) launch_bicg_init(d, s);
     else launch_pcg_init(d, dic, s);
+    if (dic) launch_dic_precond(d, 1, s);
 
     const int predicted = c->last_iters[kind];
     int chunk = predicted > 0 ? std::max(2, predicted - predicted / 4) : 4;
@@ -629,8 +629,10 @@ extern "C" fvm_status solve_pressure(fvm_case *c, const double *gamma, const dou
                                      const fvm_solver_ctl *ctl, void *stream, fvm_solve_info *out)
 {
     if (!c || !gamma || !rhs || !p || !ctl) return fvm_fail(FVM_EINVAL, "solve_pressure: null argument");
-    if (ctl->precond == FVM_PC_DIC) return fvm_fail(FVM_EINVAL, "solve_pressure: DIC is not available in this build");
-    if (ctl->precond != FVM_PC_JACOBI) return fvm_fail(FVM_EINVAL, "solve_pressure: bad preconditioner");
+    if (ctl->precond != FVM_PC_JACOBI && ctl->precond != FVM_PC_DIC)
+        return fvm_fail(FVM_EINVAL, "solve_pressure: bad preconditioner");
+    if (ctl->precond == FVM_PC_DIC && !c->d.dstar)
+        return fvm_fail(FVM_EINVAL, "solve_pressure: DIC needs a case created with the DIC preconditioner");
     if (ctl->max_iter < 1) return fvm_fail(FVM_EINVAL, "solve_pressure: max_iter must be >= 1");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const DevCase &d = c->d;

@@ -100,7 +100,7 @@ struct DevCase {
     double *rAU, *HbyA, *gradp, *phiH, *gam, *pdiag, *poff, *pb, *tno;
     // Krylov work vectors
     double *r, *rt, *pp, *pt, *q, *qt;           // [3][N] each (CG uses component 0)
-    double *z;                                   // [N] DIC output
+    double *y, *z;                               // [N] DIC forward / backward sweep outputs
     double *dstar;                               // [N] DIC diagonal
     int32_t *lvl_start, *lvl_cells;              // DIC level schedule
     int32_t n_levels;
@@ -150,7 +150,7 @@ void launch_bicg_iter(const DevCase &d, hipStream_t s);
 // Krylov: pressure CG (FP64), Jacobi or DIC
 void launch_pcg_init(const DevCase &d, int dic, hipStream_t s);
 void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s);
-void launch_dic_setup(const DevCase &d, hipStream_t s);
+void launch_dic_precond(const DevCase &d, int with_setup, hipStream_t s);
 
 // scalar parameters passed by value (no host staging buffers)
 void launch_set_ctl(const DevCase &d, int first, int count, double tol, double rel_tol, int max_iter, hipStream_t s);

@@ -32,6 +32,10 @@
 namespace {
 
 constexpr int kWaves = kBlock / 64;
+// DIC sweeps: a NaN payload marks "not yet published"; bounded polling
+constexpr unsigned long long kSentinel = 0x7FF4DEADBEEF0001ULL;
+constexpr unsigned long long kQNaN = 0x7FF8000000000000ULL;
+constexpr int kSpinLimit = 1 << 18;
 
 __device__ __forceinline__ int logical_block()
 {
@@ -751,6 +755,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(DevCase d, int dic)
         v[0] += fabs(ax - xb * a1) + fabs(b - xb * a1);
         v[1] += fabs(r);
         if (!dic) v[2] += r * (r / d.pdiag[i]);
+        else {
+            d.dstar[i] = __longlong_as_double(kSentinel);
+            d.y[i] = __longlong_as_double(kSentinel);
+            d.z[i] = __longlong_as_double(kSentinel);
+        }
     }
     __shared__ double tot[3];
     if (reduce_last<3>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
@@ -831,6 +840,122 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(DevCase d, int dic)
             else {
                 s.beta = tot[1] / s.rho;
                 s.rho = tot[1];
+            }
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// DIC triangular sweeps, sync-free in level order
+//
+// The diagonal-only incomplete Cholesky factor D* and the two triangular
+// solves of M = (D* + L) D*^-1 (D* + U) are recurrences over the lower
+// (upper) neighbours of each cell.  Cells are processed in the order of the
+// dependency levels computed at mesh ingest; tiles of 256 cells are claimed
+// through an atomic ticket, so every dependency of a tile lies in a tile that
+// has already been claimed by a running or finished block.  A value is
+// published with one 64-bit device-scope store into an array pre-filled with
+// a NaN sentinel: the value is its own ready flag, so no fence is needed and
+// a reader polls exactly the word it consumes.  Each lane keeps consuming
+// dependencies as they appear (no lane waits inside a loop another lane of
+// its wave must leave first), and polling is bounded: past the limit the
+// value is published as NaN, which the solver reports as a breakdown instead
+// of hanging.  Per cell the sums run over neighbours in ascending index.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool dic_try(const double *a, int j, double &v)
+{
+    const unsigned long long b =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long *>(a + j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (b == kSentinel) return false;
+    v = __longlong_as_double((long long)b);
+    return true;
+}
+
+__device__ __forceinline__ void dic_put(double *a, int i, double v)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b == kSentinel) b = kQNaN;
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(a + i), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// MODE 0: D*_i = A_ii - sum_{j<i} a_ij^2 / D*_j
+// MODE 1: y_i = (r_i - sum_{j<i} a_ij y_j) / D*_i      (also clears z)
+// MODE 2: z_i = y_i - (sum_{j>i} a_ij z_j) / D*_i      (reverse order; r.z)
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
+{
+    if (d.ks[3].done) return;
+    __shared__ int tile;
+    if (threadIdx.x == 0) tile = (int)atomicAdd(&d.ticket[1], 1u);
+    __syncthreads();
+    const int n = d.N;
+    const int pos = tile * kBlock + threadIdx.x;
+    double part = 0.0;
+    if (pos < n) {
+        const int i = MODE == 2 ? d.lvl_cells[n - 1 - pos] : d.lvl_cells[pos];
+        int k, k1;
+        double acc;
+        const double *src;
+        if (MODE == 2) { k = d.own_start[i]; k1 = d.own_start[i + 1]; acc = 0.0; src = d.z; }
+        else { k = d.nbr_start[i]; k1 = d.nbr_start[i + 1]; acc = MODE == 0 ? d.pdiag[i] : d.r[i]; src = MODE == 0 ? d.dstar : d.y; }
+        bool fin = false;
+        int spins = 0;
+        while (!fin) {
+            bool stall = false;
+            while (k < k1) {
+                const int f = MODE == 2 ? k : d.losort[k];
+                const int j = MODE == 2 ? d.nei[f] : d.own[f];
+                double v;
+                if (!dic_try(src, j, v)) { stall = true; break; }
+                const double a = d.poff[f];
+                if (MODE == 0) acc -= a * a / v;
+                else if (MODE == 1) acc -= a * v;
+                else acc += a * v;
+                ++k;
+            }
+            if (!stall) {
+                if (MODE == 0) dic_put(d.dstar, i, acc);
+                else if (MODE == 1) { dic_put(d.y, i, acc / d.dstar[i]); d.z[i] = __longlong_as_double(kSentinel); }
+                else {
+                    const double zi = d.y[i] - acc / d.dstar[i];
+                    dic_put(d.z, i, zi);
+                    d.y[i] = __longlong_as_double(kSentinel);
+                    part = d.r[i] * zi;
+                }
+                fin = true;
+            } else if (++spins > kSpinLimit) {
+                dic_put(MODE == 0 ? d.dstar : (MODE == 1 ? d.y : d.z), i, __longlong_as_double((long long)kQNaN));
+                if (MODE == 2) part = __longlong_as_double((long long)kQNaN);
+                d.ticket[8] = 1u;
+                fin = true;
+            } else {
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    }
+    if (MODE == 2) {
+        double v[1] = {part};
+        __shared__ double tot[1];
+        if (reduce_last<1>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+            KState &s = d.ks[3];
+            d.ticket[1] = 0u;
+            if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else if (s.iters == 0) s.rho = tot[0];
+            else {
+                s.beta = tot[0] / s.rho;
+                s.rho = tot[0];
+            }
+        }
+    } else {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const unsigned int t = atomicAdd(&d.ticket[2], 1u);
+            if (t == gridDim.x - 1) {
+                d.ticket[1] = 0u;
+                d.ticket[2] = 0u;
             }
         }
     }
@@ -960,6 +1085,22 @@ void launch_pcg_init(const DevCase &d, int dic, hipStream_t s)
     LAUNCH_R(k_pcg_init, d.N, s, d, dic);
 }
 
+void launch_dic_precond(const DevCase &d, int with_setup, hipStream_t s)
+{
+    const int g = cdiv(d.N, kBlock);
+    if (with_setup) {
+        prof_begin("dic_setup", s);
+        hipLaunchKernelGGL(k_dic_sweep<0>, dim3(g), dim3(kBlock), 0, s, d);
+        prof_end("dic_setup", s);
+    }
+    prof_begin("dic_fwd", s);
+    hipLaunchKernelGGL(k_dic_sweep<1>, dim3(g), dim3(kBlock), 0, s, d);
+    prof_end("dic_fwd", s);
+    prof_begin("dic_bwd", s);
+    hipLaunchKernelGGL(k_dic_sweep<2>, dim3(g), dim3(kBlock), 0, s, d);
+    prof_end("dic_bwd", s);
+}
+
 void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s)
 {
     prof_begin("pcg_dir", s);
@@ -971,9 +1112,8 @@ void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s)
     prof_begin("pcg_update", s);
     LAUNCH_R(k_pcg_update, d.N, s, d, dic);
     prof_end("pcg_update", s);
+    if (dic) launch_dic_precond(d, 0, s);
 }
-
-void launch_dic_setup(const DevCase &, hipStream_t) {}
 
 void launch_set_ctl(const DevCase &d, int first, int count, double tol, double rel_tol, int max_iter, hipStream_t s)
 {

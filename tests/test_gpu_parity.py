@@ -115,8 +115,11 @@ def test_upwind_and_rcm_parity():
 
 
 def test_simple_jittered_duct_parity():
-    case = wl.duct256((32, 8, 8)).with_(p_ctl=wl.SolverCtl(1e-9, 0.05), u_ctl=wl.SolverCtl(1e-9, 0.1))
-    _parity(case, 25, simple=True, res_tol=0.0, what="SIMPLE jittered duct")
+    # relative inner tolerances let an early outer iteration cross a stopping
+    # threshold on one side only; absolute tight tolerances keep every outer
+    # iteration comparable
+    case = wl.duct256((32, 8, 8)).with_(p_ctl=wl.SolverCtl(1e-12, 0.0), u_ctl=wl.SolverCtl(1e-12, 0.0))
+    _parity(case, 12, simple=True, res_tol=0.0, what="SIMPLE jittered duct")
 
 
 def test_piso_jittered_duct_nonorth_correctors():
@@ -151,7 +154,7 @@ def test_solve_pressure_parity():
 
 
 def test_zero_lid_exact_rest_and_zero_iterations():
-    case = wl.cavity((8, 8, 8), Re=100.0, dt=0.01, tol=1e-8, u_lid=0.0)
+    case = wl.cavity((8, 8, 8), Re=100.0, dt=0.01, tol=1e-8, u_lid=0.0).with_(nu=0.01)
     g = _gpu(case, 3)
     assert np.all(g["U"] == 0.0) and np.all(g["p"] == 0.0) and np.all(g["phi"] == 0.0)
     assert all(k == 0 for k in _counts(g["info"]))
@@ -204,3 +207,44 @@ def test_time_dependent_patch_value():
         oc = oc2
     Ug, pg, phig = c.get_state_numpy()
     assert _rel(Ug, oc.U) <= TOL_FP64 and _rel(pg, oc.p) <= TOL_FP64
+
+
+@pytest.mark.parametrize("shape,perm,rcm", [((11, 9, 7), 2, True), ((20, 20, 1), 1, False), ((8, 8, 8), None, False)])
+def test_dic_pcg_piso_parity(shape, perm, rcm):
+    case = wl.cavity(shape, Re=400.0, dt=0.005, perm_seed=perm, use_rcm=rcm, tol=1e-9, p_precond=wl.PC_DIC)
+    _parity(case, 5, what=f"DIC cavity {shape}")
+
+
+def test_dic_exact_on_chain_and_solve_pressure():
+    import torch
+    from paper_1207_1571_amd import fvm
+    # a 1-D chain with a fixed-p end: tridiagonal SPD, DIC is exact -> 1 iteration
+    case = wl.duct((40, 1, 1), lengths=(4.0, 0.1, 0.1), Re=10.0, mode="piso", dt=0.01)
+    case = case.with_(p_ctl=wl.SolverCtl(1e-12, precond=wl.PC_DIC))
+    rng = np.random.default_rng(3)
+    m = case.mesh
+    gamma = rng.uniform(0.5, 2.0, m.n_faces)
+    rhs = rng.normal(size=m.n_cells)
+    c = fvm.Case(case)
+    pg = torch.zeros(m.n_cells, dtype=torch.float64, device="cuda")
+    st, info = c.solve_pressure(torch.from_numpy(gamma).cuda(), torch.from_numpy(rhs).cuda(), pg, 1e-12,
+                                precond=wl.PC_DIC)
+    assert st == 0 and info["iters"] == 1, info
+    oc = orc.OracleCase(case)
+    po = np.zeros(m.n_cells)
+    oc.solve_pressure(gamma, rhs, po, 1e-12, precond=wl.PC_DIC)
+    assert _rel(pg.cpu().numpy(), po) <= 1e-12
+    # a 3-D renumbered mesh: same iterations and solution as the oracle
+    case = wl.cavity((13, 11, 9), Re=100.0, dt=0.01, perm_seed=5, use_rcm=True, tol=1e-9, p_precond=wl.PC_DIC)
+    m = case.mesh
+    gamma = rng.uniform(0.5, 2.0, m.n_faces)
+    rhs = rng.normal(size=m.n_cells); rhs -= rhs.mean()
+    c = fvm.Case(case)
+    pg = torch.zeros(m.n_cells, dtype=torch.float64, device="cuda")
+    st, info = c.solve_pressure(torch.from_numpy(gamma).cuda(), torch.from_numpy(rhs).cuda(), pg, 1e-10,
+                                precond=wl.PC_DIC)
+    po = np.zeros(m.n_cells)
+    st_o, info_o = orc.OracleCase(case).solve_pressure(gamma, rhs, po, 1e-10, precond=wl.PC_DIC)
+    _say(f"  DIC solve_pressure iters gpu {info['iters']} oracle {info_o['iters']}")
+    assert info["iters"] == info_o["iters"]
+    assert _rel(pg.cpu().numpy(), po) <= TOL_FP64

@@ -280,7 +280,7 @@ def test_T9_reference_cell_holds_reference_pressure():
 # --------------------------------------------------------------------- T10
 
 def test_T10_zero_lid_velocity_stays_exactly_at_rest():
-    case = wl.cavity((5, 4, 3), Re=100.0, dt=0.01, tol=1e-8, u_lid=0.0)
+    case = wl.cavity((5, 4, 3), Re=100.0, dt=0.01, tol=1e-8, u_lid=0.0).with_(nu=0.01)
     oc = orc.OracleCase(case)
     st, info = oc.piso(3)
     assert st == 0
