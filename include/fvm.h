@@ -181,6 +181,15 @@ fvm_status simple_iterate(fvm_case *c, int32_t max_iters, double res_tol, void *
 fvm_status solve_pressure(fvm_case *c, const double *d_gamma_f, const double *d_rhs, double *d_p,
                           const fvm_solver_ctl *ctl, void *stream, fvm_solve_info *info);
 
+/* fvm_dic_apply -- the diagonal incomplete Cholesky preconditioner alone
+ * (diagnostics and tests): assemble the pressure matrix from d_gamma_f as
+ * solve_pressure does, factor it (D*_i = A_ii - sum_{j<i} A_ij^2 / D*_j) and
+ * apply M^-1 = ((D* + L) D*^-1 (D* + U))^-1 to d_r, giving d_z (and D* in
+ * d_dstar unless NULL).  Needs a case created with FVM_PC_DIC.  Overwrites
+ * the case's pressure work arrays, not its fields.  Synchronises. */
+fvm_status fvm_dic_apply(fvm_case *c, const double *d_gamma_f, const double *d_r, double *d_z, double *d_dstar,
+                         void *stream);
+
 /* piso_step_batch -- advance several resident cases by n_steps PISO steps,
  * their kernels batched into shared launches (continuous-batching serving).
  * Every case must be FVM_MIXED or every case FVM_FP64.  infos[i] (may be

@@ -190,7 +190,8 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
         d.f_rt = b.take<float>(3 * N); d.f_p = b.take<float>(3 * N); d.f_pt = b.take<float>(3 * N);
         d.f_q = b.take<float>(3 * N); d.f_qt = b.take<float>(3 * N);
     }
-    d.partials = b.take<double>((size_t)kMaxRed * kMaxGrid);
+    d.red_stride = std::max<int32_t>(kMaxGrid, (int32_t)((N + kBlock - 1) / kBlock));
+    d.partials = b.take<double>((size_t)kMaxRed * d.red_stride);
     d.ticket = b.take<unsigned int>(64);
     d.ks = b.take<KState>(4);
     b.off = (b.off + 255) / 256 * 256;
@@ -326,6 +327,7 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     UPCHK(hipMemsetAsync(d.ks, 0, 4 * sizeof(KState), s));
     st = upload_patches(c, s);
     if (st != FVM_OK) return fail(st);
+    launch_init_partials(d, s);
     launch_geometry(d, s);
     UPCHK(hipMemsetAsync(d.U, 0, 3 * N * sizeof(double), s));
     UPCHK(hipMemsetAsync(d.p, 0, N * sizeof(double), s));
@@ -650,6 +652,24 @@ extern "C" fvm_status solve_pressure(fvm_case *c, const double *gamma, const dou
     if (out) to_info(ks, *out);
     if (ks.status < 0) return fvm_fail(ks.status, "solve_pressure: non-finite value or breakdown");
     return ks.status;
+}
+
+extern "C" fvm_status fvm_dic_apply(fvm_case *c, const double *gamma, const double *r, double *z, double *dstar,
+                                    void *stream)
+{
+    if (!c || !gamma || !r || !z) return fvm_fail(FVM_EINVAL, "dic_apply: null argument");
+    if (!c->d.dstar) return fvm_fail(FVM_EINVAL, "dic_apply: case was not created with the DIC preconditioner");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const DevCase &d = c->d;
+    launch_gather_faces(d, gamma, d.phiH, s);
+    launch_p_system_from_gamma(d, d.phiH, r, c->o.p_ref_value, s);
+    HIPCHK(hipMemcpyAsync(d.r, r, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
+    launch_dic_reset(d, s);
+    launch_dic_precond(d, 1, s);
+    HIPCHK(hipMemcpyAsync(z, d.z, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
+    if (dstar) HIPCHK(hipMemcpyAsync(dstar, d.dstar, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FVM_OK;
 }
 
 extern "C" fvm_status piso_step_batch(fvm_case *const *cases, int32_t n, int32_t n_steps, void *stream,

@@ -67,7 +67,7 @@ static_assert(sizeof(KState) == 128, "KState layout");
 
 // maximum grid of a reducing kernel; partial-sum buffers hold this many
 // values per reduced quantity
-constexpr int kMaxGrid = 2048;
+constexpr int kMaxGrid = 1024;
 constexpr int kBlock = 256;
 constexpr int kMaxRed = 12;          // reduced quantities per kernel
 
@@ -108,7 +108,8 @@ struct DevCase {
     float *f_diag, *f_up, *f_lo, *f_pdiag, *f_poff;
     float *f_x, *f_b, *f_r, *f_rt, *f_p, *f_pt, *f_q, *f_qt;   // [3][N]
     // reductions
-    double *partials;                            // [kMaxRed][kMaxGrid]
+    double *partials;                            // [kMaxRed][red_stride]
+    int32_t red_stride;                          // >= any reducing grid
     unsigned int *ticket;
     KState *ks;                                  // [4]: 0..2 momentum components, 3 pressure
     // setup temporaries (alias Krylov vectors)
@@ -151,6 +152,8 @@ void launch_bicg_iter(const DevCase &d, hipStream_t s);
 void launch_pcg_init(const DevCase &d, int dic, hipStream_t s);
 void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s);
 void launch_dic_precond(const DevCase &d, int with_setup, hipStream_t s);
+void launch_dic_reset(const DevCase &d, hipStream_t s);
+void launch_init_partials(const DevCase &d, hipStream_t s);
 
 // scalar parameters passed by value (no host staging buffers)
 void launch_set_ctl(const DevCase &d, int first, int count, double tol, double rel_tol, int max_iter, hipStream_t s);

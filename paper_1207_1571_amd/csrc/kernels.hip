@@ -33,9 +33,13 @@ namespace {
 
 constexpr int kWaves = kBlock / 64;
 // DIC sweeps: a NaN payload marks "not yet published"; bounded polling
-constexpr unsigned long long kSentinel = 0x7FF4DEADBEEF0001ULL;
+constexpr unsigned long long kSentinel = 0x7FF8DEADBEEF0001ULL;   // quiet NaN with a payload
 constexpr unsigned long long kQNaN = 0x7FF8000000000000ULL;
 constexpr int kSpinLimit = 1 << 18;
+
+// sentinels are written as integers: a double-typed store of a NaN constant
+// need not keep its bit pattern
+__device__ __forceinline__ void clear_word(double *a, int i) { reinterpret_cast<unsigned long long *>(a)[i] = kSentinel; }
 
 __device__ __forceinline__ int logical_block()
 {
@@ -70,8 +74,35 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV])
 
 // Block partial of NV sums -> per-block slot; returns true in every thread of
 // the last block, with the grid totals in tot[] (LDS, valid after return).
+//
+// No memory fence is used (on this GPU a device-scope release writes back the
+// whole L2 of the XCD).  Each block publishes its partials with device-scope
+// atomic stores into slots that hold a NaN sentinel while empty, then takes
+// an integer ticket.  The block that draws the last ticket reads every slot
+// with device-scope atomic loads, waiting on any slot whose store has not
+// landed yet, sums them in slot order and refills the slots with the
+// sentinel for the next reduction.
+__device__ __forceinline__ double slot_take(double *slot)
+{
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(slot);
+    unsigned long long b = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int spin = 0; b == kSentinel && spin < kSpinLimit; ++spin) {
+        __builtin_amdgcn_s_sleep(1);
+        b = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __hip_atomic_store(w, kSentinel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return b == kSentinel ? __longlong_as_double((long long)kQNaN) : __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ void slot_put(double *slot, double v)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b == kSentinel) b = kQNaN;
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(slot), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int NV>
-__device__ bool reduce_last(double (&v)[NV], double *partials, unsigned int *ticket, double *tot)
+__device__ bool reduce_last(double (&v)[NV], double *partials, int stride, unsigned int *ticket, double *tot)
 {
     __shared__ double lds[NV][kWaves];
     __shared__ int amlast;
@@ -88,21 +119,18 @@ __device__ bool reduce_last(double (&v)[NV], double *partials, unsigned int *tic
         for (int k = 0; k < NV; ++k) {
             double s = lds[k][0];
             for (int w = 1; w < kWaves; ++w) s += lds[k][w];
-            __hip_atomic_store(&partials[k * kMaxGrid + lb], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            slot_put(&partials[k * stride + lb], s);
         }
-        __threadfence();
-        unsigned int t = atomicAdd(ticket, 1u);
+        const unsigned int t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         amlast = (t == (unsigned int)G - 1);
     }
     __syncthreads();
     if (!amlast) return false;
-    __threadfence();
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         acc[k] = 0.0;
-        for (int j = threadIdx.x; j < G; j += kBlock)
-            acc[k] += __hip_atomic_load(&partials[k * kMaxGrid + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = threadIdx.x; j < G; j += kBlock) acc[k] += slot_take(&partials[k * stride + j]);
     }
     wave_sum(acc);
     __syncthreads();
@@ -581,7 +609,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_sumx(DevCase d)
     for (int i = r.beg + threadIdx.x; i < r.end; i += kBlock)
         for (int c = 0; c < 3; ++c) v[c] += d.U[(size_t)c * N + i];
     __shared__ double tot[3];
-    if (reduce_last<3>(v, d.partials, d.ticket, tot) && threadIdx.x == 0)
+    if (reduce_last<3>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0)
         for (int c = 0; c < 3; ++c) d.ks[c].xbar = tot[c] / (double)N;
 }
 
@@ -610,7 +638,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(DevCase d)
         }
     }
     __shared__ double tot[9];
-    if (reduce_last<9>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<9>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) {
             KState &s = d.ks[c];
             s.nf = tot[c] + 1e-20;
@@ -673,7 +701,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_spmv(DevCase d)
         }
     }
     __shared__ double tot[3];
-    if (reduce_last<3>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<3>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) {
             if (!act[c]) continue;
             KState &s = d.ks[c];
@@ -708,7 +736,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_update(DevCase d)
         }
     }
     __shared__ double tot[6];
-    if (reduce_last<6>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<6>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) {
             if (!act[c]) continue;
             KState &s = d.ks[c];
@@ -737,7 +765,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_sumx(DevCase d)
     double v[1] = {0.0};
     for (int i = r.beg + threadIdx.x; i < r.end; i += kBlock) v[0] += d.p[i];
     __shared__ double tot[1];
-    if (reduce_last<1>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) d.ks[3].xbar = tot[0] / (double)d.N;
+    if (reduce_last<1>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) d.ks[3].xbar = tot[0] / (double)d.N;
 }
 
 // r = b - A x; normalisation; Jacobi: first rho = r.(r/diag)
@@ -756,13 +784,13 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(DevCase d, int dic)
         v[1] += fabs(r);
         if (!dic) v[2] += r * (r / d.pdiag[i]);
         else {
-            d.dstar[i] = __longlong_as_double(kSentinel);
-            d.y[i] = __longlong_as_double(kSentinel);
-            d.z[i] = __longlong_as_double(kSentinel);
+            clear_word(d.dstar, i);
+            clear_word(d.y, i);
+            clear_word(d.z, i);
         }
     }
     __shared__ double tot[3];
-    if (reduce_last<3>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<3>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
         KState &s = d.ks[3];
         s.nf = tot[0] + 1e-20;
         s.nres0 = tot[1] / s.nf;
@@ -805,7 +833,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv(DevCase d)
         v[0] += d.pp[i] * q;
     }
     __shared__ double tot[1];
-    if (reduce_last<1>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<1>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
         KState &s = d.ks[3];
         if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
         else s.alpha = s.rho / tot[0];
@@ -827,7 +855,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(DevCase d, int dic)
         if (!dic) v[1] += r * (r / d.pdiag[i]);
     }
     __shared__ double tot[2];
-    if (reduce_last<2>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<2>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
         KState &s = d.ks[3];
         s.iters += 1;
         s.nres = tot[0] / s.nf;
@@ -893,54 +921,61 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
     const int n = d.N;
     const int pos = tile * kBlock + threadIdx.x;
     double part = 0.0;
-    if (pos < n) {
-        const int i = MODE == 2 ? d.lvl_cells[n - 1 - pos] : d.lvl_cells[pos];
+    {
+        const bool live = pos < n;
+        const int i = live ? (MODE == 2 ? d.lvl_cells[n - 1 - pos] : d.lvl_cells[pos]) : 0;
         int k, k1;
         double acc;
         const double *src;
         if (MODE == 2) { k = d.own_start[i]; k1 = d.own_start[i + 1]; acc = 0.0; src = d.z; }
         else { k = d.nbr_start[i]; k1 = d.nbr_start[i + 1]; acc = MODE == 0 ? d.pdiag[i] : d.r[i]; src = MODE == 0 ? d.dstar : d.y; }
-        bool fin = false;
+        if (!live) k = k1;
+        // The loop exits only when the whole wave is done: work placed on a
+        // divergent loop-exit path runs after every lane has left the loop,
+        // which would hold back a value another lane of the wave waits for.
+        bool fin = !live;
         int spins = 0;
-        while (!fin) {
-            bool stall = false;
-            while (k < k1) {
-                const int f = MODE == 2 ? k : d.losort[k];
-                const int j = MODE == 2 ? d.nei[f] : d.own[f];
-                double v;
-                if (!dic_try(src, j, v)) { stall = true; break; }
-                const double a = d.poff[f];
-                if (MODE == 0) acc -= a * a / v;
-                else if (MODE == 1) acc -= a * v;
-                else acc += a * v;
-                ++k;
-            }
-            if (!stall) {
-                if (MODE == 0) dic_put(d.dstar, i, acc);
-                else if (MODE == 1) { dic_put(d.y, i, acc / d.dstar[i]); d.z[i] = __longlong_as_double(kSentinel); }
-                else {
-                    const double zi = d.y[i] - acc / d.dstar[i];
-                    dic_put(d.z, i, zi);
-                    d.y[i] = __longlong_as_double(kSentinel);
-                    part = d.r[i] * zi;
+        for (;;) {
+            if (!fin) {
+                bool stall = false;
+                while (k < k1) {
+                    const int f = MODE == 2 ? k : d.losort[k];
+                    const int j = MODE == 2 ? d.nei[f] : d.own[f];
+                    double v;
+                    if (!dic_try(src, j, v)) { stall = true; break; }
+                    const double a = d.poff[f];
+                    if (MODE == 0) acc -= a * a / v;
+                    else if (MODE == 1) acc -= a * v;
+                    else acc += a * v;
+                    ++k;
                 }
-                fin = true;
-            } else if (++spins > kSpinLimit) {
-                dic_put(MODE == 0 ? d.dstar : (MODE == 1 ? d.y : d.z), i, __longlong_as_double((long long)kQNaN));
-                if (MODE == 2) part = __longlong_as_double((long long)kQNaN);
-                d.ticket[8] = 1u;
-                fin = true;
-            } else {
-                __builtin_amdgcn_s_sleep(1);
+                if (!stall) {
+                    if (MODE == 0) dic_put(d.dstar, i, acc);
+                    else if (MODE == 1) { dic_put(d.y, i, acc / d.dstar[i]); clear_word(d.z, i); }
+                    else {
+                        const double zi = d.y[i] - acc / d.dstar[i];
+                        dic_put(d.z, i, zi);
+                        clear_word(d.y, i);
+                        part = d.r[i] * zi;
+                    }
+                    fin = true;
+                } else if (++spins > kSpinLimit) {
+                    dic_put(MODE == 0 ? d.dstar : (MODE == 1 ? d.y : d.z), i, __longlong_as_double((long long)kQNaN));
+                    if (MODE == 2) part = __longlong_as_double((long long)kQNaN);
+                    d.ticket[8] = 1u;
+                    fin = true;
+                }
             }
+            if (__all(fin)) break;
+            __builtin_amdgcn_s_sleep(1);
         }
     }
     if (MODE == 2) {
         double v[1] = {part};
         __shared__ double tot[1];
-        if (reduce_last<1>(v, d.partials, d.ticket, tot) && threadIdx.x == 0) {
+        if (reduce_last<1>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
             KState &s = d.ks[3];
-            d.ticket[1] = 0u;
+            __hip_atomic_store(&d.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
             else if (s.iters == 0) s.rho = tot[0];
             else {
@@ -951,14 +986,33 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
     } else {
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();
-            const unsigned int t = atomicAdd(&d.ticket[2], 1u);
+            const unsigned int t = __hip_atomic_fetch_add(&d.ticket[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (t == gridDim.x - 1) {
-                d.ticket[1] = 0u;
-                d.ticket[2] = 0u;
+                __hip_atomic_store(&d.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&d.ticket[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
+}
+
+__global__ void k_fill_sentinel(double *a, long n)
+{
+    const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) clear_word(a, (int)i);
+}
+
+__global__ void k_dic_reset(DevCase d)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) {
+        d.ks[3].done = 0;
+        d.ks[3].iters = 0;
+        d.ks[3].status = FVM_OK;
+    }
+    if (i >= d.N) return;
+    clear_word(d.dstar, i);
+    clear_word(d.y, i);
+    clear_word(d.z, i);
 }
 
 __global__ void k_set_ctl(KState *ks, int first, int count, double tol, double rel_tol, int max_iter)
@@ -1099,6 +1153,14 @@ void launch_dic_precond(const DevCase &d, int with_setup, hipStream_t s)
     prof_begin("dic_bwd", s);
     hipLaunchKernelGGL(k_dic_sweep<2>, dim3(g), dim3(kBlock), 0, s, d);
     prof_end("dic_bwd", s);
+}
+
+void launch_dic_reset(const DevCase &d, hipStream_t s) { LAUNCH_N(k_dic_reset, d.N, s, d); }
+
+void launch_init_partials(const DevCase &d, hipStream_t s)
+{
+    const long n = (long)kMaxRed * d.red_stride;
+    hipLaunchKernelGGL(k_fill_sentinel, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, d.partials, n);
 }
 
 void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s)

@@ -76,7 +76,7 @@ _lib = None
 
 EXPORTS = ("fvm_mesh_create", "fvm_mesh_destroy", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
            "fvm_case_destroy", "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
-           "simple_iterate", "solve_pressure", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read",
+           "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read",
            "fvm_last_error")
 
 
@@ -102,13 +102,14 @@ def lib():
         L.piso_step.argtypes = [vp, ct.c_int32, vp, ct.POINTER(FvmStepInfo)]
         L.simple_iterate.argtypes = [vp, ct.c_int32, ct.c_double, vp, i32p, ct.POINTER(FvmStepInfo)]
         L.solve_pressure.argtypes = [vp, vp, vp, vp, ct.POINTER(FvmSolverCtl), vp, ct.POINTER(FvmSolveInfo)]
+        L.fvm_dic_apply.argtypes = [vp, vp, vp, vp, vp, vp]
         L.piso_step_batch.argtypes = [ct.POINTER(vp), ct.c_int32, ct.c_int32, vp, ct.POINTER(FvmStepInfo)]
         L.fvm_profile_enable.argtypes = [ct.c_int32]
         L.fvm_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
         L.fvm_last_error.restype = ct.c_char_p
         for name in ("fvm_mesh_create", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
                      "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
-                     "simple_iterate", "solve_pressure", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read"):
+                     "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read"):
             getattr(L, name).restype = ct.c_int32
         _lib = L
     return _lib
@@ -251,6 +252,11 @@ class Case:
         st = _check(lib().solve_pressure(self.handle, _dptr(gamma), _dptr(rhs), _dptr(p), ct.byref(ctl),
                                          ct.c_void_p(_stream_ptr(self.stream)), ct.byref(info)))
         return st, info.as_dict()
+
+
+def dic_apply(case: Case, gamma, r, z, dstar=None):
+    _check(lib().fvm_dic_apply(case.handle, _dptr(gamma), _dptr(r), _dptr(z), _dptr(dstar),
+                               ct.c_void_p(_stream_ptr(case.stream))))
 
 
 def piso_batch(cases: Sequence[Case], n_steps: int, stream=None):
