@@ -911,6 +911,14 @@ __device__ __forceinline__ void dic_put(double *a, int i, double v)
 // MODE 0: D*_i = A_ii - sum_{j<i} a_ij^2 / D*_j
 // MODE 1: y_i = (r_i - sum_{j<i} a_ij y_j) / D*_i      (also clears z)
 // MODE 2: z_i = y_i - (sum_{j>i} a_ij z_j) / D*_i      (reverse order; r.z)
+//
+// A cell's dependency list (neighbour index and coefficient) is read into
+// registers before polling, so each poll round is one batch of independent
+// device-scope loads of the values still missing; once all are present the
+// sum is formed in ascending neighbour order.  Cells with more than kDicDeps
+// dependencies take a streaming path that consumes them one at a time.
+constexpr int kDicDeps = 8;
+
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
 {
@@ -920,55 +928,92 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
     __syncthreads();
     const int n = d.N;
     const int pos = tile * kBlock + threadIdx.x;
+    const bool live = pos < n;
+    const int i = live ? (MODE == 2 ? d.lvl_cells[n - 1 - pos] : d.lvl_cells[pos]) : 0;
+    int k0, k1;
+    double acc;
+    const double *src;
+    if (MODE == 2) { k0 = d.own_start[i]; k1 = d.own_start[i + 1]; acc = 0.0; src = d.z; }
+    else { k0 = d.nbr_start[i]; k1 = d.nbr_start[i + 1]; acc = MODE == 0 ? d.pdiag[i] : d.r[i]; src = MODE == 0 ? d.dstar : d.y; }
+    if (!live) k1 = k0;
+    const int nd = k1 - k0;
+    const bool fast = nd <= kDicDeps;
+    int js[kDicDeps];
+    double as[kDicDeps], vs[kDicDeps];
+#pragma unroll
+    for (int t = 0; t < kDicDeps; ++t) {
+        js[t] = 0; as[t] = 0.0; vs[t] = 0.0;
+        if (fast && t < nd) {
+            const int f = MODE == 2 ? k0 + t : d.losort[k0 + t];
+            js[t] = MODE == 2 ? d.nei[f] : d.own[f];
+            as[t] = d.poff[f];
+        }
+    }
+    const double dsi = (MODE != 0 && live) ? d.dstar[i] : 1.0;
+    const double yi = (MODE == 2 && live) ? d.y[i] : 0.0;
+    unsigned int missing = fast ? (nd >= 32 ? 0xffffffffu : ((1u << nd) - 1u)) : 0u;
+    int k = k0;               // streaming path cursor
     double part = 0.0;
-    {
-        const bool live = pos < n;
-        const int i = live ? (MODE == 2 ? d.lvl_cells[n - 1 - pos] : d.lvl_cells[pos]) : 0;
-        int k, k1;
-        double acc;
-        const double *src;
-        if (MODE == 2) { k = d.own_start[i]; k1 = d.own_start[i + 1]; acc = 0.0; src = d.z; }
-        else { k = d.nbr_start[i]; k1 = d.nbr_start[i + 1]; acc = MODE == 0 ? d.pdiag[i] : d.r[i]; src = MODE == 0 ? d.dstar : d.y; }
-        if (!live) k = k1;
-        // The loop exits only when the whole wave is done: work placed on a
-        // divergent loop-exit path runs after every lane has left the loop,
-        // which would hold back a value another lane of the wave waits for.
-        bool fin = !live;
-        int spins = 0;
-        for (;;) {
-            if (!fin) {
-                bool stall = false;
+    bool fin = !live;
+    int spins = 0;
+    // the loop exits only when the whole wave is done: work placed on a
+    // divergent loop-exit path would run after every lane has left the loop,
+    // holding back values that other lanes of the wave wait for
+    for (;;) {
+        if (!fin) {
+            bool ready;
+            if (fast) {
+#pragma unroll
+                for (int t = 0; t < kDicDeps; ++t) {
+                    if (missing & (1u << t)) {
+                        double v;
+                        if (dic_try(src, js[t], v)) { vs[t] = v; missing &= ~(1u << t); }
+                    }
+                }
+                ready = missing == 0u;
+                if (ready) {
+#pragma unroll
+                    for (int t = 0; t < kDicDeps; ++t) {
+                        if (t < nd) {
+                            if (MODE == 0) acc -= as[t] * as[t] / vs[t];
+                            else if (MODE == 1) acc -= as[t] * vs[t];
+                            else acc += as[t] * vs[t];
+                        }
+                    }
+                }
+            } else {
+                ready = true;
                 while (k < k1) {
                     const int f = MODE == 2 ? k : d.losort[k];
                     const int j = MODE == 2 ? d.nei[f] : d.own[f];
                     double v;
-                    if (!dic_try(src, j, v)) { stall = true; break; }
+                    if (!dic_try(src, j, v)) { ready = false; break; }
                     const double a = d.poff[f];
                     if (MODE == 0) acc -= a * a / v;
                     else if (MODE == 1) acc -= a * v;
                     else acc += a * v;
                     ++k;
                 }
-                if (!stall) {
-                    if (MODE == 0) dic_put(d.dstar, i, acc);
-                    else if (MODE == 1) { dic_put(d.y, i, acc / d.dstar[i]); clear_word(d.z, i); }
-                    else {
-                        const double zi = d.y[i] - acc / d.dstar[i];
-                        dic_put(d.z, i, zi);
-                        clear_word(d.y, i);
-                        part = d.r[i] * zi;
-                    }
-                    fin = true;
-                } else if (++spins > kSpinLimit) {
-                    dic_put(MODE == 0 ? d.dstar : (MODE == 1 ? d.y : d.z), i, __longlong_as_double((long long)kQNaN));
-                    if (MODE == 2) part = __longlong_as_double((long long)kQNaN);
-                    d.ticket[8] = 1u;
-                    fin = true;
-                }
             }
-            if (__all(fin)) break;
-            __builtin_amdgcn_s_sleep(1);
+            if (ready) {
+                if (MODE == 0) dic_put(d.dstar, i, acc);
+                else if (MODE == 1) { dic_put(d.y, i, acc / dsi); clear_word(d.z, i); }
+                else {
+                    const double zi = yi - acc / dsi;
+                    dic_put(d.z, i, zi);
+                    clear_word(d.y, i);
+                    part = d.r[i] * zi;
+                }
+                fin = true;
+            } else if (++spins > kSpinLimit) {
+                dic_put(MODE == 0 ? d.dstar : (MODE == 1 ? d.y : d.z), i, __longlong_as_double((long long)kQNaN));
+                if (MODE == 2) part = __longlong_as_double((long long)kQNaN);
+                d.ticket[8] = 1u;
+                fin = true;
+            }
         }
+        if (__all(fin)) break;
+        __builtin_amdgcn_s_sleep(1);
     }
     if (MODE == 2) {
         double v[1] = {part};
