@@ -193,7 +193,7 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
     d.red_stride = std::max<int32_t>(kMaxGrid, (int32_t)((N + kBlock - 1) / kBlock));
     d.partials = b.take<double>((size_t)kMaxRed * d.red_stride);
     d.ticket = b.take<unsigned int>(64);
-    d.ks = b.take<KState>(4);
+    d.ks = b.take<KState>(kNumKs);
     b.off = (b.off + 255) / 256 * 256;
 }
 
@@ -205,7 +205,10 @@ fvm_status check_opts(const fvm_mesh *m, const fvm_case_opts *o)
         return fvm_fail(FVM_EINVAL, "case: need 1 <= n_corr*(n_non_orth_corr+1) <= 16");
     if (o->p_ref_cell < 0 || o->p_ref_cell >= m->N) return fvm_fail(FVM_EINVAL, "case: p_ref_cell out of range");
     if (o->precision != FVM_FP64 && o->precision != FVM_MIXED) return fvm_fail(FVM_EINVAL, "case: bad precision");
-    if (o->precision == FVM_MIXED) return fvm_fail(FVM_EINVAL, "case: mixed precision is not available in this build");
+    if (o->precision == FVM_MIXED && o->p_ctl.precond == FVM_PC_DIC)
+        return fvm_fail(FVM_EINVAL, "case: mixed precision runs Jacobi inner solves (DIC is FP64 only)");
+    if (o->precision == FVM_MIXED && (!(o->inner_rel_tol > 0.0) || !(o->inner_rel_tol < 1.0) || o->inner_max_iter < 1))
+        return fvm_fail(FVM_EINVAL, "case: mixed precision needs 0 < inner_rel_tol < 1 and inner_max_iter >= 1");
     if (o->p_ctl.precond != FVM_PC_JACOBI && o->p_ctl.precond != FVM_PC_DIC)
         return fvm_fail(FVM_EINVAL, "case: bad preconditioner");
     if (o->u_ctl.precond != FVM_PC_JACOBI) return fvm_fail(FVM_EINVAL, "case: momentum solver takes Jacobi only");
@@ -228,11 +231,11 @@ struct fvm_case {
     bool nonorth, has_fixed_p;
     std::vector<fvm_patch> patches;
     // Krylov state mirror: a ring of pinned host copies, one per chunk
-    KState *hks = nullptr;          // [kRing][4]
+    KState *hks = nullptr;          // [kRing][kNumKs]
     hipEvent_t ev[kRing];
     bool ev_pending[kRing];
     int ring = 0;
-    int last_iters[2] = {0, 0};     // 0 momentum, 1 pressure: chunk-size prediction
+    int last_iters[4] = {0, 0, 0, 0};   // momentum, pressure, and their inner solves: chunk sizing
 };
 
 // ---------------------------------------------------------------------------
@@ -302,7 +305,7 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
         delete c;
         return code;
     };
-    if (hipHostMalloc((void **)&c->hks, sizeof(KState) * 4 * kRing, hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&c->hks, sizeof(KState) * kNumKs * kRing, hipHostMallocDefault) != hipSuccess)
         return fail(fvm_fail(FVM_EDEVICE, "case: pinned host buffer"));
     for (int k = 0; k < kRing; ++k) {
         c->ev_pending[k] = false;
@@ -324,7 +327,7 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     UPCHK(up(d.tmpCf, m->Cf, s));
     if (d.lvl_start) { UPCHK(up(d.lvl_start, m->lvl_start, s)); UPCHK(up(d.lvl_cells, m->lvl_cells, s)); }
     UPCHK(hipMemsetAsync(d.ticket, 0, 64 * sizeof(unsigned int), s));
-    UPCHK(hipMemsetAsync(d.ks, 0, 4 * sizeof(KState), s));
+    UPCHK(hipMemsetAsync(d.ks, 0, kNumKs * sizeof(KState), s));
     st = upload_patches(c, s);
     if (st != FVM_OK) return fail(st);
     launch_init_partials(d, s);
@@ -395,35 +398,25 @@ struct SolveOut {
     KState ks[4];
 };
 
-// Enqueue one solve and return its final scalars.  kind 0: momentum BiCG
-// (systems 0..2), kind 1: pressure CG (system 3).
-fvm_status run_solve(fvm_case *c, int kind, const fvm_solver_ctl &ctl, hipStream_t s, KState *final_state)
+// Enqueue iterations in chunks until the systems [first, first+count) are
+// done; the Krylov state array after the last chunk is returned in res.
+// launch_iter enqueues one iteration.  `predicted` sizes the first chunk.
+template <class F>
+fvm_status iterate_until_done(fvm_case *c, int first, int count, int predicted, long limit, hipStream_t s,
+                              F launch_iter, KState *res)
 {
     const DevCase &d = c->d;
-    const int first = kind == 0 ? 0 : 3, count = kind == 0 ? 3 : 1;
-    const int dic = kind == 1 && ctl.precond == FVM_PC_DIC;
-    launch_set_ctl(d, first, count, ctl.tol, ctl.rel_tol, ctl.max_iter, s);
-    if (kind == 0) launch_bicg_init(d, s);
-    else launch_pcg_init(d, dic, s);
-    if (dic) launch_dic_precond(d, 1, s);
-
-    const int predicted = c->last_iters[kind];
     int chunk = predicted > 0 ? std::max(2, predicted - predicted / 4) : 4;
-    const long limit = (long)ctl.max_iter + 1;   // the device stops at max_iter
     long issued = 0;
     int prev_slot = -1;
-    KState res[4];
     auto all_done = [&](const KState *h) {
         for (int k = 0; k < count; ++k)
             if (!h[first + k].done) return false;
         return true;
     };
     for (;;) {
-        const int n = (int)std::min<long>(chunk, limit - issued);
-        for (int k = 0; k < n; ++k) {
-            if (kind == 0) launch_bicg_iter(d, s);
-            else launch_pcg_iter(d, dic, s);
-        }
+        const int n = (int)std::min<long>(chunk, std::max<long>(1, limit - issued));
+        for (int k = 0; k < n; ++k) launch_iter();
         issued += n;
         HIPCHK(hipGetLastError());
         const int slot = c->ring;
@@ -432,27 +425,87 @@ fvm_status run_solve(fvm_case *c, int kind, const fvm_solver_ctl &ctl, hipStream
             HIPCHK(hipEventSynchronize(c->ev[slot]));
             c->ev_pending[slot] = false;
         }
-        HIPCHK(hipMemcpyAsync(c->hks + 4 * slot, d.ks, 4 * sizeof(KState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(c->hks + kNumKs * slot, d.ks, kNumKs * sizeof(KState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(c->ev[slot], s));
         c->ev_pending[slot] = true;
         // inspect the previous chunk while this one runs
         if (prev_slot >= 0) {
             HIPCHK(hipEventSynchronize(c->ev[prev_slot]));
             c->ev_pending[prev_slot] = false;
-            if (all_done(c->hks + 4 * prev_slot)) {
-                std::memcpy(res, c->hks + 4 * prev_slot, sizeof(res));
-                break;
+            if (all_done(c->hks + kNumKs * prev_slot)) {
+                std::memcpy(res, c->hks + kNumKs * prev_slot, kNumKs * sizeof(KState));
+                return FVM_OK;
             }
         }
         if (issued >= limit) {
             HIPCHK(hipEventSynchronize(c->ev[slot]));
             c->ev_pending[slot] = false;
-            std::memcpy(res, c->hks + 4 * slot, sizeof(res));
+            std::memcpy(res, c->hks + kNumKs * slot, kNumKs * sizeof(KState));
             if (!all_done(res)) return fvm_fail(FVM_EDEVICE, "solve: iteration limit passed without a stop flag");
-            break;
+            return FVM_OK;
         }
         prev_slot = slot;
         chunk = predicted > 0 ? std::max(2, predicted / 8) : std::min(64, chunk * 2);
+    }
+}
+
+// synchronous copy of the Krylov states (once per outer refinement step)
+fvm_status snapshot(fvm_case *c, hipStream_t s, KState *res)
+{
+    const int slot = c->ring;
+    c->ring = (c->ring + 1) % kRing;
+    if (c->ev_pending[slot]) {
+        HIPCHK(hipEventSynchronize(c->ev[slot]));
+        c->ev_pending[slot] = false;
+    }
+    HIPCHK(hipMemcpyAsync(c->hks + kNumKs * slot, c->d.ks, kNumKs * sizeof(KState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(c->ev[slot], s));
+    HIPCHK(hipEventSynchronize(c->ev[slot]));
+    std::memcpy(res, c->hks + kNumKs * slot, kNumKs * sizeof(KState));
+    return FVM_OK;
+}
+
+// Enqueue one solve and return its final scalars.  kind 0: momentum BiCG
+// (systems 0..2), kind 1: pressure CG (system 3).  FVM_MIXED cases run the
+// FP64 refinement loop around FP32 inner solves (systems 4..7).
+fvm_status run_solve(fvm_case *c, int kind, const fvm_solver_ctl &ctl, hipStream_t s, KState *final_state)
+{
+    const DevCase &d = c->d;
+    const int first = kind == 0 ? 0 : 3, count = kind == 0 ? 3 : 1;
+    const int dic = kind == 1 && ctl.precond == FVM_PC_DIC;
+    const bool mixed = c->o.precision == FVM_MIXED;
+    launch_set_ctl(d, first, count, ctl.tol, ctl.rel_tol, ctl.max_iter, s);
+    if (kind == 0) launch_bicg_init(d, s);
+    else launch_pcg_init(d, dic, s);
+    KState res[kNumKs];
+    fvm_status st;
+    if (!mixed) {
+        if (dic) launch_dic_precond(d, 1, s);
+        st = iterate_until_done(c, first, count, c->last_iters[kind], (long)ctl.max_iter + 1, s, [&] {
+            if (kind == 0) launch_bicg_iter(d, s);
+            else launch_pcg_iter(d, dic, s);
+        }, res);
+        if (st != FVM_OK) return st;
+    } else {
+        const int ifirst = kind == 0 ? 4 : 7;
+        launch_set_ctl(d, ifirst, count, 0.0, c->o.inner_rel_tol, c->o.inner_max_iter, s);
+        launch_mx_cvt(d, kind, s);
+        for (int outer = 0;; ++outer) {
+            st = snapshot(c, s, res);
+            if (st != FVM_OK) return st;
+            bool all = true;
+            for (int k = 0; k < count; ++k) all = all && res[first + k].done;
+            if (all) break;
+            if (outer >= 1000) return fvm_fail(FVM_EDEVICE, "solve: refinement did not terminate");
+            launch_mx_inner_init(d, kind, s);
+            st = iterate_until_done(c, ifirst, count, c->last_iters[2 + kind], (long)c->o.inner_max_iter + 1, s,
+                                    [&] { launch_mx_inner_iter(d, kind, s); }, res);
+            if (st != FVM_OK) return st;
+            int mi = 0;
+            for (int k = 0; k < count; ++k) mi = std::max(mi, res[ifirst + k].iters);
+            c->last_iters[2 + kind] = mi;
+            launch_mx_correct_resid(d, kind, s);
+        }
     }
     int mx = 0;
     for (int k = 0; k < count; ++k) mx = std::max(mx, res[first + k].iters);

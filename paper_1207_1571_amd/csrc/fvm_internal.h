@@ -70,6 +70,7 @@ static_assert(sizeof(KState) == 128, "KState layout");
 constexpr int kMaxGrid = 1024;
 constexpr int kBlock = 256;
 constexpr int kMaxRed = 12;          // reduced quantities per kernel
+constexpr int kNumKs = 8;            // Krylov states per case
 
 // ---------------------------------------------------------------------------
 // Device view of one case: every pointer lies inside the caller's workspace.
@@ -111,7 +112,7 @@ struct DevCase {
     double *partials;                            // [kMaxRed][red_stride]
     int32_t red_stride;                          // >= any reducing grid
     unsigned int *ticket;
-    KState *ks;                                  // [4]: 0..2 momentum components, 3 pressure
+    KState *ks;                                  // [8]: 0..2 momentum, 3 pressure; 4..7 their FP32 inner solves
     // setup temporaries (alias Krylov vectors)
     double *tmpC, *tmpCf;
 };
@@ -152,6 +153,11 @@ void launch_bicg_iter(const DevCase &d, hipStream_t s);
 void launch_pcg_init(const DevCase &d, int dic, hipStream_t s);
 void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s);
 void launch_dic_precond(const DevCase &d, int with_setup, hipStream_t s);
+// mixed precision (kind 0: momentum, 1: pressure)
+void launch_mx_cvt(const DevCase &d, int kind, hipStream_t s);
+void launch_mx_inner_init(const DevCase &d, int kind, hipStream_t s);
+void launch_mx_inner_iter(const DevCase &d, int kind, hipStream_t s);
+void launch_mx_correct_resid(const DevCase &d, int kind, hipStream_t s);
 void launch_dic_reset(const DevCase &d, hipStream_t s);
 void launch_init_partials(const DevCase &d, hipStream_t s);
 

@@ -591,7 +591,12 @@ __global__ void k_U_corr(DevCase d)
 }
 
 // ---------------------------------------------------------------------------
-// Krylov: momentum BiCG, three components sharing one matrix
+// Krylov solvers (Barrett et al., "Templates": CG and BiCG)
+//
+// The iteration kernels are templated on the vector/matrix value type: the
+// FP64 solves and the FP32 inner solves of the mixed-precision refinement run
+// the same code over different arrays.  Every dot product and residual sum is
+// accumulated in FP64 whatever the vector type.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ void set_done(KState &s, int status)
@@ -600,7 +605,142 @@ __device__ __forceinline__ void set_done(KState &s, int status)
     s.done = 1;
 }
 
-// sum x_c -> xbar_c
+template <class T>
+__device__ __forceinline__ T row_apply_t(const DevCase &d, int i, const T *__restrict__ diag, const T *__restrict__ up,
+                                         const T *__restrict__ lo, const T *__restrict__ x)
+{
+    T acc = diag[i] * x[i];
+    const int f0 = d.own_start[i], f1 = d.own_start[i + 1];
+    for (int f = f0; f < f1; ++f) acc += up[f] * x[d.nei[f]];
+    const int k0 = d.nbr_start[i], k1 = d.nbr_start[i + 1];
+    for (int k = k0; k < k1; ++k) {
+        const int f = d.losort[k];
+        acc += lo[f] * x[d.own[f]];
+    }
+    return acc;
+}
+
+// symmetric system (pressure): one coefficient per face
+template <class T>
+struct CGView {
+    const T *diag, *off;
+    T *x, *r, *p, *q;
+    const double *z;    // DIC output (FP64 path), else nullptr
+    KState *ks;
+};
+
+// non-symmetric system (momentum), three right-hand sides sharing A
+template <class T>
+struct BiView {
+    const T *diag, *up, *lo;
+    T *x, *r, *rt, *p, *pt, *q, *qt;     // [3][N]
+    KState *ks;                          // [3]
+};
+
+// ---- BiCG --------------------------------------------------------------
+
+// p = z + beta p, p~ = z~ + beta p~ (z = r/diag, z~ = r~/diag)
+template <class T>
+__global__ void k_bicg_dir(DevCase d, BiView<T> v)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const int N = d.N;
+    const T dg = v.diag[i];
+    for (int c = 0; c < 3; ++c) {
+        const KState &s = v.ks[c];
+        if (s.done) continue;
+        const size_t j = (size_t)c * N + i;
+        const T z = v.r[j] / dg, zt = v.rt[j] / dg;
+        if (s.first) {
+            v.p[j] = z;
+            v.pt[j] = zt;
+        } else {
+            const T be = (T)s.beta;
+            v.p[j] = z + be * v.p[j];
+            v.pt[j] = zt + be * v.pt[j];
+        }
+    }
+}
+
+// q = A p, q~ = A^T p~, p~.q -> alpha
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_bicg_spmv(DevCase d, BiView<T> v)
+{
+    int act[3];
+    for (int c = 0; c < 3; ++c) act[c] = !v.ks[c].done;
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N);
+    const int N = d.N;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const T *p = v.p + (size_t)c * N, *pt = v.pt + (size_t)c * N;
+            const T q = row_apply_t<T>(d, i, v.diag, v.up, v.lo, p);
+            const T qt = row_apply_t<T>(d, i, v.diag, v.lo, v.up, pt);
+            v.q[(size_t)c * N + i] = q;
+            v.qt[(size_t)c * N + i] = qt;
+            acc[c] += (double)pt[i] * (double)q;
+        }
+    }
+    __shared__ double tot[3];
+    if (reduce_last<3>(acc, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = v.ks[c];
+            if (tot[c] == 0.0 || !isfinite(tot[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else s.alpha = s.rho / tot[c];
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q, r~ -= alpha q~; rho = z.r~, |r| -> stop test, beta
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_bicg_update(DevCase d, BiView<T> v)
+{
+    int act[3];
+    T al[3];
+    for (int c = 0; c < 3; ++c) { act[c] = !v.ks[c].done; al[c] = (T)v.ks[c].alpha; }
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N);
+    const int N = d.N;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const T dg = v.diag[i];
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const size_t j = (size_t)c * N + i;
+            v.x[j] += al[c] * v.p[j];
+            const T r = v.r[j] - al[c] * v.q[j];
+            const T rt = v.rt[j] - al[c] * v.qt[j];
+            v.r[j] = r;
+            v.rt[j] = rt;
+            acc[c] += (double)(r / dg) * (double)rt;
+            acc[3 + c] += fabs((double)r);
+        }
+    }
+    __shared__ double tot[6];
+    if (reduce_last<6>(acc, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = v.ks[c];
+            s.iters += 1;
+            s.nres = tot[3 + c] / s.nf;
+            s.first = 0;
+            if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
+            else if (s.nres <= s.tol_eff) set_done(s, FVM_OK);
+            else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+            else if (tot[c] == 0.0 || !isfinite(tot[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else {
+                s.beta = tot[c] / s.rho;
+                s.rho = tot[c];
+            }
+        }
+    }
+}
+
+// FP64 start: sum x_c -> xbar_c
 __global__ void __launch_bounds__(kBlock) k_bicg_sumx(DevCase d)
 {
     const Range r = block_range(d.N);
@@ -613,7 +753,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_sumx(DevCase d)
         for (int c = 0; c < 3; ++c) d.ks[c].xbar = tot[c] / (double)N;
 }
 
-// r = b - A x, r~ = r, normalisation, first rho = z.r~ (z = r/diag)
+// FP64 start: r = b - A x, r~ = r, normalisation, first rho = z.r~
 __global__ void __launch_bounds__(kBlock) k_bicg_init(DevCase d)
 {
     const Range rg = block_range(d.N);
@@ -658,106 +798,73 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(DevCase d)
     }
 }
 
-// p = z + beta p, p~ = z~ + beta p~ (z = r/diag, z~ = r~/diag)
-__global__ void k_bicg_dir(DevCase d)
+// ---- CG ----------------------------------------------------------------
+
+// p = z + beta p (Jacobi z = r/diag; DIC z from the sweeps)
+template <class T>
+__global__ void k_cg_dir(DevCase d, CGView<T> v)
 {
+    const KState &s = *v.ks;
+    if (s.done) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= d.N) return;
-    const int N = d.N;
-    const double dg = d.mdiag[i];
-    for (int c = 0; c < 3; ++c) {
-        const KState &s = d.ks[c];
-        if (s.done) continue;
-        const size_t j = (size_t)c * N + i;
-        const double z = d.r[j] / dg, zt = d.rt[j] / dg;
-        if (s.first) {
-            d.pp[j] = z;
-            d.pt[j] = zt;
-        } else {
-            d.pp[j] = z + s.beta * d.pp[j];
-            d.pt[j] = zt + s.beta * d.pt[j];
-        }
+    const T z = v.z ? (T)v.z[i] : v.r[i] / v.diag[i];
+    v.p[i] = s.first ? z : z + (T)s.beta * v.p[i];
+}
+
+// q = A p, p.q -> alpha
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cg_spmv(DevCase d, CGView<T> v)
+{
+    if (v.ks->done) return;
+    const Range rg = block_range(d.N);
+    double acc[1] = {0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const T q = row_apply_t<T>(d, i, v.diag, v.off, v.off, v.p);
+        v.q[i] = q;
+        acc[0] += (double)v.p[i] * (double)q;
+    }
+    __shared__ double tot[1];
+    if (reduce_last<1>(acc, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+        KState &s = *v.ks;
+        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else s.alpha = s.rho / tot[0];
     }
 }
 
-// q = A p, q~ = A^T p~, p~.q -> alpha
-__global__ void __launch_bounds__(kBlock) k_bicg_spmv(DevCase d)
+// x += alpha p, r -= alpha q, |r| -> stop test; Jacobi: rho = r.(r/diag), beta
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cg_update(DevCase d, CGView<T> v, int dic)
 {
-    int act[3];
-    for (int c = 0; c < 3; ++c) act[c] = !d.ks[c].done;
-    if (!act[0] && !act[1] && !act[2]) return;
+    if (v.ks->done) return;
+    const T al = (T)v.ks->alpha;
     const Range rg = block_range(d.N);
-    const int N = d.N;
-    double v[3] = {0.0, 0.0, 0.0};
+    double acc[2] = {0.0, 0.0};
     for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        for (int c = 0; c < 3; ++c) {
-            if (!act[c]) continue;
-            const double *p = d.pp + (size_t)c * N, *pt = d.pt + (size_t)c * N;
-            const double q = row_apply(d, i, d.mdiag, d.upper, d.lower, p);
-            const double qt = row_apply(d, i, d.mdiag, d.lower, d.upper, pt);
-            d.q[(size_t)c * N + i] = q;
-            d.qt[(size_t)c * N + i] = qt;
-            v[c] += pt[i] * q;
-        }
+        v.x[i] += al * v.p[i];
+        const T r = v.r[i] - al * v.q[i];
+        v.r[i] = r;
+        acc[0] += fabs((double)r);
+        if (!dic) acc[1] += (double)r * (double)(r / v.diag[i]);
     }
-    __shared__ double tot[3];
-    if (reduce_last<3>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
-        for (int c = 0; c < 3; ++c) {
-            if (!act[c]) continue;
-            KState &s = d.ks[c];
-            if (tot[c] == 0.0 || !isfinite(tot[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
-            else s.alpha = s.rho / tot[c];
-        }
-    }
-}
-
-// x += alpha p, r -= alpha q, r~ -= alpha q~; rho = z.r~, |r| -> stop test, beta
-__global__ void __launch_bounds__(kBlock) k_bicg_update(DevCase d)
-{
-    int act[3];
-    double al[3];
-    for (int c = 0; c < 3; ++c) { act[c] = !d.ks[c].done; al[c] = d.ks[c].alpha; }
-    if (!act[0] && !act[1] && !act[2]) return;
-    const Range rg = block_range(d.N);
-    const int N = d.N;
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        const double dg = d.mdiag[i];
-        for (int c = 0; c < 3; ++c) {
-            if (!act[c]) continue;
-            const size_t j = (size_t)c * N + i;
-            d.U[j] += al[c] * d.pp[j];
-            const double r = d.r[j] - al[c] * d.q[j];
-            const double rt = d.rt[j] - al[c] * d.qt[j];
-            d.r[j] = r;
-            d.rt[j] = rt;
-            v[c] += (r / dg) * rt;
-            v[3 + c] += fabs(r);
-        }
-    }
-    __shared__ double tot[6];
-    if (reduce_last<6>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
-        for (int c = 0; c < 3; ++c) {
-            if (!act[c]) continue;
-            KState &s = d.ks[c];
-            s.iters += 1;
-            s.nres = tot[3 + c] / s.nf;
-            s.first = 0;
-            if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
-            else if (s.nres <= s.tol_eff) set_done(s, FVM_OK);
-            else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
-            else if (tot[c] == 0.0 || !isfinite(tot[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+    __shared__ double tot[2];
+    if (reduce_last<2>(acc, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+        KState &s = *v.ks;
+        s.iters += 1;
+        s.nres = tot[0] / s.nf;
+        s.first = 0;
+        if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
+        else if (s.nres <= s.tol_eff) set_done(s, FVM_OK);
+        else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+        else if (!dic) {
+            if (!(tot[1] > 0.0) || !isfinite(tot[1])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
             else {
-                s.beta = tot[c] / s.rho;
-                s.rho = tot[c];
+                s.beta = tot[1] / s.rho;
+                s.rho = tot[1];
             }
         }
     }
 }
-
-// ---------------------------------------------------------------------------
-// Krylov: pressure CG (symmetric matrix pdiag / poff), Jacobi or DIC
-// ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kBlock) k_pcg_sumx(DevCase d)
 {
@@ -765,10 +872,11 @@ __global__ void __launch_bounds__(kBlock) k_pcg_sumx(DevCase d)
     double v[1] = {0.0};
     for (int i = r.beg + threadIdx.x; i < r.end; i += kBlock) v[0] += d.p[i];
     __shared__ double tot[1];
-    if (reduce_last<1>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) d.ks[3].xbar = tot[0] / (double)d.N;
+    if (reduce_last<1>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0)
+        d.ks[3].xbar = tot[0] / (double)d.N;
 }
 
-// r = b - A x; normalisation; Jacobi: first rho = r.(r/diag)
+// FP64 start: r = b - A x; normalisation; Jacobi: first rho = r.(r/diag)
 __global__ void __launch_bounds__(kBlock) k_pcg_init(DevCase d, int dic)
 {
     const Range rg = block_range(d.N);
@@ -810,69 +918,138 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(DevCase d, int dic)
     }
 }
 
-// p = z + beta p (Jacobi z = r/diag; DIC z from the sweeps)
-__global__ void k_pcg_dir(DevCase d, int dic)
-{
-    const KState &s = d.ks[3];
-    if (s.done) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.N) return;
-    const double z = dic ? d.z[i] : d.r[i] / d.pdiag[i];
-    d.pp[i] = s.first ? z : z + s.beta * d.pp[i];
-}
+// ---------------------------------------------------------------------------
+// Mixed precision: FP64 iterative refinement around FP32 inner solves
+//
+// Outer (FP64, states ks[0..3]):  r = b - A x  ->  if nres <= tol: stop
+//   inner (FP32, states ks[4..7]): A e = s r from e = 0 to a relative
+//                                  reduction eta, s = N / sum|r| (keeps the
+//                                  demoted residual O(1))
+//   x += e / s  (FP64).
+// The outer iteration count is the total number of inner iterations.
+// ---------------------------------------------------------------------------
 
-// q = A p, p.q -> alpha
-__global__ void __launch_bounds__(kBlock) k_pcg_spmv(DevCase d)
+// FP32 copies of the assembled matrix values (the topology is shared)
+__global__ void k_mx_cvt(DevCase d, int kind)
 {
-    if (d.ks[3].done) return;
-    const Range rg = block_range(d.N);
-    double v[1] = {0.0};
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        const double q = row_apply(d, i, d.pdiag, d.poff, d.poff, d.pp);
-        d.q[i] = q;
-        v[0] += d.pp[i] * q;
-    }
-    __shared__ double tot[1];
-    if (reduce_last<1>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
-        KState &s = d.ks[3];
-        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
-        else s.alpha = s.rho / tot[0];
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (kind == 1) {
+        if (t < d.N) d.f_pdiag[t] = (float)d.pdiag[t];
+        if (t < d.Fi) d.f_poff[t] = (float)d.poff[t];
+    } else {
+        if (t < d.N) d.f_diag[t] = (float)d.mdiag[t];
+        if (t < d.Fi) { d.f_up[t] = (float)d.upper[t]; d.f_lo[t] = (float)d.lower[t]; }
     }
 }
 
-// x += alpha p, r -= alpha q, |r| -> stop test; Jacobi: rho = r.(r/diag), beta
-__global__ void __launch_bounds__(kBlock) k_pcg_update(DevCase d, int dic)
+__device__ __forceinline__ double mx_scale(const KState &o, int N) { return (double)N / (o.nres * o.nf); }
+
+// inner start: r_in = s r (FP32), e = 0, inner normalisation sum|r_in|,
+// Jacobi rho.  kind 1: pressure (one system), kind 0: momentum (three).
+__global__ void __launch_bounds__(kBlock) k_mx_inner_init(DevCase d, int kind)
 {
-    if (d.ks[3].done) return;
-    const double al = d.ks[3].alpha;
-    const Range rg = block_range(d.N);
-    double v[2] = {0.0, 0.0};
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        d.p[i] += al * d.pp[i];
-        const double r = d.r[i] - al * d.q[i];
-        d.r[i] = r;
-        v[0] += fabs(r);
-        if (!dic) v[1] += r * (r / d.pdiag[i]);
+    const int nsys = kind == 1 ? 1 : 3, o0 = kind == 1 ? 3 : 0, i0 = kind == 1 ? 7 : 4;
+    int act[3];
+    double sc[3];
+    for (int c = 0; c < 3; ++c) {
+        act[c] = c < nsys && !d.ks[o0 + c].done;
+        sc[c] = act[c] ? mx_scale(d.ks[o0 + c], d.N) : 0.0;
     }
-    __shared__ double tot[2];
-    if (reduce_last<2>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
-        KState &s = d.ks[3];
-        s.iters += 1;
-        s.nres = tot[0] / s.nf;
-        s.first = 0;
-        if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
-        else if (s.nres <= s.tol_eff) set_done(s, FVM_OK);
-        else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
-        else if (!dic) {
-            if (!(tot[1] > 0.0) || !isfinite(tot[1])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
-            else {
-                s.beta = tot[1] / s.rho;
-                s.rho = tot[1];
-            }
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N);
+    const int N = d.N;
+    const float *diag = kind == 1 ? d.f_pdiag : d.f_diag;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const float dg = diag[i];
+        for (int c = 0; c < nsys; ++c) {
+            if (!act[c]) continue;
+            const size_t j = (size_t)c * N + i;
+            const float r = (float)(sc[c] * d.r[j]);
+            d.f_r[j] = r;
+            d.f_x[j] = 0.0f;
+            if (kind == 0) d.f_rt[j] = r;
+            v[c] += fabs((double)r);
+            v[3 + c] += (double)(r / dg) * (double)r;
+        }
+    }
+    __shared__ double tot[6];
+    if (reduce_last<6>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < nsys; ++c) {
+            KState &s = d.ks[i0 + c];
+            if (!act[c]) { set_done(s, FVM_OK); s.iters = 0; continue; }
+            s.nf = tot[c];
+            s.nres0 = 1.0;
+            s.nres = 1.0;
+            s.tol_eff = fmax(s.tol, s.rel_tol);
+            s.iters = 0;
+            s.done = 0;
+            s.status = FVM_OK;
+            s.first = 1;
+            s.beta = 0.0;
+            const bool bad = kind == 1 ? !(tot[3 + c] > 0.0) : tot[3 + c] == 0.0;
+            if (!isfinite(tot[c]) || !(tot[c] > 0.0)) set_done(s, FVM_ENUMERIC);
+            else if (bad || !isfinite(tot[3 + c])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+            else s.rho = tot[3 + c];
         }
     }
 }
 
+// x += e / s (FP64), for the systems whose outer loop is still running
+__global__ void k_mx_correct(DevCase d, int kind)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const int nsys = kind == 1 ? 1 : 3, o0 = kind == 1 ? 3 : 0;
+    double *x = kind == 1 ? d.p : d.U;
+    for (int c = 0; c < nsys; ++c) {
+        const KState &o = d.ks[o0 + c];
+        if (o.done) continue;
+        const double s = mx_scale(o, d.N);
+        const size_t j = (size_t)c * d.N + i;
+        x[j] += (double)d.f_x[j] / s;
+    }
+}
+
+// outer residual after a correction: r = b - A x (FP64), nres, stop test;
+// the inner iterations are added to the outer count
+__global__ void __launch_bounds__(kBlock) k_mx_resid(DevCase d, int kind)
+{
+    const int nsys = kind == 1 ? 1 : 3, o0 = kind == 1 ? 3 : 0, i0 = kind == 1 ? 7 : 4;
+    int act[3];
+    for (int c = 0; c < 3; ++c) act[c] = c < nsys && !d.ks[o0 + c].done;
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N);
+    const int N = d.N;
+    const double *diag = kind == 1 ? d.pdiag : d.mdiag;
+    const double *up = kind == 1 ? d.poff : d.upper;
+    const double *lo = kind == 1 ? d.poff : d.lower;
+    const double *xb = kind == 1 ? d.p : d.U;
+    const double *bb = kind == 1 ? d.pb : d.rhs;
+    double v[3] = {0, 0, 0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        for (int c = 0; c < nsys; ++c) {
+            if (!act[c]) continue;
+            const size_t j = (size_t)c * N + i;
+            const double r = bb[j] - row_apply(d, i, diag, up, lo, xb + (size_t)c * N);
+            d.r[j] = r;
+            v[c] += fabs(r);
+        }
+    }
+    __shared__ double tot[3];
+    if (reduce_last<3>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < nsys; ++c) {
+            if (!act[c]) continue;
+            KState &o = d.ks[o0 + c];
+            const KState &in = d.ks[i0 + c];
+            o.iters += in.iters;
+            o.nres = tot[c] / o.nf;
+            if (in.status == FVM_ENUMERIC || !isfinite(o.nres)) set_done(o, FVM_ENUMERIC);
+            else if (o.nres <= o.tol_eff) set_done(o, FVM_OK);
+            else if (o.iters >= o.max_iter) set_done(o, FVM_WARN_MAXITER);
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------
 // DIC triangular sweeps, sync-free in level order
@@ -1169,19 +1346,76 @@ void launch_bicg_init(const DevCase &d, hipStream_t s)
     LAUNCH_R(k_bicg_init, d.N, s, d);
 }
 
+static BiView<double> bi64(const DevCase &d)
+{
+    return BiView<double>{d.mdiag, d.upper, d.lower, d.U, d.r, d.rt, d.pp, d.pt, d.q, d.qt, d.ks};
+}
+
+static BiView<float> bi32(const DevCase &d)
+{
+    return BiView<float>{d.f_diag, d.f_up, d.f_lo, d.f_x, d.f_r, d.f_rt, d.f_p, d.f_pt, d.f_q, d.f_qt, d.ks + 4};
+}
+
+static CGView<double> cg64(const DevCase &d, int dic)
+{
+    return CGView<double>{d.pdiag, d.poff, d.p, d.r, d.pp, d.q, dic ? d.z : nullptr, d.ks + 3};
+}
+
+static CGView<float> cg32(const DevCase &d)
+{
+    return CGView<float>{d.f_pdiag, d.f_poff, d.f_x, d.f_r, d.f_p, d.f_q, nullptr, d.ks + 7};
+}
+
 void launch_bicg_iter(const DevCase &d, hipStream_t s)
 {
-    LAUNCH_N(k_bicg_dir, d.N, s, d);
+    const BiView<double> v = bi64(d);
+    LAUNCH_N(k_bicg_dir<double>, d.N, s, d, v);
     prof_begin("bicg_spmv", s);
-    LAUNCH_R(k_bicg_spmv, d.N, s, d);
+    LAUNCH_R(k_bicg_spmv<double>, d.N, s, d, v);
     prof_end("bicg_spmv", s);
-    LAUNCH_R(k_bicg_update, d.N, s, d);
+    LAUNCH_R(k_bicg_update<double>, d.N, s, d, v);
 }
 
 void launch_pcg_init(const DevCase &d, int dic, hipStream_t s)
 {
     LAUNCH_R(k_pcg_sumx, d.N, s, d);
     LAUNCH_R(k_pcg_init, d.N, s, d, dic);
+}
+
+void launch_mx_cvt(const DevCase &d, int kind, hipStream_t s)
+{
+    LAUNCH_N(k_mx_cvt, d.N > d.Fi ? d.N : d.Fi, s, d, kind);
+}
+
+void launch_mx_inner_init(const DevCase &d, int kind, hipStream_t s) { LAUNCH_R(k_mx_inner_init, d.N, s, d, kind); }
+
+void launch_mx_inner_iter(const DevCase &d, int kind, hipStream_t s)
+{
+    if (kind == 1) {
+        const CGView<float> v = cg32(d);
+        prof_begin("pcg32_dir", s);
+        LAUNCH_N(k_cg_dir<float>, d.N, s, d, v);
+        prof_end("pcg32_dir", s);
+        prof_begin("pcg32_spmv", s);
+        LAUNCH_R(k_cg_spmv<float>, d.N, s, d, v);
+        prof_end("pcg32_spmv", s);
+        prof_begin("pcg32_update", s);
+        LAUNCH_R(k_cg_update<float>, d.N, s, d, v, 0);
+        prof_end("pcg32_update", s);
+    } else {
+        const BiView<float> v = bi32(d);
+        LAUNCH_N(k_bicg_dir<float>, d.N, s, d, v);
+        prof_begin("bicg32_spmv", s);
+        LAUNCH_R(k_bicg_spmv<float>, d.N, s, d, v);
+        prof_end("bicg32_spmv", s);
+        LAUNCH_R(k_bicg_update<float>, d.N, s, d, v);
+    }
+}
+
+void launch_mx_correct_resid(const DevCase &d, int kind, hipStream_t s)
+{
+    LAUNCH_N(k_mx_correct, d.N, s, d, kind);
+    LAUNCH_R(k_mx_resid, d.N, s, d, kind);
 }
 
 void launch_dic_precond(const DevCase &d, int with_setup, hipStream_t s)
@@ -1210,14 +1444,15 @@ void launch_init_partials(const DevCase &d, hipStream_t s)
 
 void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s)
 {
+    const CGView<double> v = cg64(d, dic);
     prof_begin("pcg_dir", s);
-    LAUNCH_N(k_pcg_dir, d.N, s, d, dic);
+    LAUNCH_N(k_cg_dir<double>, d.N, s, d, v);
     prof_end("pcg_dir", s);
     prof_begin("pcg_spmv", s);
-    LAUNCH_R(k_pcg_spmv, d.N, s, d);
+    LAUNCH_R(k_cg_spmv<double>, d.N, s, d, v);
     prof_end("pcg_spmv", s);
     prof_begin("pcg_update", s);
-    LAUNCH_R(k_pcg_update, d.N, s, d, dic);
+    LAUNCH_R(k_cg_update<double>, d.N, s, d, v, dic);
     prof_end("pcg_update", s);
     if (dic) launch_dic_precond(d, 0, s);
 }

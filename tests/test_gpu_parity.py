@@ -277,3 +277,53 @@ def test_dic_apply_matches_oracle(shape, perm, rcm):
     bad = np.nonzero(~np.isfinite(zg) | (np.abs(zg - z_o) > 1e-10 * np.abs(z_o).max()))[0]
     _say(f"  z: {bad.size} mismatches; first {bad[:5]} gpu {zg[bad[:5]]} oracle {z_o[bad[:5]]}")
     assert bad.size == 0
+
+
+TOL_MIXED = 1e-6
+
+
+@pytest.mark.parametrize("shape,perm", [((12, 10, 9), 2), ((24, 24, 1), 1)])
+def test_mixed_precision_parity_tight(shape, perm):
+    """FP32 inner / FP64 refinement against the FP64 oracle, both run to an
+    outer normalised residual of 1e-10: agreement within 1e-6."""
+    case = wl.cavity(shape, Re=400.0, dt=0.01, perm_seed=perm, tol=1e-10, precision=wl.MIXED)
+    _say(f"[mixed] cavity {shape}")
+    g = _gpu(case, 5)
+    o = _oracle(case, 5)
+    assert g["st"] == o["st"] == 0
+    _compare(g, o, tol=TOL_MIXED, what="mixed tight")
+
+
+def test_mixed_precision_error_at_benchmark_tolerance():
+    """At the 1e-6 stopping threshold the mixed result is stated, and bounded
+    by what the threshold allows (the FP64 path itself differs from the exact
+    solution by that much)."""
+    case = wl.cavity((16, 16, 16), Re=1000.0, dt=0.001, tol=1e-6, precision=wl.MIXED)
+    g = _gpu(case, 5)
+    o = _oracle(case, 5)
+    eU, ep = _rel(g["U"], o["U"]), _rel(g["p"], o["p"])
+    _say(f"  mixed at tol 1e-6: relL2 U {eU:.2e} p {ep:.2e}; p iters gpu {_counts(g['info'])} oracle {_counts(o['info'])}")
+    assert eU <= 1e-4 and ep <= 1e-3
+
+
+def test_mixed_solve_pressure_and_simple():
+    import torch
+    from paper_1207_1571_amd import fvm
+    case = wl.cavity((15, 13, 9), Re=100.0, dt=0.01, perm_seed=6, tol=1e-10, precision=wl.MIXED)
+    rng = np.random.default_rng(0)
+    m = case.mesh
+    gamma = rng.uniform(0.5, 2.0, m.n_faces)
+    rhs = rng.normal(size=m.n_cells); rhs -= rhs.mean()
+    po = np.zeros(m.n_cells)
+    orc.OracleCase(case).solve_pressure(gamma, rhs, po, 1e-11)
+    c = fvm.Case(case)
+    pg = torch.zeros(m.n_cells, dtype=torch.float64, device="cuda")
+    st, info = c.solve_pressure(torch.from_numpy(gamma).cuda(), torch.from_numpy(rhs).cuda(), pg, 1e-11)
+    _say(f"  mixed solve_pressure: {info}")
+    assert st == 0 and info["res_final"] <= 1e-11
+    assert _rel(pg.cpu().numpy(), po) <= TOL_MIXED
+    sc = wl.duct256((24, 6, 6)).with_(p_ctl=wl.SolverCtl(1e-11, 0.0), u_ctl=wl.SolverCtl(1e-11, 0.0),
+                                      precision=wl.MIXED)
+    g = _gpu(sc, 8, simple=True, res_tol=0.0)
+    o = _oracle(sc, 8, simple=True, res_tol=0.0)
+    _compare(g, o, tol=TOL_MIXED, what="mixed SIMPLE")
