@@ -52,6 +52,10 @@ def algorithmic_bytes(cls: str, N: int, Fi: int, dic: bool) -> float:
         "dic_bwd": 32 * N + 16 * Fi,               # y, D*, r, z out; upper faces
         "dic_setup": 16 * N + 16 * Fi,             # diag, D* out; lower faces
         "bicg_spmv": 104 * N + 24 * Fi,            # 3 components, A and A^T
+        "pcg32_spmv": 12 * N + 12 * Fi,            # FP32 inner: diag, x, y + coefficient + 2 int32
+        "pcg32_update": 28 * N,
+        "pcg32_dir": 16 * N,
+        "bicg32_spmv": 52 * N + 16 * Fi,
         "mom_face": 32 * Fi,                       # phi, w, dl in; upper, lower out
         "mom_cell": 136 * N + 40 * Fi,
         "hbya": 104 * N + 24 * Fi,
@@ -64,7 +68,74 @@ def algorithmic_bytes(cls: str, N: int, Fi: int, dic: bool) -> float:
 
 
 KERNEL_CLASSES = ["pcg_spmv", "pcg_update", "pcg_dir", "dic_setup", "dic_fwd", "dic_bwd", "bicg_spmv", "mom_face",
-                  "mom_cell", "hbya", "p_face", "p_cell", "flux_corr", "U_corr"]
+                  "mom_cell", "hbya", "p_face", "p_cell", "flux_corr", "U_corr", "pcg32_spmv", "pcg32_update",
+                  "pcg32_dir", "bicg32_spmv"]
+
+
+def profile_classes(fvm, case, steps, N, Fi, dic):
+    """Per-class device time of `steps` PISO steps (HIP events per launch)."""
+    import torch
+    fvm.profile_enable(True)
+    case.piso(steps)
+    torch.cuda.synchronize()
+    out = {}
+    for cls in KERNEL_CLASSES:
+        ms, n = fvm.profile_read(cls)
+        if n == 0:
+            continue
+        mean_us = 1e3 * ms / n
+        b = algorithmic_bytes(cls, N, Fi, dic)
+        out[cls] = dict(total_ms=round(ms, 4), launches=n, mean_us=round(mean_us, 3),
+                        alg_GBps=round(b / (mean_us * 1e-6) / 1e9, 1) if b and mean_us > 0 else None)
+    fvm.profile_enable(False)
+    return out
+
+
+def cav200_section(fvm, wl, steps, log):
+    """200^3 cavity, FP64 and mixed (FP32 inner + FP64 refinement), `steps`
+    PISO steps each from rest: time per step, pressure iterations, SpMV and
+    CG-iteration bandwidth, and the mixed-vs-FP64 field difference."""
+    import numpy as np
+    import torch
+    t = time.perf_counter()
+    spec = wl.cav200(n=200, n_steps=steps)
+    mesh = fvm.Mesh(spec.mesh, spec.bcs)
+    N, Fi = mesh.n_cells, mesh.n_internal
+    log(f"cav200 mesh: {N} cells in {time.perf_counter() - t:.1f}s")
+    res = {}
+    fields = {}
+    for name, prec in (("fp64", wl.FP64), ("mixed", wl.MIXED)):
+        sp = spec.with_(precision=prec)
+        c = fvm.Case(sp, mesh=mesh)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p_iters = 0
+        for _ in range(steps):
+            st, info = c.piso(1)
+            p_iters += sum(s["iters"] for s in info["p"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fields[name] = c.get_state_numpy()
+        del c
+        pc = fvm.Case(sp, mesh=mesh)
+        k = profile_classes(fvm, pc, 2, N, Fi, False)
+        del pc
+        pre = "pcg32" if prec == wl.MIXED else "pcg"
+        it_us = sum(k[c]["mean_us"] for c in (pre + "_dir", pre + "_spmv", pre + "_update") if c in k)
+        it_bytes = (112 * N + 16 * Fi) if prec == wl.FP64 else (56 * N + 12 * Fi)
+        res[name] = dict(ms_per_step=round(1e3 * wall / steps, 2), cell_updates_per_s=round(N * steps / wall, 1),
+                         p_iters_total=p_iters, ms_per_p_solve=round(1e3 * wall / (2 * steps), 2),
+                         spmv_GBps=k.get(pre + "_spmv", {}).get("alg_GBps"),
+                         spmv_mean_us=k.get(pre + "_spmv", {}).get("mean_us"),
+                         cg_iter_us=round(it_us, 2), cg_iter_GBps=round(it_bytes / (it_us * 1e-6) / 1e9, 1) if it_us else None,
+                         kernels=k)
+        log(f"cav200 {name}: {res[name]['ms_per_step']} ms/step, p iters {p_iters}, SpMV {res[name]['spmv_GBps']} GB/s, "
+            f"CG iteration {res[name]['cg_iter_GBps']} GB/s")
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    res["mixed_vs_fp64_relL2"] = dict(U=rel(fields["mixed"][0], fields["fp64"][0]), p=rel(fields["mixed"][1], fields["fp64"][1]))
+    res["workload"] = (f"cav200: 3-D lid-driven cavity 200^3 hex cells, lexicographic, Re=1000, PISO dt=0.001, "
+                       f"{steps} steps, PCG-Jacobi / PBiCG-Jacobi tol 1e-6; mixed = FP32 inner (eta 1e-3) + FP64 refinement")
+    return res
 
 
 def main():
@@ -75,6 +146,7 @@ def main():
     ap.add_argument("--n", type=int, default=100, help="cube side (100 = the benchmark configuration)")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cav200-steps", type=int, default=20, help="steps of the 200^3 FP64-vs-mixed section (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for memory counters)")
     args = ap.parse_args()
@@ -133,20 +205,11 @@ def main():
     kernels = {}
     if args.profile_steps > 0:
         pc = fvm.Case(spec, mesh=mesh)
-        fvm.profile_enable(True)
-        pc.piso(args.profile_steps)
-        torch.cuda.synchronize()
-        for cls in KERNEL_CLASSES:
-            ms, n = fvm.profile_read(cls)
-            if n == 0:
-                continue
-            mean_us = 1e3 * ms / n
-            b = algorithmic_bytes(cls, N, Fi, spec.p_ctl.precond == wl.PC_DIC)
-            kernels[cls] = dict(total_ms=round(ms, 4), launches=n, mean_us=round(mean_us, 3),
-                                alg_GBps=round(b / (mean_us * 1e-6) / 1e9, 1) if b and mean_us > 0 else None)
-        fvm.profile_enable(False)
+        kernels = profile_classes(fvm, pc, args.profile_steps, N, Fi, spec.p_ctl.precond == wl.PC_DIC)
         del pc
         log("kernel classes: " + json.dumps(kernels))
+    del mesh
+    cav200 = cav200_section(fvm, wl, args.cav200_steps, log) if args.cav200_steps > 0 else None
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
     roofline = None
     if dom:
@@ -183,6 +246,7 @@ def main():
                                f"(seed 2) + RCM, Re=400, PISO dt=0.002, 2 correctors, PCG-DIC / PBiCG tol 1e-7",
                    "cells": N, "internal_faces": Fi, "precision": "fp64"},
         "pcg_spmv_GBps": spmv["alg_GBps"] if spmv else None,
+        "cav200": cav200,
         "p_iters_last_step": p_iters_last,
         "roofline": roofline,
         "kernels": kernels,

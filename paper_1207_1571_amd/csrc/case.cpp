@@ -153,7 +153,13 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
     std::memset(&d, 0, sizeof(d));
     d.N = m.N; d.F = m.F; d.Fi = m.Fi; d.Fb = m.Fb; d.npatch = m.npatch;
     d.nonorth = no; d.has_fixed_p = m.has_fixed_p; d.pin_cell = o.p_ref_cell;
+    d.nu = o.nu; d.dt = o.dt; d.alpha_u = o.alpha_u; d.alpha_p = o.alpha_p; d.p_ref = o.p_ref_value;
+    d.inner_rel_tol = o.inner_rel_tol; d.inner_max_iter = o.inner_max_iter;
+    d.upwind = o.convection == FVM_CONV_UPWIND;
+    d.u_tol = o.u_ctl.tol; d.u_rel_tol = o.u_ctl.rel_tol; d.u_max_iter = o.u_ctl.max_iter;
+    d.p_tol = o.p_ctl.tol; d.p_rel_tol = o.p_ctl.rel_tol; d.p_max_iter = o.p_ctl.max_iter;
     d.n_levels = (int32_t)m.lvl_start.size() - 1;
+    d.self = b.take<DevCase>(1);
     d.own = b.take<int32_t>(F); d.nei = b.take<int32_t>(Fi);
     d.own_start = b.take<int32_t>(N + 1); d.nbr_start = b.take<int32_t>(N + 1); d.losort = b.take<int32_t>(Fi);
     d.bnd_start = b.take<int32_t>(N + 1); d.bnd_list = b.take<int32_t>(Fb); d.bpatch = b.take<int32_t>(Fb);
@@ -185,15 +191,19 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
     }
     if (mixed) {
         d.f_diag = b.take<float>(N); d.f_up = b.take<float>(Fi); d.f_lo = b.take<float>(Fi);
-        d.f_pdiag = b.take<float>(N); d.f_poff = b.take<float>(Fi);
-        d.f_x = b.take<float>(3 * N); d.f_b = b.take<float>(3 * N); d.f_r = b.take<float>(3 * N);
+        d.f_pdiag = b.take<float>(N); d.f_poff = b.take<float>(Fi); d.f_pexc = b.take<float>(N);
+        d.f_x = b.take<float>(3 * N); d.f_r = b.take<float>(3 * N);
         d.f_rt = b.take<float>(3 * N); d.f_p = b.take<float>(3 * N); d.f_pt = b.take<float>(3 * N);
         d.f_q = b.take<float>(3 * N); d.f_qt = b.take<float>(3 * N);
     }
-    d.red_stride = std::max<int32_t>(kMaxGrid, (int32_t)((N + kBlock - 1) / kBlock));
+    d.red_stride = (int32_t)(((N + kBlock - 1) / kBlock + 7) / 8 * 8);
+    d.red_stride2 = (d.red_stride + kGroup - 1) / kGroup;
     d.partials = b.take<double>((size_t)kMaxRed * d.red_stride);
+    d.partials2 = b.take<double>((size_t)kMaxRed * d.red_stride2);
+    d.gticket = b.take<unsigned int>((size_t)d.red_stride2);
     d.ticket = b.take<unsigned int>(64);
     d.ks = b.take<KState>(kNumKs);
+    d.ks_gather = b.take<KState>((size_t)kMaxBatch * kNumKs);
     b.off = (b.off + 255) / 256 * 256;
 }
 
@@ -222,21 +232,79 @@ fvm_status check_opts(const fvm_mesh *m, const fvm_case_opts *o)
 
 constexpr int kRing = 4;
 
+// Pinned ring of Krylov-state copies (kMaxBatch cases x kNumKs states per
+// slot) with one event per slot: the host inspects the copy of chunk k while
+// chunk k+1 runs.
+struct Poller {
+    KState *h = nullptr;
+    hipEvent_t ev[kRing];
+    bool pending[kRing] = {false, false, false, false};
+    int ring = 0;
+    bool ok = false;
+    fvm_status init()
+    {
+        if (ok) return FVM_OK;
+        if (hipHostMalloc((void **)&h, sizeof(KState) * kMaxBatch * kNumKs * kRing, hipHostMallocDefault) != hipSuccess)
+            return fvm_fail(FVM_EDEVICE, "poller: pinned host buffer");
+        for (int k = 0; k < kRing; ++k)
+            if (hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess)
+                return fvm_fail(FVM_EDEVICE, "poller: event");
+        ok = true;
+        return FVM_OK;
+    }
+    void release()
+    {
+        if (!ok) return;
+        for (int k = 0; k < kRing; ++k) {
+            if (pending[k]) (void)hipEventSynchronize(ev[k]);
+            (void)hipEventDestroy(ev[k]);
+        }
+        (void)hipHostFree(h);
+        ok = false;
+    }
+    KState *slot_ptr(int slot) { return h + (size_t)slot * kMaxBatch * kNumKs; }
+};
+
 }  // namespace
 
 struct fvm_case {
     fvm_case_opts o;
-    DevCase d;
+    DevCase d;                      // host copy; d.self is the device copy
     int32_t N, F, Fi, Fb, npatch;
     bool nonorth, has_fixed_p;
     std::vector<fvm_patch> patches;
-    // Krylov state mirror: a ring of pinned host copies, one per chunk
-    KState *hks = nullptr;          // [kRing][kNumKs]
-    hipEvent_t ev[kRing];
-    bool ev_pending[kRing];
-    int ring = 0;
-    int last_iters[4] = {0, 0, 0, 0};   // momentum, pressure, and their inner solves: chunk sizing
+    Poller poll;
+    int last_iters[4] = {0, 0, 0, 0};   // momentum, pressure, momentum inner; chunk sizing
 };
+
+namespace {
+
+// a group of resident cases advanced by shared launches
+struct Group {
+    std::vector<fvm_case *> cs;
+    BatchSet bs;
+    Poller *poll;
+    hipStream_t s;
+    explicit Group(fvm_case *c, hipStream_t st) : poll(&c->poll), s(st)
+    {
+        cs.push_back(c);
+        bs.n = 0;
+        batch_add(bs, c->d.self, &c->d);
+    }
+    Group(fvm_case *const *c, int n, Poller *p, hipStream_t st) : poll(p), s(st)
+    {
+        bs.n = 0;
+        for (int i = 0; i < n; ++i) {
+            cs.push_back(c[i]);
+            batch_add(bs, c[i]->d.self, &c[i]->d);
+        }
+    }
+    int n() const { return (int)cs.size(); }
+};
+
+thread_local Poller t_batch_poll;
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // public: workspace size, create, destroy
@@ -260,24 +328,6 @@ hipError_t up(T *dst, const std::vector<T> &src, hipStream_t s)
     if (src.empty()) return hipSuccess;
     return hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s);
 }
-
-fvm_status upload_patches(fvm_case *c, hipStream_t s)
-{
-    const int np = c->npatch;
-    if (np == 0) return FVM_OK;
-    std::vector<int32_t> uk(np), pk(np);
-    std::vector<double> uv(3 * (size_t)np), pv(np);
-    for (int p = 0; p < np; ++p) {
-        uk[p] = c->patches[p].u_kind; pk[p] = c->patches[p].p_kind; pv[p] = c->patches[p].p_value;
-        for (int k = 0; k < 3; ++k) uv[3 * p + k] = c->patches[p].u_value[k];
-    }
-    HIPCHK(up(c->d.patch_uk, uk, s));
-    HIPCHK(up(c->d.patch_pk, pk, s));
-    HIPCHK(up(c->d.patch_uv, uv, s));
-    HIPCHK(up(c->d.patch_pv, pv, s));
-    HIPCHK(hipStreamSynchronize(s));    // the host vectors above are temporaries
-    return FVM_OK;
-}
 }  // namespace
 
 extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o, void *ws, size_t bytes, void *stream,
@@ -290,7 +340,8 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return fvm_fail(FVM_EINVAL, "case: workspace must be 256-byte aligned");
     size_t need = 0;
     fvm_case_workspace_bytes(m, o, &need);
-    if (bytes < need) return fvm_fail(FVM_ENOMEM, "case: workspace too small (" + std::to_string(bytes) + " < " + std::to_string(need) + ")");
+    if (bytes < need)
+        return fvm_fail(FVM_ENOMEM, "case: workspace too small (" + std::to_string(bytes) + " < " + std::to_string(need) + ")");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     fvm_case *c = new (std::nothrow) fvm_case();
     if (!c) return fvm_fail(FVM_ENOMEM, "case: out of host memory");
@@ -301,24 +352,28 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     Bump b{reinterpret_cast<char *>(ws)};
     plan(*m, *o, b, c->d);
     auto fail = [&](fvm_status code) {
-        if (c->hks) (void)hipHostFree(c->hks);
+        c->poll.release();
         delete c;
         return code;
     };
-    if (hipHostMalloc((void **)&c->hks, sizeof(KState) * kNumKs * kRing, hipHostMallocDefault) != hipSuccess)
-        return fail(fvm_fail(FVM_EDEVICE, "case: pinned host buffer"));
-    for (int k = 0; k < kRing; ++k) {
-        c->ev_pending[k] = false;
-        if (hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming) != hipSuccess)
-            return fail(fvm_fail(FVM_EDEVICE, "case: event"));
-    }
+    st = c->poll.init();
+    if (st != FVM_OK) return fail(st);
     DevCase &d = c->d;
-    const size_t N = m->N, F = m->F;
+    const int np = c->npatch;
+    std::vector<int32_t> uk(np), pk(np);
+    std::vector<double> uv(3 * (size_t)np), pv(np);
+    for (int p = 0; p < np; ++p) {
+        uk[p] = c->patches[p].u_kind; pk[p] = c->patches[p].p_kind; pv[p] = c->patches[p].p_value;
+        for (int k = 0; k < 3; ++k) uv[3 * p + k] = c->patches[p].u_value[k];
+    }
+    const size_t F = m->F;
 #define UPCHK(x) do { if ((x) != hipSuccess) return fail(fvm_fail(FVM_EDEVICE, "case: upload " #x)); } while (0)
+    UPCHK(hipMemcpyAsync(d.self, &c->d, sizeof(DevCase), hipMemcpyHostToDevice, s));
     UPCHK(up(d.own, m->own, s)); UPCHK(up(d.nei, m->nei, s));
     UPCHK(up(d.own_start, m->own_start, s)); UPCHK(up(d.nbr_start, m->nbr_start, s)); UPCHK(up(d.losort, m->losort, s));
     UPCHK(up(d.bnd_start, m->bnd_start, s)); UPCHK(up(d.bnd_list, m->bnd_list, s)); UPCHK(up(d.bpatch, m->bpatch, s));
     UPCHK(up(d.face_user, m->face_user, s)); UPCHK(up(d.face_sign, m->face_sign, s));
+    UPCHK(up(d.patch_uk, uk, s)); UPCHK(up(d.patch_pk, pk, s)); UPCHK(up(d.patch_uv, uv, s)); UPCHK(up(d.patch_pv, pv, s));
     UPCHK(hipMemcpyAsync(d.Sx, m->S.data(), sizeof(double) * F, hipMemcpyHostToDevice, s));
     UPCHK(hipMemcpyAsync(d.Sy, m->S.data() + F, sizeof(double) * F, hipMemcpyHostToDevice, s));
     UPCHK(hipMemcpyAsync(d.Sz, m->S.data() + 2 * F, sizeof(double) * F, hipMemcpyHostToDevice, s));
@@ -327,16 +382,16 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     UPCHK(up(d.tmpCf, m->Cf, s));
     if (d.lvl_start) { UPCHK(up(d.lvl_start, m->lvl_start, s)); UPCHK(up(d.lvl_cells, m->lvl_cells, s)); }
     UPCHK(hipMemsetAsync(d.ticket, 0, 64 * sizeof(unsigned int), s));
+    UPCHK(hipMemsetAsync(d.gticket, 0, d.red_stride2 * sizeof(unsigned int), s));
     UPCHK(hipMemsetAsync(d.ks, 0, kNumKs * sizeof(KState), s));
-    st = upload_patches(c, s);
-    if (st != FVM_OK) return fail(st);
-    launch_init_partials(d, s);
-    launch_geometry(d, s);
-    UPCHK(hipMemsetAsync(d.U, 0, 3 * N * sizeof(double), s));
-    UPCHK(hipMemsetAsync(d.p, 0, N * sizeof(double), s));
-    launch_flux_from_U(d, s);
+    const Group g(c, s);
+    launch_init_partials(g.bs, s);
+    launch_geometry(g.bs, s);
+    UPCHK(hipMemsetAsync(d.U, 0, 3 * (size_t)m->N * sizeof(double), s));
+    UPCHK(hipMemsetAsync(d.p, 0, (size_t)m->N * sizeof(double), s));
+    launch_flux_from_U(g.bs, s);
     UPCHK(hipGetLastError());
-    UPCHK(hipStreamSynchronize(s));   // the mesh vectors may be freed by the caller after return
+    UPCHK(hipStreamSynchronize(s));   // host vectors above are temporaries
 #undef UPCHK
     *out = c;
     return FVM_OK;
@@ -345,8 +400,7 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
 extern "C" void fvm_case_destroy(fvm_case *c)
 {
     if (!c) return;
-    for (int k = 0; k < kRing; ++k) (void)hipEventDestroy(c->ev[k]);
-    if (c->hks) (void)hipHostFree(c->hks);
+    c->poll.release();
     delete c;
 }
 
@@ -357,10 +411,11 @@ extern "C" fvm_status fvm_case_set_state(fvm_case *c, const double *U, const dou
 {
     if (!c) return fvm_fail(FVM_EINVAL, "case: null handle");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (U) launch_U_in(c->d, U, s);
+    const Group g(c, s);
+    if (U) launch_U_in(g.bs, U, s);
     if (p) HIPCHK(hipMemcpyAsync(c->d.p, p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    if (phi) launch_phi_in(c->d, phi, s);
-    else launch_flux_from_U(c->d, s);
+    if (phi) launch_phi_in(g.bs, phi, s);
+    else launch_flux_from_U(g.bs, s);
     HIPCHK(hipGetLastError());
     return FVM_OK;
 }
@@ -369,9 +424,10 @@ extern "C" fvm_status fvm_case_get_state(const fvm_case *c, double *U, double *p
 {
     if (!c) return fvm_fail(FVM_EINVAL, "case: null handle");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (U) launch_U_out(c->d, U, s);
+    const Group g(const_cast<fvm_case *>(c), s);
+    if (U) launch_U_out(g.bs, U, s);
     if (p) HIPCHK(hipMemcpyAsync(p, c->d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    if (phi) launch_phi_out(c->d, phi, s);
+    if (phi) launch_phi_out(g.bs, phi, s);
     HIPCHK(hipGetLastError());
     return FVM_OK;
 }
@@ -384,133 +440,188 @@ extern "C" fvm_status fvm_case_set_patch_value(fvm_case *c, int32_t patch, const
     for (int k = 0; k < 3; ++k) c->patches[patch].u_value[k] = u_value[k];
     c->patches[patch].p_value = p_value;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    launch_set_patch(c->d, patch, u_value[0], u_value[1], u_value[2], p_value, s);
+    const Group g(c, s);
+    launch_set_patch(g.bs, patch, u_value[0], u_value[1], u_value[2], p_value, s);
     HIPCHK(hipGetLastError());
     return FVM_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Krylov drivers
+// Krylov drivers (over a group of cases)
 // ---------------------------------------------------------------------------
 namespace {
 
-struct SolveOut {
-    KState ks[4];
-};
-
-// Enqueue iterations in chunks until the systems [first, first+count) are
-// done; the Krylov state array after the last chunk is returned in res.
-// launch_iter enqueues one iteration.  `predicted` sizes the first chunk.
-template <class F>
-fvm_status iterate_until_done(fvm_case *c, int first, int count, int predicted, long limit, hipStream_t s,
-                              F launch_iter, KState *res)
+// copy every case's states into the poller slot (one gather kernel + one
+// D2H copy); returns the slot index
+fvm_status enqueue_states(Group &g, int &slot_out)
 {
-    const DevCase &d = c->d;
+    Poller &P = *g.poll;
+    const int slot = P.ring;
+    P.ring = (P.ring + 1) % kRing;
+    if (P.pending[slot]) {
+        HIPCHK(hipEventSynchronize(P.ev[slot]));
+        P.pending[slot] = false;
+    }
+    const DevCase &lead = g.cs[0]->d;
+    if (g.n() == 1) {
+        HIPCHK(hipMemcpyAsync(P.slot_ptr(slot), lead.ks, kNumKs * sizeof(KState), hipMemcpyDeviceToHost, g.s));
+    } else {
+        launch_gather_ks(g.bs, g.s);
+        HIPCHK(hipMemcpyAsync(P.slot_ptr(slot), lead.ks_gather, (size_t)g.n() * kNumKs * sizeof(KState),
+                              hipMemcpyDeviceToHost, g.s));
+    }
+    HIPCHK(hipEventRecord(P.ev[slot], g.s));
+    P.pending[slot] = true;
+    slot_out = slot;
+    return FVM_OK;
+}
+
+fvm_status wait_slot(Group &g, int slot)
+{
+    HIPCHK(hipEventSynchronize(g.poll->ev[slot]));
+    g.poll->pending[slot] = false;
+    return FVM_OK;
+}
+
+// state k of case i in a slot
+inline const KState &st_of(Group &g, int slot, int i, int k) { return g.poll->slot_ptr(slot)[(size_t)i * kNumKs + k]; }
+
+// Enqueue iterations in chunks until the systems [first, first+count) of
+// every case are finished (done == 1; 2 means paused for a device-side
+// check); res[i*kNumKs + k] receives the final states.  launch_iter
+// enqueues one iteration; `predicted` sizes the first chunk.
+template <class F>
+fvm_status iterate_until_done(Group &g, int first, int count, int predicted, long limit, F launch_iter,
+                              std::vector<KState> &res)
+{
     int chunk = predicted > 0 ? std::max(2, predicted - predicted / 4) : 4;
     long issued = 0;
-    int prev_slot = -1;
-    auto all_done = [&](const KState *h) {
-        for (int k = 0; k < count; ++k)
-            if (!h[first + k].done) return false;
+    int prev = -1;
+    auto all_done = [&](int slot) {
+        for (int i = 0; i < g.n(); ++i)
+            for (int k = 0; k < count; ++k)
+                if (st_of(g, slot, i, first + k).done != 1) return false;
         return true;
+    };
+    auto take = [&](int slot) {
+        res.assign(g.poll->slot_ptr(slot), g.poll->slot_ptr(slot) + (size_t)g.n() * kNumKs);
     };
     for (;;) {
         const int n = (int)std::min<long>(chunk, std::max<long>(1, limit - issued));
         for (int k = 0; k < n; ++k) launch_iter();
         issued += n;
         HIPCHK(hipGetLastError());
-        const int slot = c->ring;
-        c->ring = (c->ring + 1) % kRing;
-        if (c->ev_pending[slot]) {
-            HIPCHK(hipEventSynchronize(c->ev[slot]));
-            c->ev_pending[slot] = false;
-        }
-        HIPCHK(hipMemcpyAsync(c->hks + kNumKs * slot, d.ks, kNumKs * sizeof(KState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(c->ev[slot], s));
-        c->ev_pending[slot] = true;
-        // inspect the previous chunk while this one runs
-        if (prev_slot >= 0) {
-            HIPCHK(hipEventSynchronize(c->ev[prev_slot]));
-            c->ev_pending[prev_slot] = false;
-            if (all_done(c->hks + kNumKs * prev_slot)) {
-                std::memcpy(res, c->hks + kNumKs * prev_slot, kNumKs * sizeof(KState));
+        int slot;
+        fvm_status st = enqueue_states(g, slot);
+        if (st != FVM_OK) return st;
+        if (prev >= 0) {
+            st = wait_slot(g, prev);
+            if (st != FVM_OK) return st;
+            if (all_done(prev)) {
+                take(prev);
                 return FVM_OK;
             }
         }
         if (issued >= limit) {
-            HIPCHK(hipEventSynchronize(c->ev[slot]));
-            c->ev_pending[slot] = false;
-            std::memcpy(res, c->hks + kNumKs * slot, kNumKs * sizeof(KState));
-            if (!all_done(res)) return fvm_fail(FVM_EDEVICE, "solve: iteration limit passed without a stop flag");
+            st = wait_slot(g, slot);
+            if (st != FVM_OK) return st;
+            if (!all_done(slot)) return fvm_fail(FVM_EDEVICE, "solve: iteration limit passed without a stop flag");
+            take(slot);
             return FVM_OK;
         }
-        prev_slot = slot;
+        prev = slot;
         chunk = predicted > 0 ? std::max(2, predicted / 8) : std::min(64, chunk * 2);
     }
 }
 
-// synchronous copy of the Krylov states (once per outer refinement step)
-fvm_status snapshot(fvm_case *c, hipStream_t s, KState *res)
+fvm_status snapshot(Group &g, std::vector<KState> &res)
 {
-    const int slot = c->ring;
-    c->ring = (c->ring + 1) % kRing;
-    if (c->ev_pending[slot]) {
-        HIPCHK(hipEventSynchronize(c->ev[slot]));
-        c->ev_pending[slot] = false;
-    }
-    HIPCHK(hipMemcpyAsync(c->hks + kNumKs * slot, c->d.ks, kNumKs * sizeof(KState), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipEventRecord(c->ev[slot], s));
-    HIPCHK(hipEventSynchronize(c->ev[slot]));
-    std::memcpy(res, c->hks + kNumKs * slot, kNumKs * sizeof(KState));
+    int slot;
+    fvm_status st = enqueue_states(g, slot);
+    if (st != FVM_OK) return st;
+    st = wait_slot(g, slot);
+    if (st != FVM_OK) return st;
+    res.assign(g.poll->slot_ptr(slot), g.poll->slot_ptr(slot) + (size_t)g.n() * kNumKs);
     return FVM_OK;
 }
 
-// Enqueue one solve and return its final scalars.  kind 0: momentum BiCG
-// (systems 0..2), kind 1: pressure CG (system 3).  FVM_MIXED cases run the
-// FP64 refinement loop around FP32 inner solves (systems 4..7).
-fvm_status run_solve(fvm_case *c, int kind, const fvm_solver_ctl &ctl, hipStream_t s, KState *final_state)
+int predicted_iters(Group &g, int slot)
 {
-    const DevCase &d = c->d;
+    int m = 0;
+    for (auto *c : g.cs) m = std::max(m, c->last_iters[slot]);
+    return m;
+}
+
+void record_iters(Group &g, const std::vector<KState> &res, int first, int count, int slot)
+{
+    for (int i = 0; i < g.n(); ++i) {
+        int m = 0;
+        for (int k = 0; k < count; ++k) m = std::max(m, res[(size_t)i * kNumKs + first + k].iters);
+        g.cs[i]->last_iters[slot] = m;
+    }
+}
+
+// One solve for every case of the group.  kind 0: momentum BiCG (systems
+// 0..2), kind 1: pressure CG (system 3).  ctl_src selects the controls:
+// 0/1 = the cases' own momentum / pressure controls, 2 = *ctl.
+// FVM_MIXED cases run the mixed-precision variants.
+fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl, std::vector<KState> &res)
+{
+    const BatchSet &bs = g.bs;
+    hipStream_t s = g.s;
+    fvm_case *c0 = g.cs[0];
     const int first = kind == 0 ? 0 : 3, count = kind == 0 ? 3 : 1;
-    const int dic = kind == 1 && ctl.precond == FVM_PC_DIC;
-    const bool mixed = c->o.precision == FVM_MIXED;
-    launch_set_ctl(d, first, count, ctl.tol, ctl.rel_tol, ctl.max_iter, s);
-    if (kind == 0) launch_bicg_init(d, s);
-    else launch_pcg_init(d, dic, s);
-    KState res[kNumKs];
+    const int precond = ctl_src == 2 ? ctl->precond : c0->o.p_ctl.precond;
+    const int dic = kind == 1 && precond == FVM_PC_DIC;
+    const bool mixed = c0->o.precision == FVM_MIXED;
+    long max_iter = 0;
+    for (auto *c : g.cs)
+        max_iter = std::max<long>(max_iter, ctl_src == 2 ? ctl->max_iter : kind == 0 ? c->o.u_ctl.max_iter : c->o.p_ctl.max_iter);
+    launch_set_ctl(bs, first, count, ctl_src, ctl ? ctl->tol : 0.0, ctl ? ctl->rel_tol : 0.0, ctl ? ctl->max_iter : 0, s);
+    if (kind == 0) launch_bicg_init(bs, s);
+    else launch_pcg_init(bs, dic, s);
     fvm_status st;
     if (!mixed) {
-        if (dic) launch_dic_precond(d, 1, s);
-        st = iterate_until_done(c, first, count, c->last_iters[kind], (long)ctl.max_iter + 1, s, [&] {
-            if (kind == 0) launch_bicg_iter(d, s);
-            else launch_pcg_iter(d, dic, s);
+        if (dic) launch_dic_precond(bs, 1, s);
+        st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 1, [&] {
+            if (kind == 0) launch_bicg_iter(bs, s);
+            else launch_pcg_iter(bs, dic, s);
+        }, res);
+        if (st != FVM_OK) return st;
+    } else if (kind == 1) {
+        // FP32 CG recurrence, FP64 solution; the replacement kernel follows
+        // every iteration and does nothing unless the device state asks for
+        // a replacement (paused at the tolerance or the iteration limit, or
+        // the recurrence residual fell 10x since the last one)
+        launch_rr_start(bs, s);
+        st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 2, [&] {
+            launch_rr_iter(bs, s);
+            launch_rr_replace(bs, s);
         }, res);
         if (st != FVM_OK) return st;
     } else {
-        const int ifirst = kind == 0 ? 4 : 7;
-        launch_set_ctl(d, ifirst, count, 0.0, c->o.inner_rel_tol, c->o.inner_max_iter, s);
-        launch_mx_cvt(d, kind, s);
+        // momentum: FP64 refinement around restarted FP32 BiCG solves
+        long inner_max = 0;
+        for (auto *c : g.cs) inner_max = std::max<long>(inner_max, c->o.inner_max_iter);
+        launch_set_ctl(bs, 4, 3, 3, 0.0, 0.0, 0, s);
+        launch_mx_cvt(bs, 0, s);
         for (int outer = 0;; ++outer) {
-            st = snapshot(c, s, res);
+            st = snapshot(g, res);
             if (st != FVM_OK) return st;
             bool all = true;
-            for (int k = 0; k < count; ++k) all = all && res[first + k].done;
+            for (int i = 0; i < g.n(); ++i)
+                for (int k = 0; k < 3; ++k) all = all && res[(size_t)i * kNumKs + k].done == 1;
             if (all) break;
             if (outer >= 1000) return fvm_fail(FVM_EDEVICE, "solve: refinement did not terminate");
-            launch_mx_inner_init(d, kind, s);
-            st = iterate_until_done(c, ifirst, count, c->last_iters[2 + kind], (long)c->o.inner_max_iter + 1, s,
-                                    [&] { launch_mx_inner_iter(d, kind, s); }, res);
+            launch_mx_inner_init(bs, 0, s);
+            st = iterate_until_done(g, 4, 3, predicted_iters(g, 2), inner_max + 1,
+                                    [&] { launch_mx_inner_iter(bs, 0, s); }, res);
             if (st != FVM_OK) return st;
-            int mi = 0;
-            for (int k = 0; k < count; ++k) mi = std::max(mi, res[ifirst + k].iters);
-            c->last_iters[2 + kind] = mi;
-            launch_mx_correct_resid(d, kind, s);
+            record_iters(g, res, 4, 3, 2);
+            launch_mx_correct_resid(bs, 0, s);
         }
     }
-    int mx = 0;
-    for (int k = 0; k < count; ++k) mx = std::max(mx, res[first + k].iters);
-    c->last_iters[kind] = mx;
-    for (int k = 0; k < count; ++k) final_state[k] = res[first + k];
+    record_iters(g, res, first, count, kind);
     return FVM_OK;
 }
 
@@ -528,92 +639,97 @@ void worst(int32_t &acc, int32_t s)
     else if (acc >= 0 && s > acc) acc = s;
 }
 
-fvm_status save_state(fvm_case *c, hipStream_t s)
+// momentum matrix + predictor solve; mode 0 PISO, 1 SIMPLE
+fvm_status momentum_predictor(Group &g, int mode, std::vector<fvm_step_info> &info)
 {
-    const DevCase &d = c->d;
-    HIPCHK(hipMemcpyAsync(d.U_save, d.U, 3 * sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(d.p_save, d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(d.phi_save, d.phi, sizeof(double) * c->F, hipMemcpyDeviceToDevice, s));
-    return FVM_OK;
-}
-
-fvm_status restore_state(fvm_case *c, hipStream_t s)
-{
-    const DevCase &d = c->d;
-    HIPCHK(hipMemcpyAsync(d.U, d.U_save, 3 * sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(d.p, d.p_save, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(d.phi, d.phi_save, sizeof(double) * c->F, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return FVM_OK;
-}
-
-// momentum matrix + predictor solve; dt > 0 transient, alpha_u < 1 relaxed
-fvm_status momentum_predictor(fvm_case *c, double dt, double alpha_u, hipStream_t s, fvm_step_info &info)
-{
-    const DevCase &d = c->d;
-    const int upwind = c->o.convection == FVM_CONV_UPWIND;
-    if (c->nonorth) launch_gradU(d, s);
-    launch_mom_face(d, c->o.nu, upwind, s);
-    launch_mom_cell(d, c->o.nu, dt, alpha_u, upwind, s);
-    KState ks[3];
-    fvm_status st = run_solve(c, 0, c->o.u_ctl, s, ks);
+    launch_gradU(g.bs, g.s);
+    launch_mom_face(g.bs, g.s);
+    launch_mom_cell(g.bs, mode, g.s);
+    std::vector<KState> res;
+    fvm_status st = run_solve(g, 0, 0, nullptr, res);
     if (st != FVM_OK) return st;
-    for (int k = 0; k < 3; ++k) {
-        to_info(ks[k], info.u[k]);
-        worst(info.status, ks[k].status);
-    }
-    return FVM_OK;
-}
-
-// one pressure solve on the assembled system, recorded in info
-fvm_status pressure_solve(fvm_case *c, const fvm_solver_ctl &ctl, hipStream_t s, fvm_step_info &info)
-{
-    KState ks;
-    fvm_status st = run_solve(c, 1, ctl, s, &ks);
-    if (st != FVM_OK) return st;
-    if (info.n_p_solves < 16) to_info(ks, info.p[info.n_p_solves++]);
-    worst(info.status, ks.status);
-    return FVM_OK;
-}
-
-fvm_status piso_one(fvm_case *c, hipStream_t s, fvm_step_info &info)
-{
-    const DevCase &d = c->d;
-    std::memset(&info, 0, sizeof(info));
-    fvm_status st = momentum_predictor(c, c->o.dt, 1.0, s, info);
-    if (st != FVM_OK || info.status < 0) return st;
-    for (int corr = 0; corr < c->o.n_corr; ++corr) {
-        for (int k = 0; k <= c->o.n_non_orth_corr; ++k) {
-            if (k == 0) launch_hbya(d, c->nonorth, s);
-            else launch_gradp(d, s);
-            launch_p_face(d, s);
-            launch_p_cell(d, c->o.p_ref_value, s);
-            st = pressure_solve(c, c->o.p_ctl, s, info);
-            if (st != FVM_OK || info.status < 0) return st;
+    for (int i = 0; i < g.n(); ++i)
+        for (int k = 0; k < 3; ++k) {
+            to_info(res[(size_t)i * kNumKs + k], info[i].u[k]);
+            worst(info[i].status, res[(size_t)i * kNumKs + k].status);
         }
-        launch_flux_corr(d, s);
-        launch_U_corr(d, s);
+    return FVM_OK;
+}
+
+fvm_status pressure_solve(Group &g, std::vector<fvm_step_info> &info)
+{
+    std::vector<KState> res;
+    fvm_status st = run_solve(g, 1, 1, nullptr, res);
+    if (st != FVM_OK) return st;
+    for (int i = 0; i < g.n(); ++i) {
+        const KState &k = res[(size_t)i * kNumKs + 3];
+        if (info[i].n_p_solves < 16) to_info(k, info[i].p[info[i].n_p_solves++]);
+        worst(info[i].status, k.status);
     }
+    return FVM_OK;
+}
+
+bool any_failed(const std::vector<fvm_step_info> &info)
+{
+    for (auto &i : info)
+        if (i.status < 0) return true;
+    return false;
+}
+
+// one PISO step of every case of the group; a case whose solve failed keeps
+// going (its kernels see non-finite values) and is rolled back afterwards
+fvm_status piso_one(Group &g, std::vector<fvm_step_info> &info)
+{
+    info.assign(g.n(), fvm_step_info{});
+    fvm_status st = momentum_predictor(g, 0, info);
+    if (st != FVM_OK) return st;
+    const fvm_case *c0 = g.cs[0];
+    if (!(g.n() == 1 && any_failed(info)))
+        for (int corr = 0; corr < c0->o.n_corr; ++corr) {
+            for (int k = 0; k <= c0->o.n_non_orth_corr; ++k) {
+                if (k == 0) launch_hbya(g.bs, 1, g.s);
+                else launch_gradp(g.bs, g.s);
+                launch_p_face(g.bs, g.s);
+                launch_p_cell(g.bs, g.s);
+                st = pressure_solve(g, info);
+                if (st != FVM_OK) return st;
+                if (g.n() == 1 && any_failed(info)) return FVM_OK;
+            }
+            launch_flux_corr(g.bs, g.s);
+            launch_U_corr(g.bs, g.s);
+        }
     HIPCHK(hipGetLastError());
     return FVM_OK;
 }
 
-fvm_status simple_one(fvm_case *c, hipStream_t s, fvm_step_info &info)
+fvm_status simple_one(Group &g, std::vector<fvm_step_info> &info)
 {
-    const DevCase &d = c->d;
-    std::memset(&info, 0, sizeof(info));
-    fvm_status st = momentum_predictor(c, 0.0, c->o.alpha_u, s, info);
-    if (st != FVM_OK || info.status < 0) return st;
-    HIPCHK(hipMemcpyAsync(d.p_prev, d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    launch_hbya(d, c->nonorth, s);
-    launch_p_face(d, s);
-    launch_p_cell(d, c->o.p_ref_value, s);
-    st = pressure_solve(c, c->o.p_ctl, s, info);
-    if (st != FVM_OK || info.status < 0) return st;
-    launch_flux_corr(d, s);
-    launch_p_relax(d, c->o.alpha_p, s);
-    launch_U_corr(d, s);
+    info.assign(g.n(), fvm_step_info{});
+    fvm_status st = momentum_predictor(g, 1, info);
+    if (st != FVM_OK || any_failed(info)) return st;
+    for (auto *c : g.cs)
+        HIPCHK(hipMemcpyAsync(c->d.p_prev, c->d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, g.s));
+    launch_hbya(g.bs, 1, g.s);
+    launch_p_face(g.bs, g.s);
+    launch_p_cell(g.bs, g.s);
+    st = pressure_solve(g, info);
+    if (st != FVM_OK || any_failed(info)) return st;
+    launch_flux_corr(g.bs, g.s);
+    launch_p_relax(g.bs, g.s);
+    launch_U_corr(g.bs, g.s);
     HIPCHK(hipGetLastError());
+    return FVM_OK;
+}
+
+// roll back the cases of the group whose step failed
+fvm_status rollback_failed(Group &g, const std::vector<fvm_step_info> &info)
+{
+    for (int i = 0; i < g.n(); ++i)
+        if (info[i].status < 0) {
+            const Group one(g.cs[i], g.s);
+            launch_save(one.bs, 1, g.s);
+        }
+    HIPCHK(hipStreamSynchronize(g.s));
     return FVM_OK;
 }
 
@@ -625,26 +741,7 @@ fvm_status simple_one(fvm_case *c, hipStream_t s, fvm_step_info &info)
 extern "C" fvm_status piso_step(fvm_case *c, int32_t n_steps, void *stream, fvm_step_info *last)
 {
     if (!c) return fvm_fail(FVM_EINVAL, "piso: null handle");
-    if (n_steps < 0) return fvm_fail(FVM_EINVAL, "piso: n_steps < 0");
-    if (!(c->o.dt > 0.0)) return fvm_fail(FVM_EINVAL, "piso: dt must be > 0");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int32_t acc = FVM_OK;
-    fvm_step_info info;
-    std::memset(&info, 0, sizeof(info));
-    for (int32_t k = 0; k < n_steps; ++k) {
-        fvm_status st = save_state(c, s);
-        if (st != FVM_OK) return st;
-        st = piso_one(c, s, info);
-        if (st == FVM_OK && info.status < 0) st = fvm_fail(info.status, "piso: a solve failed (non-finite value or breakdown)");
-        if (st < 0) {
-            restore_state(c, s);
-            if (last) *last = info;
-            return st;
-        }
-        worst(acc, info.status);
-    }
-    if (last) *last = info;
-    return acc;
+    return piso_step_batch(&c, 1, n_steps, stream, last);
 }
 
 extern "C" fvm_status simple_iterate(fvm_case *c, int32_t max_iters, double res_tol, void *stream, int32_t *iters_done,
@@ -655,28 +752,27 @@ extern "C" fvm_status simple_iterate(fvm_case *c, int32_t max_iters, double res_
     if (!(c->o.alpha_u > 0.0 && c->o.alpha_u <= 1.0) || !(c->o.alpha_p > 0.0 && c->o.alpha_p <= 1.0))
         return fvm_fail(FVM_EINVAL, "simple: relaxation factors must be in (0, 1]");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Group g(c, s);
     int32_t acc = FVM_OK, it = 0;
-    fvm_step_info info;
-    std::memset(&info, 0, sizeof(info));
+    std::vector<fvm_step_info> info(1, fvm_step_info{});
     for (it = 0; it < max_iters;) {
-        fvm_status st = save_state(c, s);
+        launch_save(g.bs, 0, s);
+        fvm_status st = simple_one(g, info);
         if (st != FVM_OK) return st;
-        st = simple_one(c, s, info);
-        if (st == FVM_OK && info.status < 0) st = fvm_fail(info.status, "simple: a solve failed (non-finite value or breakdown)");
-        if (st < 0) {
-            restore_state(c, s);
+        if (info[0].status < 0) {
+            rollback_failed(g, info);
             if (iters_done) *iters_done = it;
-            if (last) *last = info;
-            return st;
+            if (last) *last = info[0];
+            return fvm_fail(info[0].status, "simple: a solve failed (non-finite value or breakdown)");
         }
         ++it;
-        worst(acc, info.status);
-        if (info.u[0].res_initial <= res_tol && info.u[1].res_initial <= res_tol && info.u[2].res_initial <= res_tol &&
-            info.p[0].res_initial <= res_tol)
+        worst(acc, info[0].status);
+        if (info[0].u[0].res_initial <= res_tol && info[0].u[1].res_initial <= res_tol &&
+            info[0].u[2].res_initial <= res_tol && info[0].p[0].res_initial <= res_tol)
             break;
     }
     if (iters_done) *iters_done = it;
-    if (last) *last = info;
+    if (last) *last = info[0];
     return acc;
 }
 
@@ -690,15 +786,17 @@ extern "C" fvm_status solve_pressure(fvm_case *c, const double *gamma, const dou
         return fvm_fail(FVM_EINVAL, "solve_pressure: DIC needs a case created with the DIC preconditioner");
     if (ctl->max_iter < 1) return fvm_fail(FVM_EINVAL, "solve_pressure: max_iter must be >= 1");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Group g(c, s);
     const DevCase &d = c->d;
     // the case's p field is the solver's unknown: park it
     HIPCHK(hipMemcpyAsync(d.p_save, d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    launch_gather_faces(d, gamma, d.phiH, s);
-    launch_p_system_from_gamma(d, d.phiH, rhs, c->o.p_ref_value, s);
+    launch_gather_faces(g.bs, gamma, d.phiH, s);
+    launch_p_system_from_gamma(g.bs, d.phiH, rhs, s);
     HIPCHK(hipMemcpyAsync(d.p, p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    KState ks;
-    fvm_status st = run_solve(c, 1, *ctl, s, &ks);
+    std::vector<KState> res;
+    fvm_status st = run_solve(g, 1, 2, ctl, res);
     if (st != FVM_OK) return st;
+    const KState &ks = res[3];
     if (ks.status >= 0) HIPCHK(hipMemcpyAsync(p, d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(d.p, d.p_save, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -713,12 +811,13 @@ extern "C" fvm_status fvm_dic_apply(fvm_case *c, const double *gamma, const doub
     if (!c || !gamma || !r || !z) return fvm_fail(FVM_EINVAL, "dic_apply: null argument");
     if (!c->d.dstar) return fvm_fail(FVM_EINVAL, "dic_apply: case was not created with the DIC preconditioner");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Group g(c, s);
     const DevCase &d = c->d;
-    launch_gather_faces(d, gamma, d.phiH, s);
-    launch_p_system_from_gamma(d, d.phiH, r, c->o.p_ref_value, s);
+    launch_gather_faces(g.bs, gamma, d.phiH, s);
+    launch_p_system_from_gamma(g.bs, d.phiH, r, s);
     HIPCHK(hipMemcpyAsync(d.r, r, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
-    launch_dic_reset(d, s);
-    launch_dic_precond(d, 1, s);
+    launch_dic_reset(g.bs, s);
+    launch_dic_precond(g.bs, 1, s);
     HIPCHK(hipMemcpyAsync(z, d.z, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
     if (dstar) HIPCHK(hipMemcpyAsync(dstar, d.dstar, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -728,12 +827,62 @@ extern "C" fvm_status fvm_dic_apply(fvm_case *c, const double *gamma, const doub
 extern "C" fvm_status piso_step_batch(fvm_case *const *cases, int32_t n, int32_t n_steps, void *stream,
                                       fvm_step_info *infos)
 {
-    if (!cases || n < 0) return fvm_fail(FVM_EINVAL, "batch: bad arguments");
-    int32_t acc = FVM_OK;
-    for (int32_t i = 0; i < n; ++i) {
-        fvm_status st = piso_step(cases[i], n_steps, stream, infos ? infos + i : nullptr);
-        if (st < 0) return st;
-        worst(acc, st);
+    if (!cases || n < 1 || n > kMaxBatch) return fvm_fail(FVM_EINVAL, "batch: need 1 <= n_cases <= 32");
+    if (n_steps < 0) return fvm_fail(FVM_EINVAL, "piso: n_steps < 0");
+    for (int i = 0; i < n; ++i) {
+        const fvm_case *c = cases[i];
+        if (!c) return fvm_fail(FVM_EINVAL, "batch: null case");
+        if (!(c->o.dt > 0.0)) return fvm_fail(FVM_EINVAL, "piso: dt must be > 0");
+        const fvm_case *a = cases[0];
+        if (c->o.precision != a->o.precision || c->o.n_corr != a->o.n_corr ||
+            c->o.n_non_orth_corr != a->o.n_non_orth_corr || c->o.p_ctl.precond != a->o.p_ctl.precond)
+            return fvm_fail(FVM_EINVAL, "batch: cases must share precision, correctors and preconditioner");
+        for (int j = 0; j < i; ++j)
+            if (cases[j] == c) return fvm_fail(FVM_EINVAL, "batch: a case appears twice");
     }
-    return acc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Poller *P = &cases[0]->poll;
+    if (n > 1) {
+        fvm_status st = t_batch_poll.init();
+        if (st != FVM_OK) return st;
+        P = &t_batch_poll;
+    }
+    Group g(cases, n, P, s);
+    std::vector<int> idx(n);                 // group member -> caller's index
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::vector<int32_t> acc(n, FVM_OK);
+    std::vector<fvm_step_info> info;
+    std::vector<fvm_step_info> last(n, fvm_step_info{});
+    for (int32_t k = 0; k < n_steps; ++k) {
+        launch_save(g.bs, 0, s);
+        fvm_status st = piso_one(g, info);
+        if (st != FVM_OK) return st;
+        bool anyf = false;
+        for (int j = 0; j < g.n(); ++j) {
+            last[idx[j]] = info[j];
+            worst(acc[idx[j]], info[j].status);
+            anyf = anyf || info[j].status < 0;
+        }
+        if (anyf) {
+            // failed cases are rolled back to the start of the step and leave
+            // the batch; the others go on
+            st = rollback_failed(g, info);
+            if (st != FVM_OK) return st;
+            std::vector<fvm_case *> keep;
+            std::vector<int> kidx;
+            for (int j = 0; j < g.n(); ++j)
+                if (info[j].status >= 0) { keep.push_back(g.cs[j]); kidx.push_back(idx[j]); }
+            if (keep.empty()) break;
+            g = Group(keep.data(), (int)keep.size(), P, s);
+            idx = kidx;
+        }
+    }
+    // report in the caller's order
+    int32_t all = FVM_OK;
+    for (int i = 0; i < n; ++i) {
+        if (infos) infos[i] = last[i];
+        worst(all, acc[i]);
+    }
+    if (all < 0) return fvm_fail(all, "piso: a solve failed (non-finite value or breakdown); the case was rolled back");
+    return all;
 }

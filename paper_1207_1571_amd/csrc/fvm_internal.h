@@ -65,10 +65,8 @@ struct KState {
 };
 static_assert(sizeof(KState) == 128, "KState layout");
 
-// maximum grid of a reducing kernel; partial-sum buffers hold this many
-// values per reduced quantity
-constexpr int kMaxGrid = 1024;
 constexpr int kBlock = 256;
+constexpr int kGroup = 64;           // blocks per first-level reduction group
 constexpr int kMaxRed = 12;          // reduced quantities per kernel
 constexpr int kNumKs = 8;            // Krylov states per case
 
@@ -78,6 +76,11 @@ constexpr int kNumKs = 8;            // Krylov states per case
 struct DevCase {
     int32_t N, F, Fi, Fb, npatch;
     int32_t nonorth, has_fixed_p, pin_cell;
+    // per-case controls read by the kernels (a launch may serve many cases)
+    double nu, dt, alpha_u, alpha_p, p_ref, inner_rel_tol;
+    int32_t upwind, inner_max_iter;
+    double u_tol, u_rel_tol, p_tol, p_rel_tol;
+    int32_t u_max_iter, p_max_iter;
     // topology
     int32_t *own, *nei, *own_start, *nbr_start, *losort, *bnd_start, *bnd_list, *bpatch;
     int32_t *face_user, *face_sign;
@@ -107,63 +110,100 @@ struct DevCase {
     int32_t n_levels;
     // FP32 copies (mixed precision)
     float *f_diag, *f_up, *f_lo, *f_pdiag, *f_poff;
+    float *f_pexc;   // pressure row sums diag_i + sum_f off_f (FP64 sum, rounded)
     float *f_x, *f_b, *f_r, *f_rt, *f_p, *f_pt, *f_q, *f_qt;   // [3][N]
     // reductions
-    double *partials;                            // [kMaxRed][red_stride]
-    int32_t red_stride;                          // >= any reducing grid
+    double *partials;                            // [kMaxRed][red_stride]   level-1 slots
+    double *partials2;                           // [kMaxRed][red_stride2]  level-2 slots
+    int32_t red_stride, red_stride2;             // >= any reducing grid, and its groups
+    unsigned int *gticket;                       // [red_stride2] group tickets
     unsigned int *ticket;
     KState *ks;                                  // [8]: 0..2 momentum, 3 pressure; 4..7 their FP32 inner solves
     // setup temporaries (alias Krylov vectors)
     double *tmpC, *tmpCf;
+    KState *ks_gather;                           // [kMaxBatch][kNumKs] staging of a batch's states
+    DevCase *self;                               // device copy of this descriptor
+};
+
+// ---------------------------------------------------------------------------
+// A launch serves up to kMaxBatch cases: block b belongs to the case c with
+// start[c] <= b < start[c+1]; every case's block count is a multiple of 8, so
+// a block sits on the same XCD (b mod 8) whether its case runs alone or in a
+// batch, and each case's reductions see the same partial-sum order.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatch = 32;
+struct Batch {
+    const DevCase *dc[kMaxBatch];
+    int32_t start[kMaxBatch + 1];
+    int32_t n;
+};
+enum { SZ_CELL = 0, SZ_FACE = 1, SZ_FACEI = 2, SZ_MAXNF = 3, SZ_KINDS = 4 };
+struct BatchSet {
+    Batch b[SZ_KINDS];
+    const DevCase *host[kMaxBatch];   // host copies (sizes, pointers) of the same cases
+    int n;
 };
 
 // ---------------------------------------------------------------------------
 // Launchers (kernels.hip).  All enqueue on `s`; none synchronises.
 // ---------------------------------------------------------------------------
 int grid_for(int n);
+int blocks_for(int n);     // element-wise launches: 256 per block, multiple of 8
+void batch_add(BatchSet &bs, const DevCase *dev, const DevCase *host);
 
-void launch_geometry(const DevCase &d, hipStream_t s);
-void launch_flux_from_U(const DevCase &d, hipStream_t s);
-void launch_U_in(const DevCase &d, const double *U_user, hipStream_t s);
-void launch_U_out(const DevCase &d, double *U_user, hipStream_t s);
-void launch_phi_in(const DevCase &d, const double *phi_user, hipStream_t s);
-void launch_phi_out(const DevCase &d, double *phi_user, hipStream_t s);
-void launch_gather_faces(const DevCase &d, const double *user_face_vals, double *canon, hipStream_t s);
+// single-case utilities (caller arrays in the caller's numbering)
+void launch_geometry(const BatchSet &bs, hipStream_t s);
+void launch_flux_from_U(const BatchSet &bs, hipStream_t s);
+void launch_U_in(const BatchSet &bs, const double *U_user, hipStream_t s);
+void launch_U_out(const BatchSet &bs, double *U_user, hipStream_t s);
+void launch_phi_in(const BatchSet &bs, const double *phi_user, hipStream_t s);
+void launch_phi_out(const BatchSet &bs, double *phi_user, hipStream_t s);
+void launch_gather_faces(const BatchSet &bs, const double *user_face_vals, double *canon, hipStream_t s);
+void launch_p_system_from_gamma(const BatchSet &bs, const double *gamma_canon, const double *rhs, hipStream_t s);
+void launch_init_partials(const BatchSet &bs, hipStream_t s);
+void launch_set_patch(const BatchSet &bs, int patch, double u0, double u1, double u2, double pv, hipStream_t s);
 
-// momentum assembly: transient (dt > 0) or SIMPLE-relaxed (alpha_u < 1)
-void launch_gradU(const DevCase &d, hipStream_t s);
-void launch_mom_face(const DevCase &d, double nu, int upwind, hipStream_t s);
-void launch_mom_cell(const DevCase &d, double nu, double dt, double alpha_u, int upwind, hipStream_t s);
+// state save / restore (rollback of a failed step)
+void launch_save(const BatchSet &bs, int restore, hipStream_t s);
+
+// momentum assembly: mode 0 PISO (ddt), 1 SIMPLE (relaxed, no ddt)
+void launch_gradU(const BatchSet &bs, hipStream_t s);
+void launch_mom_face(const BatchSet &bs, hipStream_t s);
+void launch_mom_cell(const BatchSet &bs, int mode, hipStream_t s);
 
 // pressure corrector pieces
-void launch_hbya(const DevCase &d, int with_gradp, hipStream_t s);
-void launch_gradp(const DevCase &d, hipStream_t s);
-void launch_p_face(const DevCase &d, hipStream_t s);
-void launch_p_cell(const DevCase &d, double p_ref, hipStream_t s);
-void launch_p_system_from_gamma(const DevCase &d, const double *gamma_canon, const double *rhs, double p_ref,
-                                hipStream_t s);
-void launch_flux_corr(const DevCase &d, hipStream_t s);
-void launch_p_relax(const DevCase &d, double alpha_p, hipStream_t s);
-void launch_U_corr(const DevCase &d, hipStream_t s);
+void launch_hbya(const BatchSet &bs, int with_gradp, hipStream_t s);
+void launch_gradp(const BatchSet &bs, hipStream_t s);
+void launch_p_face(const BatchSet &bs, hipStream_t s);
+void launch_p_cell(const BatchSet &bs, hipStream_t s);
+void launch_flux_corr(const BatchSet &bs, hipStream_t s);
+void launch_p_relax(const BatchSet &bs, hipStream_t s);
+void launch_U_corr(const BatchSet &bs, hipStream_t s);
+
+// Krylov controls: src 0 = the case's momentum controls, 1 = its pressure
+// controls, 2 = the explicit values given
+void launch_set_ctl(const BatchSet &bs, int first, int count, int src, double tol, double rel_tol, int max_iter,
+                    hipStream_t s);
+// copy the Krylov states of every case of the batch next to each other
+void launch_gather_ks(const BatchSet &bs, hipStream_t s);
 
 // Krylov: momentum BiCG on the three components (FP64)
-void launch_bicg_init(const DevCase &d, hipStream_t s);
-void launch_bicg_iter(const DevCase &d, hipStream_t s);
+void launch_bicg_init(const BatchSet &bs, hipStream_t s);
+void launch_bicg_iter(const BatchSet &bs, hipStream_t s);
 // Krylov: pressure CG (FP64), Jacobi or DIC
-void launch_pcg_init(const DevCase &d, int dic, hipStream_t s);
-void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s);
-void launch_dic_precond(const DevCase &d, int with_setup, hipStream_t s);
-// mixed precision (kind 0: momentum, 1: pressure)
-void launch_mx_cvt(const DevCase &d, int kind, hipStream_t s);
-void launch_mx_inner_init(const DevCase &d, int kind, hipStream_t s);
-void launch_mx_inner_iter(const DevCase &d, int kind, hipStream_t s);
-void launch_mx_correct_resid(const DevCase &d, int kind, hipStream_t s);
-void launch_dic_reset(const DevCase &d, hipStream_t s);
-void launch_init_partials(const DevCase &d, hipStream_t s);
-
-// scalar parameters passed by value (no host staging buffers)
-void launch_set_ctl(const DevCase &d, int first, int count, double tol, double rel_tol, int max_iter, hipStream_t s);
-void launch_set_patch(const DevCase &d, int patch, double u0, double u1, double u2, double pv, hipStream_t s);
+void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s);
+void launch_pcg_iter(const BatchSet &bs, int dic, hipStream_t s);
+void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s);
+void launch_dic_reset(const BatchSet &bs, hipStream_t s);
+// mixed precision momentum (restarted FP32 BiCG inside FP64 refinement)
+void launch_mx_cvt(const BatchSet &bs, int kind, hipStream_t s);
+void launch_mx_inner_init(const BatchSet &bs, int kind, hipStream_t s);
+void launch_mx_inner_iter(const BatchSet &bs, int kind, hipStream_t s);
+void launch_mx_correct_resid(const BatchSet &bs, int kind, hipStream_t s);
+// mixed-precision pressure CG: FP32 recurrence with FP64 residual replacement
+void launch_rr_start(const BatchSet &bs, hipStream_t s);
+void launch_rr_iter(const BatchSet &bs, hipStream_t s);
+void launch_rr_replace(const BatchSet &bs, hipStream_t s);
 
 // profiling
 void prof_begin(const char *cls, hipStream_t s);

@@ -13,16 +13,22 @@
 // faces, then boundary faces), so every result is deterministic and no
 // floating-point atomics are used.
 //
-// Work decomposition: each block handles one contiguous chunk of cells in
-// 256-wide tiles.  Block b runs on XCD b % 8; the chunk index is remapped so
-// that each XCD walks one contiguous eighth of the cells, which keeps the
-// neighbour gathers of a chunk in the L2 of the XCD that produced them.
+// Batching: every kernel takes a Batch (up to kMaxBatch cases, each with its
+// own descriptor in its own workspace); a block first finds its case.  A
+// case's block count is a multiple of 8, so a block runs on the same XCD and
+// sees the same partial-sum order whether its case is launched alone or
+// together with others: results do not depend on the batch.
 //
-// Reductions: a wave reduces with xor shuffles, a block through LDS, and the
-// last block to finish (integer ticket) sums the per-block partials in a
-// fixed order and updates the Krylov scalars in device memory.  The next
-// kernels read those scalars; a solve never synchronises with the host per
-// iteration, and every iteration kernel is a no-op once its system is done.
+// Work decomposition: a reducing kernel gives each block 256 consecutive
+// cells; block b runs on XCD b % 8 and its tile index is remapped so that
+// each XCD walks one contiguous eighth of the cells, keeping neighbour
+// gathers in the L2 of the XCD that produced them.
+//
+// Reductions: wave xor-shuffles, LDS across waves, then a two-level grid
+// reduction through device-scope atomic slots (no memory fence, see
+// reduce_last).  The Krylov scalars live in device memory; a solve never
+// synchronises with the host per iteration, and every iteration kernel is a
+// no-op once its system is done.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -32,37 +38,62 @@
 namespace {
 
 constexpr int kWaves = kBlock / 64;
-// DIC sweeps: a NaN payload marks "not yet published"; bounded polling
-constexpr unsigned long long kSentinel = 0x7FF8DEADBEEF0001ULL;   // quiet NaN with a payload
+// a NaN payload marks "not yet published" (reduction slots, DIC sweeps)
+constexpr unsigned long long kSentinel = 0x7FF8DEADBEEF0001ULL;
 constexpr unsigned long long kQNaN = 0x7FF8000000000000ULL;
 constexpr int kSpinLimit = 1 << 18;
 
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
 // sentinels are written as integers: a double-typed store of a NaN constant
 // need not keep its bit pattern
-__device__ __forceinline__ void clear_word(double *a, int i) { reinterpret_cast<unsigned long long *>(a)[i] = kSentinel; }
+__device__ __forceinline__ void clear_word(double *a, long i) { reinterpret_cast<unsigned long long *>(a)[i] = kSentinel; }
 
-__device__ __forceinline__ int logical_block()
+// ---------------------------------------------------------------------------
+// case resolution
+// ---------------------------------------------------------------------------
+struct Blk {
+    const DevCase *d;
+    int raw;   // block index within the case
+    int lb;    // XCD-remapped tile index within the case
+    int G;     // blocks of the case
+};
+
+__device__ __forceinline__ Blk resolve(const Batch &b)
 {
-    const int G = gridDim.x, b = blockIdx.x;
-    return (G & 7) == 0 ? ((b & 7) * (G >> 3) + (b >> 3)) : b;
+    const int bid = blockIdx.x;
+    int c = 0;
+    while (c + 1 < b.n && bid >= b.start[c + 1]) ++c;
+    Blk k;
+    k.d = b.dc[c];
+    k.raw = bid - b.start[c];
+    k.G = b.start[c + 1] - b.start[c];
+    k.lb = (k.G & 7) == 0 ? ((k.raw & 7) * (k.G >> 3) + (k.raw >> 3)) : k.raw;
+    return k;
 }
+
+#define CASE_OF(bt)             \
+    const Blk K = resolve(bt);  \
+    const DevCase &d = *K.d
 
 struct Range {
     int beg, end;
 };
 
-__device__ __forceinline__ Range block_range(int n)
+__device__ __forceinline__ Range block_range(int n, const Blk &K)
 {
-    const int G = gridDim.x;
-    long per = ((long)n + G - 1) / G;
+    long per = ((long)n + K.G - 1) / K.G;
     per = (per + kBlock - 1) / kBlock * kBlock;
-    long b = (long)logical_block() * per;
+    const long b = (long)K.lb * per;
     Range r;
     r.beg = (int)(b < n ? b : n);
     r.end = (int)(b + per < n ? b + per : n);
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
 template <int NV>
 __device__ __forceinline__ void wave_sum(double (&v)[NV])
 {
@@ -72,16 +103,30 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV])
         for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
 }
 
-// Block partial of NV sums -> per-block slot; returns true in every thread of
-// the last block, with the grid totals in tot[] (LDS, valid after return).
-//
-// No memory fence is used (on this GPU a device-scope release writes back the
-// whole L2 of the XCD).  Each block publishes its partials with device-scope
-// atomic stores into slots that hold a NaN sentinel while empty, then takes
-// an integer ticket.  The block that draws the last ticket reads every slot
-// with device-scope atomic loads, waiting on any slot whose store has not
-// landed yet, sums them in slot order and refills the slots with the
-// sentinel for the next reduction.
+// fixed-order block sum of NV values; result valid in thread 0
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (&lds)[NV][kWaves])
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    wave_sum(v);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k][wv] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = lds[k][0];
+            for (int w = 1; w < kWaves; ++w) s += lds[k][w];
+            v[k] = s;
+        }
+}
+
+// Slots hold the NaN sentinel while empty.  A device-scope release fence
+// would compile to a write-back of the whole L2 of the XCD; instead each
+// value is published by one device-scope atomic store, and the reader waits
+// on the slot itself, then refills it with the sentinel.
 __device__ __forceinline__ double slot_take(double *slot)
 {
     unsigned long long *w = reinterpret_cast<unsigned long long *>(slot);
@@ -101,70 +146,80 @@ __device__ __forceinline__ void slot_put(double *slot, double v)
     __hip_atomic_store(reinterpret_cast<unsigned long long *>(slot), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Two-level grid reduction.  Level 1: each block publishes its partials and
+// takes its group's ticket (groups of kGroup consecutive tiles); the block
+// that completes a group sums the group's slots in order and publishes one
+// level-2 partial.  Level 2: the block that completes the last group sums
+// the level-2 slots in order.  Returns true in every thread of that final
+// block, with the totals in tot[].
 template <int NV>
-__device__ bool reduce_last(double (&v)[NV], double *partials, int stride, unsigned int *ticket, double *tot)
+__device__ bool reduce_last(double (&v)[NV], const DevCase &d, const Blk &K, double *tot)
 {
     __shared__ double lds[NV][kWaves];
-    __shared__ int amlast;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    wave_sum(v);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) lds[k][wv] = v[k];
-    __syncthreads();
-    const int G = gridDim.x;
+    __shared__ int stage;
+    const int G = K.G, lb = K.lb;
+    const int grp = lb / kGroup, ngrp = (G + kGroup - 1) / kGroup;
+    const int gsize = min(kGroup, G - grp * kGroup);
+    block_sum(v, lds);
     if (threadIdx.x == 0) {
-        const int lb = logical_block();
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = lds[k][0];
-            for (int w = 1; w < kWaves; ++w) s += lds[k][w];
-            slot_put(&partials[k * stride + lb], s);
-        }
-        const unsigned int t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        amlast = (t == (unsigned int)G - 1);
+        for (int k = 0; k < NV; ++k) slot_put(&d.partials[k * d.red_stride + lb], v[k]);
+        const unsigned int t = __hip_atomic_fetch_add(&d.gticket[grp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        stage = t == (unsigned int)gsize - 1;
     }
     __syncthreads();
-    if (!amlast) return false;
-    double acc[NV];
+    if (!stage) return false;
+    double g[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        g[k] = (int)threadIdx.x < gsize ? slot_take(&d.partials[k * d.red_stride + grp * kGroup + threadIdx.x]) : 0.0;
+    block_sum(g, lds);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&d.gticket[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) slot_put(&d.partials2[k * d.red_stride2 + grp], g[k]);
+        const unsigned int t = __hip_atomic_fetch_add(d.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        stage = t == (unsigned int)ngrp - 1 ? 2 : 0;
+    }
+    __syncthreads();
+    if (stage != 2) return false;
+    double a[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        acc[k] = 0.0;
-        for (int j = threadIdx.x; j < G; j += kBlock) acc[k] += slot_take(&partials[k * stride + j]);
+        a[k] = 0.0;
+        for (int j = threadIdx.x; j < ngrp; j += kBlock) a[k] += slot_take(&d.partials2[k * d.red_stride2 + j]);
     }
-    wave_sum(acc);
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) lds[k][wv] = acc[k];
-    __syncthreads();
+    block_sum(a, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = lds[k][0];
-            for (int w = 1; w < kWaves; ++w) s += lds[k][w];
-            tot[k] = s;
-        }
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < NV; ++k) tot[k] = a[k];
+        __hip_atomic_store(d.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     return true;
 }
 
-// y_i = diag_i x_i + sum_owned up_f x_nei + sum_nbrside lo_f x_own
-__device__ __forceinline__ double row_apply(const DevCase &d, int i, const double *__restrict__ diag,
-                                            const double *__restrict__ up, const double *__restrict__ lo,
-                                            const double *__restrict__ x)
+// ---------------------------------------------------------------------------
+// gathers
+// ---------------------------------------------------------------------------
+
+// y_i = diag_i x_i + sum_owned up_f x_nei + sum_nbrside lo_f x_own.  The
+// sum is formed in FP64 for FP32 data too: products of two FP32 values are
+// exact in FP64, and an FP32 sum of the nearly cancelling Laplacian terms
+// would lose the smooth modes Krylov methods converge on last.
+template <class T>
+__device__ __forceinline__ T row_apply(const DevCase &d, int i, const T *__restrict__ diag, const T *__restrict__ up,
+                                       const T *__restrict__ lo, const T *__restrict__ x)
 {
-    double acc = diag[i] * x[i];
+    double acc = (double)diag[i] * (double)x[i];
     const int f0 = d.own_start[i], f1 = d.own_start[i + 1];
-    for (int f = f0; f < f1; ++f) acc += up[f] * x[d.nei[f]];
+    for (int f = f0; f < f1; ++f) acc += (double)up[f] * (double)x[d.nei[f]];
     const int k0 = d.nbr_start[i], k1 = d.nbr_start[i + 1];
     for (int k = k0; k < k1; ++k) {
         const int f = d.losort[k];
-        acc += lo[f] * x[d.own[f]];
+        acc += (double)lo[f] * (double)x[d.own[f]];
     }
-    return acc;
+    return (T)acc;
 }
 
 // row sum of the off-diagonal coefficients plus the diagonal (A 1)_i
@@ -177,116 +232,9 @@ __device__ __forceinline__ double row_sum(const DevCase &d, int i, const double 
     return acc;
 }
 
-// ---------------------------------------------------------------------------
-// Setup and state exchange
-// ---------------------------------------------------------------------------
-
-// w = S.(C_N - Cf)/(S.d), dl = |S|^2/(S.d), k = S - dl d (internal);
-// dl_b = |S|^2/(S.(Cf - C_P)) (boundary)
-__global__ void k_geometry(DevCase d)
-{
-    const int f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= d.F) return;
-    const double *C = d.tmpC, *Cf = d.tmpCf;
-    const int N = d.N, F = d.F;
-    const double S0 = d.Sx[f], S1 = d.Sy[f], S2 = d.Sz[f];
-    const double SS = S0 * S0 + S1 * S1 + S2 * S2;
-    if (f < d.Fi) {
-        const int P = d.own[f], Q = d.nei[f];
-        const double d0 = C[Q] - C[P], d1 = C[N + Q] - C[N + P], d2 = C[2 * N + Q] - C[2 * N + P];
-        const double Sd = S0 * d0 + S1 * d1 + S2 * d2;
-        const double n0 = C[Q] - Cf[f], n1 = C[N + Q] - Cf[F + f], n2 = C[2 * N + Q] - Cf[2 * F + f];
-        d.w[f] = (S0 * n0 + S1 * n1 + S2 * n2) / Sd;
-        const double dl = SS / Sd;
-        d.dl[f] = dl;
-        if (d.nonorth) {
-            d.kx[f] = S0 - dl * d0;
-            d.ky[f] = S1 - dl * d1;
-            d.kz[f] = S2 - dl * d2;
-        }
-    } else {
-        const int P = d.own[f];
-        const double d0 = Cf[f] - C[P], d1 = Cf[F + f] - C[N + P], d2 = Cf[2 * F + f] - C[2 * N + P];
-        d.dl[f] = SS / (S0 * d0 + S1 * d1 + S2 * d2);
-    }
-}
-
-// phi = S.(w U_P + (1-w) U_N) internal; FIXED S.U_b, ZERO_GRAD S.U_P, EMPTY 0
-__global__ void k_flux_from_U(DevCase d)
-{
-    const int f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= d.F) return;
-    const int N = d.N;
-    const double *U = d.U;
-    double v0, v1, v2;
-    if (f < d.Fi) {
-        const int P = d.own[f], Q = d.nei[f];
-        const double w = d.w[f];
-        v0 = w * U[P] + (1.0 - w) * U[Q];
-        v1 = w * U[N + P] + (1.0 - w) * U[N + Q];
-        v2 = w * U[2 * N + P] + (1.0 - w) * U[2 * N + Q];
-    } else {
-        const int b = f - d.Fi, P = d.own[f], pt = d.bpatch[b], k = d.patch_uk[pt];
-        if (k == FVM_BC_FIXED) {
-            v0 = d.patch_uv[3 * pt]; v1 = d.patch_uv[3 * pt + 1]; v2 = d.patch_uv[3 * pt + 2];
-        } else if (k == FVM_BC_ZERO_GRAD) {
-            v0 = U[P]; v1 = U[N + P]; v2 = U[2 * N + P];
-        } else {
-            d.phi[f] = 0.0;
-            return;
-        }
-    }
-    d.phi[f] = d.Sx[f] * v0 + d.Sy[f] * v1 + d.Sz[f] * v2;
-}
-
-__global__ void k_U_in(DevCase d, const double *__restrict__ Uu)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.N) return;
-    d.U[i] = Uu[3 * (size_t)i];
-    d.U[d.N + i] = Uu[3 * (size_t)i + 1];
-    d.U[2 * d.N + i] = Uu[3 * (size_t)i + 2];
-}
-
-__global__ void k_U_out(DevCase d, double *__restrict__ Uu)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.N) return;
-    Uu[3 * (size_t)i] = d.U[i];
-    Uu[3 * (size_t)i + 1] = d.U[d.N + i];
-    Uu[3 * (size_t)i + 2] = d.U[2 * d.N + i];
-}
-
-__global__ void k_phi_in(DevCase d, const double *__restrict__ pu)
-{
-    const int f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= d.F) return;
-    d.phi[f] = f < d.Fi ? (double)d.face_sign[f] * pu[d.face_user[f]] : pu[f];
-}
-
-__global__ void k_phi_out(DevCase d, double *__restrict__ pu)
-{
-    const int f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= d.F) return;
-    if (f < d.Fi) pu[d.face_user[f]] = (double)d.face_sign[f] * d.phi[f];
-    else pu[f] = d.phi[f];
-}
-
-// caller face order -> canonical order (orientation-free face values)
-__global__ void k_gather_faces(DevCase d, const double *__restrict__ uv, double *__restrict__ out)
-{
-    const int f = blockIdx.x * kBlock + threadIdx.x;
-    if (f >= d.F) return;
-    out[f] = f < d.Fi ? uv[d.face_user[f]] : uv[f];
-}
-
-// ---------------------------------------------------------------------------
-// Momentum assembly
-// ---------------------------------------------------------------------------
-
-// Gauss gradient of a cell scalar x with the boundary rule of `kinds`/`vals`
-// (FIXED value, ZERO_GRAD owner value, EMPTY skipped); returns sum S phi_f
-// (not divided by V)
+// Gauss gradient sum of a cell scalar x (sum S phi_f, not divided by V), with
+// the boundary rule of kinds/vals: FIXED value, ZERO_GRAD owner value, EMPTY
+// skipped
 __device__ __forceinline__ void gauss_sum(const DevCase &d, int i, const double *__restrict__ x,
                                           const int32_t *__restrict__ kinds, const double *__restrict__ vals,
                                           int vstride, double &g0, double &g1, double &g2)
@@ -312,59 +260,218 @@ __device__ __forceinline__ void gauss_sum(const DevCase &d, int i, const double 
     }
 }
 
-// gradU[3c + k][i] = d U_c / d x_k (start-of-step U; non-orthogonal meshes)
-__global__ void k_gradU(DevCase d)
+// ---------------------------------------------------------------------------
+// Setup and state exchange
+// ---------------------------------------------------------------------------
+
+// w = S.(C_N - Cf)/(S.d), dl = |S|^2/(S.d), k = S - dl d (internal);
+// dl_b = |S|^2/(S.(Cf - C_P)) (boundary)
+__global__ void k_geometry(Batch bt)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    const double *C = d.tmpC, *Cf = d.tmpCf;
+    const long N = d.N, F = d.F;
+    const double S0 = d.Sx[f], S1 = d.Sy[f], S2 = d.Sz[f];
+    const double SS = S0 * S0 + S1 * S1 + S2 * S2;
+    if (f < d.Fi) {
+        const int P = d.own[f], Q = d.nei[f];
+        const double d0 = C[Q] - C[P], d1 = C[N + Q] - C[N + P], d2 = C[2 * N + Q] - C[2 * N + P];
+        const double Sd = S0 * d0 + S1 * d1 + S2 * d2;
+        const double n0 = C[Q] - Cf[f], n1 = C[N + Q] - Cf[F + f], n2 = C[2 * N + Q] - Cf[2 * F + f];
+        d.w[f] = (S0 * n0 + S1 * n1 + S2 * n2) / Sd;
+        const double dl = SS / Sd;
+        d.dl[f] = dl;
+        if (d.nonorth) {
+            d.kx[f] = S0 - dl * d0;
+            d.ky[f] = S1 - dl * d1;
+            d.kz[f] = S2 - dl * d2;
+        }
+    } else {
+        const int P = d.own[f];
+        const double d0 = Cf[f] - C[P], d1 = Cf[F + f] - C[N + P], d2 = Cf[2 * F + f] - C[2 * N + P];
+        d.dl[f] = SS / (S0 * d0 + S1 * d1 + S2 * d2);
+    }
+}
+
+// phi = S.(w U_P + (1-w) U_N) internal; FIXED S.U_b, ZERO_GRAD S.U_P, EMPTY 0
+__global__ void k_flux_from_U(Batch bt)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    const long N = d.N;
+    const double *U = d.U;
+    double v0, v1, v2;
+    if (f < d.Fi) {
+        const int P = d.own[f], Q = d.nei[f];
+        const double w = d.w[f];
+        v0 = w * U[P] + (1.0 - w) * U[Q];
+        v1 = w * U[N + P] + (1.0 - w) * U[N + Q];
+        v2 = w * U[2 * N + P] + (1.0 - w) * U[2 * N + Q];
+    } else {
+        const int b = f - d.Fi, P = d.own[f], pt = d.bpatch[b], k = d.patch_uk[pt];
+        if (k == FVM_BC_FIXED) {
+            v0 = d.patch_uv[3 * pt]; v1 = d.patch_uv[3 * pt + 1]; v2 = d.patch_uv[3 * pt + 2];
+        } else if (k == FVM_BC_ZERO_GRAD) {
+            v0 = U[P]; v1 = U[N + P]; v2 = U[2 * N + P];
+        } else {
+            d.phi[f] = 0.0;
+            return;
+        }
+    }
+    d.phi[f] = d.Sx[f] * v0 + d.Sy[f] * v1 + d.Sz[f] * v2;
+}
+
+__global__ void k_U_in(Batch bt, const double *__restrict__ Uu)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
-    const int N = d.N;
+    d.U[i] = Uu[3 * (size_t)i];
+    d.U[d.N + i] = Uu[3 * (size_t)i + 1];
+    d.U[2 * (size_t)d.N + i] = Uu[3 * (size_t)i + 2];
+}
+
+__global__ void k_U_out(Batch bt, double *__restrict__ Uu)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    Uu[3 * (size_t)i] = d.U[i];
+    Uu[3 * (size_t)i + 1] = d.U[d.N + i];
+    Uu[3 * (size_t)i + 2] = d.U[2 * (size_t)d.N + i];
+}
+
+__global__ void k_phi_in(Batch bt, const double *__restrict__ pu)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    d.phi[f] = f < d.Fi ? (double)d.face_sign[f] * pu[d.face_user[f]] : pu[f];
+}
+
+__global__ void k_phi_out(Batch bt, double *__restrict__ pu)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    if (f < d.Fi) pu[d.face_user[f]] = (double)d.face_sign[f] * d.phi[f];
+    else pu[f] = d.phi[f];
+}
+
+// caller face order -> canonical order (orientation-free face values)
+__global__ void k_gather_faces(Batch bt, const double *__restrict__ uv, double *__restrict__ out)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    out[f] = f < d.Fi ? uv[d.face_user[f]] : uv[f];
+}
+
+// start-of-step copies of U, p, phi (restore = 1 copies back)
+__global__ void k_save(Batch bt, int restore)
+{
+    CASE_OF(bt);
+    const long t = (long)K.raw * kBlock + threadIdx.x;
+    const long N = d.N, F = d.F;
+    if (t < 3 * N) {
+        if (restore) d.U[t] = d.U_save[t];
+        else d.U_save[t] = d.U[t];
+    } else if (t < 4 * N) {
+        if (restore) d.p[t - 3 * N] = d.p_save[t - 3 * N];
+        else d.p_save[t - 3 * N] = d.p[t - 3 * N];
+    } else if (t < 4 * N + F) {
+        if (restore) d.phi[t - 4 * N] = d.phi_save[t - 4 * N];
+        else d.phi_save[t - 4 * N] = d.phi[t - 4 * N];
+    }
+}
+
+__global__ void k_fill_sentinel(Batch bt)
+{
+    CASE_OF(bt);
+    const long t = (long)K.raw * kBlock + threadIdx.x;
+    const long n1 = (long)kMaxRed * d.red_stride, n2 = (long)kMaxRed * d.red_stride2;
+    for (long i = t; i < n1; i += (long)K.G * kBlock) clear_word(d.partials, i);
+    for (long i = t; i < n2; i += (long)K.G * kBlock) clear_word(d.partials2, i);
+}
+
+__global__ void k_set_patch(Batch bt, int pt, double u0, double u1, double u2, double pv)
+{
+    CASE_OF(bt);
+    if (K.raw != 0 || threadIdx.x != 0) return;
+    d.patch_uv[3 * pt] = u0;
+    d.patch_uv[3 * pt + 1] = u1;
+    d.patch_uv[3 * pt + 2] = u2;
+    d.patch_pv[pt] = pv;
+}
+
+// ---------------------------------------------------------------------------
+// Momentum assembly
+// ---------------------------------------------------------------------------
+
+// gradU[3c + k][i] = d U_c / d x_k (start-of-step U; non-orthogonal meshes)
+__global__ void k_gradU(Batch bt)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N || !d.nonorth) return;
+    const long N = d.N;
     for (int c = 0; c < 3; ++c) {
         double g0, g1, g2;
-        gauss_sum(d, i, d.U + (size_t)c * N, d.patch_uk, d.patch_uv + c, 3, g0, g1, g2);
+        gauss_sum(d, i, d.U + c * N, d.patch_uk, d.patch_uv + c, 3, g0, g1, g2);
         const double V = d.V[i];
-        d.gradU[(size_t)(3 * c) * N + i] = g0 / V;
-        d.gradU[(size_t)(3 * c + 1) * N + i] = g1 / V;
-        d.gradU[(size_t)(3 * c + 2) * N + i] = g2 / V;
+        d.gradU[(3 * c) * N + i] = g0 / V;
+        d.gradU[(3 * c + 1) * N + i] = g1 / V;
+        d.gradU[(3 * c + 2) * N + i] = g2 / V;
     }
 }
 
 // upper = F(1-w) - nu dl, lower = -F w - nu dl; non-orthogonal source
 // ns_c = nu k.(w gradU_c,P + (1-w) gradU_c,N)
-__global__ void k_mom_face(DevCase d, double nu, int upwind)
+__global__ void k_mom_face(Batch bt)
 {
-    const int f = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
     if (f >= d.Fi) return;
+    const double nu = d.nu;
     const double Fl = d.phi[f];
-    const double w = upwind ? (Fl >= 0.0 ? 1.0 : 0.0) : d.w[f];
+    const double w = d.upwind ? (Fl >= 0.0 ? 1.0 : 0.0) : d.w[f];
     const double D = nu * d.dl[f];
     d.upper[f] = Fl * (1.0 - w) - D;
     d.lower[f] = -Fl * w - D;
     if (d.nonorth) {
-        const int N = d.N, P = d.own[f], Q = d.nei[f];
+        const long N = d.N;
+        const int P = d.own[f], Q = d.nei[f];
         const double wi = d.w[f];
         const double k0 = d.kx[f], k1 = d.ky[f], k2 = d.kz[f];
         for (int c = 0; c < 3; ++c) {
-            const double *g = d.gradU + (size_t)(3 * c) * N;
+            const double *g = d.gradU + (3 * c) * N;
             const double a0 = wi * g[P] + (1.0 - wi) * g[Q];
             const double a1 = wi * g[N + P] + (1.0 - wi) * g[N + Q];
             const double a2 = wi * g[2 * N + P] + (1.0 - wi) * g[2 * N + Q];
-            d.ns[(size_t)c * d.Fi + f] = nu * (k0 * a0 + k1 * a1 + k2 * a2);
+            d.ns[(long)c * d.Fi + f] = nu * (k0 * a0 + k1 * a1 + k2 * a2);
         }
     }
 }
 
 // diag, src (without the pressure gradient) and rhs = src - V grad p.
-// dt > 0: transient term V/dt, V U/dt.  alpha_u < 1: implicit relaxation
-// diag <- diag/alpha, src += (1-alpha)/alpha diag_orig U.
-__global__ void k_mom_cell(DevCase d, double nu, double dt, double alpha_u, int upwind)
+// mode 0 (PISO): transient term V/dt, V U/dt.  mode 1 (SIMPLE): implicit
+// relaxation diag <- diag/alpha_u, src += (1-alpha_u)/alpha_u diag_orig U.
+__global__ void k_mom_cell(Batch bt, int mode)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
-    const int N = d.N;
+    const long N = d.N;
+    const double nu = d.nu;
+    const int upwind = d.upwind;
     const double V = d.V[i];
     const double U0 = d.U[i], U1 = d.U[N + i], U2 = d.U[2 * N + i];
     double dg = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (dt > 0.0) {
+    if (mode == 0) {
+        const double dt = d.dt;
         dg = V / dt;
         s0 = V * U0 / dt; s1 = V * U1 / dt; s2 = V * U2 / dt;
     }
@@ -378,7 +485,7 @@ __global__ void k_mom_cell(DevCase d, double nu, double dt, double alpha_u, int 
         const double pf = w * pi + (1.0 - w) * d.p[d.nei[f]];
         g0 += d.Sx[f] * pf; g1 += d.Sy[f] * pf; g2 += d.Sz[f] * pf;
         if (d.nonorth) {
-            s0 += d.ns[f]; s1 += d.ns[(size_t)d.Fi + f]; s2 += d.ns[2 * (size_t)d.Fi + f];
+            s0 += d.ns[f]; s1 += d.ns[(long)d.Fi + f]; s2 += d.ns[2 * (long)d.Fi + f];
         }
     }
     for (int k = d.nbr_start[i]; k < d.nbr_start[i + 1]; ++k) {
@@ -390,7 +497,7 @@ __global__ void k_mom_cell(DevCase d, double nu, double dt, double alpha_u, int 
         const double pf = w * d.p[d.own[f]] + (1.0 - w) * pi;
         g0 -= d.Sx[f] * pf; g1 -= d.Sy[f] * pf; g2 -= d.Sz[f] * pf;
         if (d.nonorth) {
-            s0 -= d.ns[f]; s1 -= d.ns[(size_t)d.Fi + f]; s2 -= d.ns[2 * (size_t)d.Fi + f];
+            s0 -= d.ns[f]; s1 -= d.ns[(long)d.Fi + f]; s2 -= d.ns[2 * (long)d.Fi + f];
         }
     }
     for (int k = d.bnd_start[i]; k < d.bnd_start[i + 1]; ++k) {
@@ -411,10 +518,11 @@ __global__ void k_mom_cell(DevCase d, double nu, double dt, double alpha_u, int 
             g0 += d.Sx[f] * pf; g1 += d.Sy[f] * pf; g2 += d.Sz[f] * pf;
         }
     }
-    if (alpha_u < 1.0) {
+    if (mode == 1) {
+        const double a = d.alpha_u;
         const double d0 = dg;
-        dg = d0 / alpha_u;
-        const double c = (1.0 - alpha_u) / alpha_u * d0;
+        dg = d0 / a;
+        const double c = (1.0 - a) / a * d0;
         s0 += c * U0; s1 += c * U1; s2 += c * U2;
     }
     d.mdiag[i] = dg;
@@ -429,11 +537,12 @@ __global__ void k_mom_cell(DevCase d, double nu, double dt, double alpha_u, int 
 // ---------------------------------------------------------------------------
 
 // H = src - sum a_PN U_N, rAU = V/a_PP, HbyA = H/a_PP; optional grad p
-__global__ void k_hbya(DevCase d, int with_gradp)
+__global__ void k_hbya(Batch bt, int with_gradp)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
-    const int N = d.N;
+    const long N = d.N;
     double h0 = d.src[i], h1 = d.src[N + i], h2 = d.src[2 * N + i];
     const double *U = d.U;
     for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) {
@@ -449,7 +558,7 @@ __global__ void k_hbya(DevCase d, int with_gradp)
     const double dg = d.mdiag[i];
     d.rAU[i] = d.V[i] / dg;
     d.HbyA[i] = h0 / dg; d.HbyA[N + i] = h1 / dg; d.HbyA[2 * N + i] = h2 / dg;
-    if (with_gradp) {
+    if (with_gradp && d.nonorth) {
         double g0, g1, g2;
         gauss_sum(d, i, d.p, d.patch_pk, d.patch_pv, 1, g0, g1, g2);
         const double V = d.V[i];
@@ -457,23 +566,25 @@ __global__ void k_hbya(DevCase d, int with_gradp)
     }
 }
 
-__global__ void k_gradp(DevCase d)
+__global__ void k_gradp(Batch bt)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
     double g0, g1, g2;
     gauss_sum(d, i, d.p, d.patch_pk, d.patch_pv, 1, g0, g1, g2);
     const double V = d.V[i];
-    d.gradp[i] = g0 / V; d.gradp[d.N + i] = g1 / V; d.gradp[2 * d.N + i] = g2 / V;
+    d.gradp[i] = g0 / V; d.gradp[d.N + i] = g1 / V; d.gradp[2 * (long)d.N + i] = g2 / V;
 }
 
 // face pass: phiH = S.interp(HbyA) (boundary per U kind), gam = interp(rAU)
 // (boundary rAU_P), poff = -gam dl, tno = gam k.interp(grad p)
-__global__ void k_p_face(DevCase d)
+__global__ void k_p_face(Batch bt)
 {
-    const int f = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
     if (f >= d.F) return;
-    const int N = d.N;
+    const long N = d.N;
     const double *H = d.HbyA;
     if (f < d.Fi) {
         const int P = d.own[f], Q = d.nei[f];
@@ -504,10 +615,12 @@ __global__ void k_p_face(DevCase d)
     }
 }
 
-// cell pass: pdiag, pb (divergence, fixed-p terms, non-orthogonal part), pin
-__global__ void k_p_cell(DevCase d, double p_ref, int with_div)
+// cell pass: pdiag, pb (divergence, fixed-p terms, non-orthogonal part), pin.
+// with_div = 0: the stand-alone pressure system (pb holds the given rhs)
+__global__ void k_p_cell(Batch bt, int with_div)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
     double dg = 0.0, b = 0.0;
     for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) {
@@ -534,7 +647,7 @@ __global__ void k_p_cell(DevCase d, double p_ref, int with_div)
     if (i == d.pin_cell && !d.has_fixed_p) {
         const double a = dg;
         dg = 2.0 * a;
-        b += a * p_ref;
+        b += a * d.p_ref;
     }
     d.pdiag[i] = dg;
     if (with_div) d.pb[i] = b;
@@ -542,9 +655,10 @@ __global__ void k_p_cell(DevCase d, double p_ref, int with_div)
 }
 
 // gamma given per face (canonical order) -> poff, gam
-__global__ void k_p_face_gamma(DevCase d, const double *__restrict__ gam)
+__global__ void k_p_face_gamma(Batch bt, const double *__restrict__ gam)
 {
-    const int f = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
     if (f >= d.F) return;
     const double g = gam[f];
     d.gam[f] = g;
@@ -552,9 +666,10 @@ __global__ void k_p_face_gamma(DevCase d, const double *__restrict__ gam)
 }
 
 // phi = phiH - g (p_N - p_P) - tno (internal); p FIXED: phiH - g_b (p_b - p_P)
-__global__ void k_flux_corr(DevCase d)
+__global__ void k_flux_corr(Batch bt)
 {
-    const int f = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
     if (f >= d.F) return;
     if (f < d.Fi) {
         double v = d.phiH[f] - d.gam[f] * d.dl[f] * (d.p[d.nei[f]] - d.p[d.own[f]]);
@@ -569,19 +684,21 @@ __global__ void k_flux_corr(DevCase d)
     }
 }
 
-__global__ void k_p_relax(DevCase d, double alpha_p)
+__global__ void k_p_relax(Batch bt)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
-    d.p[i] = d.p_prev[i] + alpha_p * (d.p[i] - d.p_prev[i]);
+    d.p[i] = d.p_prev[i] + d.alpha_p * (d.p[i] - d.p_prev[i]);
 }
 
 // U = HbyA - rAU grad p (new p)
-__global__ void k_U_corr(DevCase d)
+__global__ void k_U_corr(Batch bt)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
-    const int N = d.N;
+    const long N = d.N;
     double g0, g1, g2;
     gauss_sum(d, i, d.p, d.patch_pk, d.patch_pv, 1, g0, g1, g2);
     const double V = d.V[i], r = d.rAU[i];
@@ -594,8 +711,8 @@ __global__ void k_U_corr(DevCase d)
 // Krylov solvers (Barrett et al., "Templates": CG and BiCG)
 //
 // The iteration kernels are templated on the vector/matrix value type: the
-// FP64 solves and the FP32 inner solves of the mixed-precision refinement run
-// the same code over different arrays.  Every dot product and residual sum is
+// FP64 solves and the FP32 inner solves of the mixed-precision modes run the
+// same code over different arrays.  Every dot product and residual sum is
 // accumulated in FP64 whatever the vector type.
 // ---------------------------------------------------------------------------
 
@@ -605,52 +722,99 @@ __device__ __forceinline__ void set_done(KState &s, int status)
     s.done = 1;
 }
 
-template <class T>
-__device__ __forceinline__ T row_apply_t(const DevCase &d, int i, const T *__restrict__ diag, const T *__restrict__ up,
-                                         const T *__restrict__ lo, const T *__restrict__ x)
-{
-    T acc = diag[i] * x[i];
-    const int f0 = d.own_start[i], f1 = d.own_start[i + 1];
-    for (int f = f0; f < f1; ++f) acc += up[f] * x[d.nei[f]];
-    const int k0 = d.nbr_start[i], k1 = d.nbr_start[i + 1];
-    for (int k = k0; k < k1; ++k) {
-        const int f = d.losort[k];
-        acc += lo[f] * x[d.own[f]];
-    }
-    return acc;
-}
+// array selectors: a view names which arrays of the case a kernel uses
+enum { V_FP64 = 0, V_FP32 = 1 };
 
-// symmetric system (pressure): one coefficient per face
 template <class T>
-struct CGView {
+struct CGArr {
     const T *diag, *off;
+    const T *exc;   // FP32 only: row sums, for the difference form of A p
     T *x, *r, *p, *q;
-    const double *z;    // DIC output (FP64 path), else nullptr
+    const double *z;
     KState *ks;
 };
 
-// non-symmetric system (momentum), three right-hand sides sharing A
 template <class T>
-struct BiView {
+__device__ __forceinline__ CGArr<T> cg_arrays(const DevCase &d, int dic);
+
+template <>
+__device__ __forceinline__ CGArr<double> cg_arrays<double>(const DevCase &d, int dic)
+{
+    return CGArr<double>{d.pdiag, d.poff, nullptr, d.p, d.r, d.pp, d.q, dic ? d.z : nullptr, d.ks + 3};
+}
+
+// FP32 recurrence of the mixed-precision pressure CG (x is FP64: not here)
+template <>
+__device__ __forceinline__ CGArr<float> cg_arrays<float>(const DevCase &d, int)
+{
+    return CGArr<float>{d.f_pdiag, d.f_poff, d.f_pexc, d.f_x, d.f_r, d.f_p, d.f_q, nullptr, d.ks + 3};
+}
+
+template <class T>
+struct BiArr {
     const T *diag, *up, *lo;
-    T *x, *r, *rt, *p, *pt, *q, *qt;     // [3][N]
-    KState *ks;                          // [3]
+    T *x, *r, *rt, *p, *pt, *q, *qt;
+    KState *ks;
 };
+
+template <class T>
+__device__ __forceinline__ BiArr<T> bi_arrays(const DevCase &d);
+
+template <>
+__device__ __forceinline__ BiArr<double> bi_arrays<double>(const DevCase &d)
+{
+    return BiArr<double>{d.mdiag, d.upper, d.lower, d.U, d.r, d.rt, d.pp, d.pt, d.q, d.qt, d.ks};
+}
+
+template <>
+__device__ __forceinline__ BiArr<float> bi_arrays<float>(const DevCase &d)
+{
+    return BiArr<float>{d.f_diag, d.f_up, d.f_lo, d.f_x, d.f_r, d.f_rt, d.f_p, d.f_pt, d.f_q, d.f_qt, d.ks + 4};
+}
+
+// ---- controls ----------------------------------------------------------
+
+__global__ void k_set_ctl(Batch bt, int first, int count, int src, double tol, double rel_tol, int max_iter)
+{
+    CASE_OF(bt);
+    const int k = threadIdx.x;
+    if (K.raw != 0 || k >= count) return;
+    KState &s = d.ks[first + k];
+    if (src == 0) { s.tol = d.u_tol; s.rel_tol = d.u_rel_tol; s.max_iter = d.u_max_iter; }
+    else if (src == 1) { s.tol = d.p_tol; s.rel_tol = d.p_rel_tol; s.max_iter = d.p_max_iter; }
+    else if (src == 3) { s.tol = 0.0; s.rel_tol = d.inner_rel_tol; s.max_iter = d.inner_max_iter; }
+    else { s.tol = tol; s.rel_tol = rel_tol; s.max_iter = max_iter; }
+}
+
+// case c of the batch -> ks_gather[c][.] of the first case (one D2H copy)
+__global__ void k_gather_ks(Batch bt)
+{
+    CASE_OF(bt);
+    if (K.raw != 0) return;
+    int c = 0;
+    while (c + 1 < bt.n && (int)blockIdx.x >= bt.start[c + 1]) ++c;
+    const int words = (int)(kNumKs * sizeof(KState) / sizeof(unsigned long long));
+    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(d.ks);
+    unsigned long long *dst = reinterpret_cast<unsigned long long *>(bt.dc[0]->ks_gather + (size_t)c * kNumKs);
+    for (int w = threadIdx.x; w < words; w += kBlock) dst[w] = src[w];
+}
 
 // ---- BiCG --------------------------------------------------------------
 
 // p = z + beta p, p~ = z~ + beta p~ (z = r/diag, z~ = r~/diag)
 template <class T>
-__global__ void k_bicg_dir(DevCase d, BiView<T> v)
+__global__ void k_bicg_dir(Batch bt)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
-    const int N = d.N;
+    const BiArr<T> v = bi_arrays<T>(d);
+    const long N = d.N;
     const T dg = v.diag[i];
     for (int c = 0; c < 3; ++c) {
         const KState &s = v.ks[c];
         if (s.done) continue;
-        const size_t j = (size_t)c * N + i;
+        const long j = c * N + i;
         const T z = v.r[j] / dg, zt = v.rt[j] / dg;
         if (s.first) {
             v.p[j] = z;
@@ -665,27 +829,29 @@ __global__ void k_bicg_dir(DevCase d, BiView<T> v)
 
 // q = A p, q~ = A^T p~, p~.q -> alpha
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_bicg_spmv(DevCase d, BiView<T> v)
+__global__ void __launch_bounds__(kBlock) k_bicg_spmv(Batch bt)
 {
+    CASE_OF(bt);
+    const BiArr<T> v = bi_arrays<T>(d);
     int act[3];
     for (int c = 0; c < 3; ++c) act[c] = !v.ks[c].done;
     if (!act[0] && !act[1] && !act[2]) return;
-    const Range rg = block_range(d.N);
-    const int N = d.N;
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
         for (int c = 0; c < 3; ++c) {
             if (!act[c]) continue;
-            const T *p = v.p + (size_t)c * N, *pt = v.pt + (size_t)c * N;
-            const T q = row_apply_t<T>(d, i, v.diag, v.up, v.lo, p);
-            const T qt = row_apply_t<T>(d, i, v.diag, v.lo, v.up, pt);
-            v.q[(size_t)c * N + i] = q;
-            v.qt[(size_t)c * N + i] = qt;
+            const T *p = v.p + c * N, *pt = v.pt + c * N;
+            const T q = row_apply<T>(d, i, v.diag, v.up, v.lo, p);
+            const T qt = row_apply<T>(d, i, v.diag, v.lo, v.up, pt);
+            v.q[c * N + i] = q;
+            v.qt[c * N + i] = qt;
             acc[c] += (double)pt[i] * (double)q;
         }
     }
     __shared__ double tot[3];
-    if (reduce_last<3>(acc, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<3>(acc, d, K, tot) && threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) {
             if (!act[c]) continue;
             KState &s = v.ks[c];
@@ -697,20 +863,22 @@ __global__ void __launch_bounds__(kBlock) k_bicg_spmv(DevCase d, BiView<T> v)
 
 // x += alpha p, r -= alpha q, r~ -= alpha q~; rho = z.r~, |r| -> stop test, beta
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_bicg_update(DevCase d, BiView<T> v)
+__global__ void __launch_bounds__(kBlock) k_bicg_update(Batch bt)
 {
+    CASE_OF(bt);
+    const BiArr<T> v = bi_arrays<T>(d);
     int act[3];
     T al[3];
     for (int c = 0; c < 3; ++c) { act[c] = !v.ks[c].done; al[c] = (T)v.ks[c].alpha; }
     if (!act[0] && !act[1] && !act[2]) return;
-    const Range rg = block_range(d.N);
-    const int N = d.N;
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
         const T dg = v.diag[i];
         for (int c = 0; c < 3; ++c) {
             if (!act[c]) continue;
-            const size_t j = (size_t)c * N + i;
+            const long j = c * N + i;
             v.x[j] += al[c] * v.p[j];
             const T r = v.r[j] - al[c] * v.q[j];
             const T rt = v.rt[j] - al[c] * v.qt[j];
@@ -721,7 +889,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_update(DevCase d, BiView<T> v)
         }
     }
     __shared__ double tot[6];
-    if (reduce_last<6>(acc, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<6>(acc, d, K, tot) && threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) {
             if (!act[c]) continue;
             KState &s = v.ks[c];
@@ -741,23 +909,25 @@ __global__ void __launch_bounds__(kBlock) k_bicg_update(DevCase d, BiView<T> v)
 }
 
 // FP64 start: sum x_c -> xbar_c
-__global__ void __launch_bounds__(kBlock) k_bicg_sumx(DevCase d)
+__global__ void __launch_bounds__(kBlock) k_bicg_sumx(Batch bt)
 {
-    const Range r = block_range(d.N);
-    const int N = d.N;
+    CASE_OF(bt);
+    const Range r = block_range(d.N, K);
+    const long N = d.N;
     double v[3] = {0.0, 0.0, 0.0};
     for (int i = r.beg + threadIdx.x; i < r.end; i += kBlock)
-        for (int c = 0; c < 3; ++c) v[c] += d.U[(size_t)c * N + i];
+        for (int c = 0; c < 3; ++c) v[c] += d.U[c * N + i];
     __shared__ double tot[3];
-    if (reduce_last<3>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0)
+    if (reduce_last<3>(v, d, K, tot) && threadIdx.x == 0)
         for (int c = 0; c < 3; ++c) d.ks[c].xbar = tot[c] / (double)N;
 }
 
 // FP64 start: r = b - A x, r~ = r, normalisation, first rho = z.r~
-__global__ void __launch_bounds__(kBlock) k_bicg_init(DevCase d)
+__global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt)
 {
-    const Range rg = block_range(d.N);
-    const int N = d.N;
+    CASE_OF(bt);
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
     double xb[3];
     for (int c = 0; c < 3; ++c) xb[c] = d.ks[c].xbar;
     double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // nf_c, |r|_c, rho_c
@@ -765,12 +935,12 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(DevCase d)
         const double a1 = row_sum(d, i, d.mdiag, d.upper, d.lower);
         const double dg = d.mdiag[i];
         for (int c = 0; c < 3; ++c) {
-            const double *x = d.U + (size_t)c * N;
-            const double ax = row_apply(d, i, d.mdiag, d.upper, d.lower, x);
-            const double b = d.rhs[(size_t)c * N + i];
+            const double *x = d.U + c * N;
+            const double ax = row_apply<double>(d, i, d.mdiag, d.upper, d.lower, x);
+            const double b = d.rhs[c * N + i];
             const double r = b - ax;
-            d.r[(size_t)c * N + i] = r;
-            d.rt[(size_t)c * N + i] = r;
+            d.r[c * N + i] = r;
+            d.rt[c * N + i] = r;
             v[c] += fabs(ax - xb[c] * a1) + fabs(b - xb[c] * a1);
             v[3 + c] += fabs(r);
             const double z = r / dg;
@@ -778,7 +948,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(DevCase d)
         }
     }
     __shared__ double tot[9];
-    if (reduce_last<9>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<9>(v, d, K, tot) && threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) {
             KState &s = d.ks[c];
             s.nf = tot[c] + 1e-20;
@@ -802,53 +972,144 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(DevCase d)
 
 // p = z + beta p (Jacobi z = r/diag; DIC z from the sweeps)
 template <class T>
-__global__ void k_cg_dir(DevCase d, CGView<T> v)
+__global__ void k_cg_dir(Batch bt, int dic)
 {
+    CASE_OF(bt);
+    const CGArr<T> v = cg_arrays<T>(d, dic);
     const KState &s = *v.ks;
     if (s.done) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i >= d.N) return;
     const T z = v.z ? (T)v.z[i] : v.r[i] / v.diag[i];
     v.p[i] = s.first ? z : z + (T)s.beta * v.p[i];
 }
 
-// q = A p, p.q -> alpha
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_cg_spmv(DevCase d, CGView<T> v)
+// (A32 p)_i in difference form: sum_f off_f p_j + (exc_i - sum_f off_f) p_i,
+// with exc_i the FP64 row sum rounded once.  Rounding diag and off to FP32
+// separately would perturb every row sum by O(eps32 diag): on a pressure
+// system whose only non-zero row sums are a few boundary or reference cells
+// that moves the smallest eigenvalues by O(1) and stalls CG.  Here the FP32
+// operator is a graph Laplacian of the rounded face weights plus the rounded
+// row sums, spectrally within (1 +- eps32) of the FP64 one.  Products of
+// FP32 values are exact in FP64 and the sums are FP64.
+__device__ __forceinline__ float row_apply_diff(const DevCase &d, int i, const float *__restrict__ exc,
+                                                const float *__restrict__ off, const float *__restrict__ x)
 {
+    double acc = 0.0, so = 0.0;
+    const int f0 = d.own_start[i], f1 = d.own_start[i + 1];
+    for (int f = f0; f < f1; ++f) {
+        acc += (double)off[f] * (double)x[d.nei[f]];
+        so += (double)off[f];
+    }
+    const int k0 = d.nbr_start[i], k1 = d.nbr_start[i + 1];
+    for (int k = k0; k < k1; ++k) {
+        const int f = d.losort[k];
+        acc += (double)off[f] * (double)x[d.own[f]];
+        so += (double)off[f];
+    }
+    return (float)(acc + ((double)exc[i] - so) * (double)x[i]);
+}
+
+// q = A p, p.q -> alpha.  One block = 256 consecutive cells.  The products
+// of the block's owned faces and of its neighbour-side faces are formed by
+// face-parallel, coalesced passes into LDS; each cell then sums its faces
+// from LDS in the fixed order (owned faces, then neighbour-side faces).
+// Blocks whose face ranges exceed the staging buffers fall back to the
+// per-cell gather (same order, same result).  FP64: diag p_i + sum; FP32:
+// the difference form above.
+constexpr int kStage = 4 * kBlock;
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
+{
+    constexpr bool kDiff = sizeof(T) == 4;
+    CASE_OF(bt);
+    const CGArr<T> v = cg_arrays<T>(d, dic);
     if (v.ks->done) return;
-    const Range rg = block_range(d.N);
+    __shared__ double prodO[kStage], prodN[kStage];
+    __shared__ float offO[kDiff ? kStage : 1], offN[kDiff ? kStage : 1];
+    const Range rg = block_range(d.N, K);
+    const int i = rg.beg + threadIdx.x;
     double acc[1] = {0.0};
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        const T q = row_apply_t<T>(d, i, v.diag, v.off, v.off, v.p);
-        v.q[i] = q;
-        acc[0] += (double)v.p[i] * (double)q;
+    if (rg.beg < rg.end) {
+        const T *__restrict__ p = v.p;
+        const T *__restrict__ off = v.off;
+        const int *__restrict__ nei = d.nei;
+        const int *__restrict__ own = d.own;
+        const int *__restrict__ losort = d.losort;
+        const int F0 = d.own_start[rg.beg], F1 = d.own_start[rg.end];
+        const int K0 = d.nbr_start[rg.beg], K1 = d.nbr_start[rg.end];
+        const bool staged = F1 - F0 <= kStage && K1 - K0 <= kStage;
+        if (staged) {
+            for (int t = threadIdx.x; t < F1 - F0; t += kBlock) {
+                const int f = F0 + t;
+                const T a = off[f];
+                prodO[t] = (double)a * (double)p[nei[f]];
+                if (kDiff) offO[t] = (float)a;
+            }
+            for (int t = threadIdx.x; t < K1 - K0; t += kBlock) {
+                const int f = losort[K0 + t];
+                const T a = off[f];
+                prodN[t] = (double)a * (double)p[own[f]];
+                if (kDiff) offN[t] = (float)a;
+            }
+        }
+        __syncthreads();
+        if (i < rg.end) {
+            T q;
+            if (staged) {
+                const int a0 = d.own_start[i], a1 = d.own_start[i + 1];
+                const int b0 = d.nbr_start[i], b1 = d.nbr_start[i + 1];
+                if (kDiff) {
+                    double qa = 0.0, so = 0.0;
+                    for (int f = a0; f < a1; ++f) { qa += prodO[f - F0]; so += (double)offO[f - F0]; }
+                    for (int k = b0; k < b1; ++k) { qa += prodN[k - K0]; so += (double)offN[k - K0]; }
+                    q = (T)(qa + ((double)v.exc[i] - so) * (double)p[i]);
+                } else {
+                    double qa = (double)v.diag[i] * (double)p[i];
+                    for (int f = a0; f < a1; ++f) qa += prodO[f - F0];
+                    for (int k = b0; k < b1; ++k) qa += prodN[k - K0];
+                    q = (T)qa;
+                }
+            } else if constexpr (kDiff) {
+                q = row_apply_diff(d, i, v.exc, off, p);
+            } else {
+                q = row_apply<T>(d, i, v.diag, off, off, p);
+            }
+            v.q[i] = q;
+            acc[0] = (double)p[i] * (double)q;
+        }
     }
     __shared__ double tot[1];
-    if (reduce_last<1>(acc, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<1>(acc, d, K, tot) && threadIdx.x == 0) {
         KState &s = *v.ks;
         if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
         else s.alpha = s.rho / tot[0];
     }
 }
 
-// x += alpha p, r -= alpha q, |r| -> stop test; Jacobi: rho = r.(r/diag), beta
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_cg_update(DevCase d, CGView<T> v, int dic)
+// FP64: x += alpha p, r -= alpha q, |r| -> stop test; Jacobi: rho, beta
+__global__ void __launch_bounds__(kBlock) k_cg_update(Batch bt, int dic)
 {
+    CASE_OF(bt);
+    const CGArr<double> v = cg_arrays<double>(d, dic);
     if (v.ks->done) return;
-    const T al = (T)v.ks->alpha;
-    const Range rg = block_range(d.N);
+    const double al = v.ks->alpha;
+    const Range rg = block_range(d.N, K);
     double acc[2] = {0.0, 0.0};
+    double *__restrict__ x = v.x;
+    double *__restrict__ rr = v.r;
+    const double *__restrict__ p = v.p;
+    const double *__restrict__ q = v.q;
     for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        v.x[i] += al * v.p[i];
-        const T r = v.r[i] - al * v.q[i];
-        v.r[i] = r;
-        acc[0] += fabs((double)r);
-        if (!dic) acc[1] += (double)r * (double)(r / v.diag[i]);
+        x[i] += al * p[i];
+        const double r = rr[i] - al * q[i];
+        rr[i] = r;
+        acc[0] += fabs(r);
+        if (!dic) acc[1] += r * (r / v.diag[i]);
     }
     __shared__ double tot[2];
-    if (reduce_last<2>(acc, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<2>(acc, d, K, tot) && threadIdx.x == 0) {
         KState &s = *v.ks;
         s.iters += 1;
         s.nres = tot[0] / s.nf;
@@ -866,25 +1127,26 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(DevCase d, CGView<T> v, in
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_pcg_sumx(DevCase d)
+__global__ void __launch_bounds__(kBlock) k_pcg_sumx(Batch bt)
 {
-    const Range r = block_range(d.N);
+    CASE_OF(bt);
+    const Range r = block_range(d.N, K);
     double v[1] = {0.0};
     for (int i = r.beg + threadIdx.x; i < r.end; i += kBlock) v[0] += d.p[i];
     __shared__ double tot[1];
-    if (reduce_last<1>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0)
-        d.ks[3].xbar = tot[0] / (double)d.N;
+    if (reduce_last<1>(v, d, K, tot) && threadIdx.x == 0) d.ks[3].xbar = tot[0] / (double)d.N;
 }
 
 // FP64 start: r = b - A x; normalisation; Jacobi: first rho = r.(r/diag)
-__global__ void __launch_bounds__(kBlock) k_pcg_init(DevCase d, int dic)
+__global__ void __launch_bounds__(kBlock) k_pcg_init(Batch bt, int dic)
 {
-    const Range rg = block_range(d.N);
+    CASE_OF(bt);
+    const Range rg = block_range(d.N, K);
     const double xb = d.ks[3].xbar;
     double v[3] = {0.0, 0.0, 0.0};
     for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
         const double a1 = row_sum(d, i, d.pdiag, d.poff, d.poff);
-        const double ax = row_apply(d, i, d.pdiag, d.poff, d.poff, d.p);
+        const double ax = row_apply<double>(d, i, d.pdiag, d.poff, d.poff, d.p);
         const double b = d.pb[i];
         const double r = b - ax;
         d.r[i] = r;
@@ -898,7 +1160,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(DevCase d, int dic)
         }
     }
     __shared__ double tot[3];
-    if (reduce_last<3>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+    if (reduce_last<3>(v, d, K, tot) && threadIdx.x == 0) {
         KState &s = d.ks[3];
         s.nf = tot[0] + 1e-20;
         s.nres0 = tot[1] / s.nf;
@@ -919,139 +1181,6 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(DevCase d, int dic)
 }
 
 // ---------------------------------------------------------------------------
-// Mixed precision: FP64 iterative refinement around FP32 inner solves
-//
-// Outer (FP64, states ks[0..3]):  r = b - A x  ->  if nres <= tol: stop
-//   inner (FP32, states ks[4..7]): A e = s r from e = 0 to a relative
-//                                  reduction eta, s = N / sum|r| (keeps the
-//                                  demoted residual O(1))
-//   x += e / s  (FP64).
-// The outer iteration count is the total number of inner iterations.
-// ---------------------------------------------------------------------------
-
-// FP32 copies of the assembled matrix values (the topology is shared)
-__global__ void k_mx_cvt(DevCase d, int kind)
-{
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (kind == 1) {
-        if (t < d.N) d.f_pdiag[t] = (float)d.pdiag[t];
-        if (t < d.Fi) d.f_poff[t] = (float)d.poff[t];
-    } else {
-        if (t < d.N) d.f_diag[t] = (float)d.mdiag[t];
-        if (t < d.Fi) { d.f_up[t] = (float)d.upper[t]; d.f_lo[t] = (float)d.lower[t]; }
-    }
-}
-
-__device__ __forceinline__ double mx_scale(const KState &o, int N) { return (double)N / (o.nres * o.nf); }
-
-// inner start: r_in = s r (FP32), e = 0, inner normalisation sum|r_in|,
-// Jacobi rho.  kind 1: pressure (one system), kind 0: momentum (three).
-__global__ void __launch_bounds__(kBlock) k_mx_inner_init(DevCase d, int kind)
-{
-    const int nsys = kind == 1 ? 1 : 3, o0 = kind == 1 ? 3 : 0, i0 = kind == 1 ? 7 : 4;
-    int act[3];
-    double sc[3];
-    for (int c = 0; c < 3; ++c) {
-        act[c] = c < nsys && !d.ks[o0 + c].done;
-        sc[c] = act[c] ? mx_scale(d.ks[o0 + c], d.N) : 0.0;
-    }
-    if (!act[0] && !act[1] && !act[2]) return;
-    const Range rg = block_range(d.N);
-    const int N = d.N;
-    const float *diag = kind == 1 ? d.f_pdiag : d.f_diag;
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        const float dg = diag[i];
-        for (int c = 0; c < nsys; ++c) {
-            if (!act[c]) continue;
-            const size_t j = (size_t)c * N + i;
-            const float r = (float)(sc[c] * d.r[j]);
-            d.f_r[j] = r;
-            d.f_x[j] = 0.0f;
-            if (kind == 0) d.f_rt[j] = r;
-            v[c] += fabs((double)r);
-            v[3 + c] += (double)(r / dg) * (double)r;
-        }
-    }
-    __shared__ double tot[6];
-    if (reduce_last<6>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
-        for (int c = 0; c < nsys; ++c) {
-            KState &s = d.ks[i0 + c];
-            if (!act[c]) { set_done(s, FVM_OK); s.iters = 0; continue; }
-            s.nf = tot[c];
-            s.nres0 = 1.0;
-            s.nres = 1.0;
-            s.tol_eff = fmax(s.tol, s.rel_tol);
-            s.iters = 0;
-            s.done = 0;
-            s.status = FVM_OK;
-            s.first = 1;
-            s.beta = 0.0;
-            const bool bad = kind == 1 ? !(tot[3 + c] > 0.0) : tot[3 + c] == 0.0;
-            if (!isfinite(tot[c]) || !(tot[c] > 0.0)) set_done(s, FVM_ENUMERIC);
-            else if (bad || !isfinite(tot[3 + c])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
-            else s.rho = tot[3 + c];
-        }
-    }
-}
-
-// x += e / s (FP64), for the systems whose outer loop is still running
-__global__ void k_mx_correct(DevCase d, int kind)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.N) return;
-    const int nsys = kind == 1 ? 1 : 3, o0 = kind == 1 ? 3 : 0;
-    double *x = kind == 1 ? d.p : d.U;
-    for (int c = 0; c < nsys; ++c) {
-        const KState &o = d.ks[o0 + c];
-        if (o.done) continue;
-        const double s = mx_scale(o, d.N);
-        const size_t j = (size_t)c * d.N + i;
-        x[j] += (double)d.f_x[j] / s;
-    }
-}
-
-// outer residual after a correction: r = b - A x (FP64), nres, stop test;
-// the inner iterations are added to the outer count
-__global__ void __launch_bounds__(kBlock) k_mx_resid(DevCase d, int kind)
-{
-    const int nsys = kind == 1 ? 1 : 3, o0 = kind == 1 ? 3 : 0, i0 = kind == 1 ? 7 : 4;
-    int act[3];
-    for (int c = 0; c < 3; ++c) act[c] = c < nsys && !d.ks[o0 + c].done;
-    if (!act[0] && !act[1] && !act[2]) return;
-    const Range rg = block_range(d.N);
-    const int N = d.N;
-    const double *diag = kind == 1 ? d.pdiag : d.mdiag;
-    const double *up = kind == 1 ? d.poff : d.upper;
-    const double *lo = kind == 1 ? d.poff : d.lower;
-    const double *xb = kind == 1 ? d.p : d.U;
-    const double *bb = kind == 1 ? d.pb : d.rhs;
-    double v[3] = {0, 0, 0};
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        for (int c = 0; c < nsys; ++c) {
-            if (!act[c]) continue;
-            const size_t j = (size_t)c * N + i;
-            const double r = bb[j] - row_apply(d, i, diag, up, lo, xb + (size_t)c * N);
-            d.r[j] = r;
-            v[c] += fabs(r);
-        }
-    }
-    __shared__ double tot[3];
-    if (reduce_last<3>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
-        for (int c = 0; c < nsys; ++c) {
-            if (!act[c]) continue;
-            KState &o = d.ks[o0 + c];
-            const KState &in = d.ks[i0 + c];
-            o.iters += in.iters;
-            o.nres = tot[c] / o.nf;
-            if (in.status == FVM_ENUMERIC || !isfinite(o.nres)) set_done(o, FVM_ENUMERIC);
-            else if (o.nres <= o.tol_eff) set_done(o, FVM_OK);
-            else if (o.iters >= o.max_iter) set_done(o, FVM_WARN_MAXITER);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // DIC triangular sweeps, sync-free in level order
 //
 // The diagonal-only incomplete Cholesky factor D* and the two triangular
@@ -1061,12 +1190,11 @@ __global__ void __launch_bounds__(kBlock) k_mx_resid(DevCase d, int kind)
 // through an atomic ticket, so every dependency of a tile lies in a tile that
 // has already been claimed by a running or finished block.  A value is
 // published with one 64-bit device-scope store into an array pre-filled with
-// a NaN sentinel: the value is its own ready flag, so no fence is needed and
-// a reader polls exactly the word it consumes.  Each lane keeps consuming
-// dependencies as they appear (no lane waits inside a loop another lane of
-// its wave must leave first), and polling is bounded: past the limit the
-// value is published as NaN, which the solver reports as a breakdown instead
-// of hanging.  Per cell the sums run over neighbours in ascending index.
+// the NaN sentinel: the value is its own ready flag, so no fence is needed and
+// a reader polls exactly the word it consumes.  Polling is bounded: past the
+// limit the value is published as NaN, which the solver reports as a
+// breakdown instead of hanging.  Per cell the sums run over neighbours in
+// ascending index.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ bool dic_try(const double *a, int j, double &v)
@@ -1097,8 +1225,9 @@ __device__ __forceinline__ void dic_put(double *a, int i, double v)
 constexpr int kDicDeps = 8;
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
+__global__ void __launch_bounds__(kBlock) k_dic_sweep(Batch bt)
 {
+    CASE_OF(bt);
     if (d.ks[3].done) return;
     __shared__ int tile;
     if (threadIdx.x == 0) tile = (int)atomicAdd(&d.ticket[1], 1u);
@@ -1195,7 +1324,7 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
     if (MODE == 2) {
         double v[1] = {part};
         __shared__ double tot[1];
-        if (reduce_last<1>(v, d.partials, d.red_stride, d.ticket, tot) && threadIdx.x == 0) {
+        if (reduce_last<1>(v, d, K, tot) && threadIdx.x == 0) {
             KState &s = d.ks[3];
             __hip_atomic_store(&d.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
@@ -1209,7 +1338,7 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
         __syncthreads();
         if (threadIdx.x == 0) {
             const unsigned int t = __hip_atomic_fetch_add(&d.ticket[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (t == gridDim.x - 1) {
+            if (t == (unsigned int)K.G - 1) {
                 __hip_atomic_store(&d.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&d.ticket[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -1217,15 +1346,10 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(DevCase d)
     }
 }
 
-__global__ void k_fill_sentinel(double *a, long n)
+__global__ void k_dic_reset(Batch bt)
 {
-    const long i = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) clear_word(a, (int)i);
-}
-
-__global__ void k_dic_reset(DevCase d)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
     if (i == 0) {
         d.ks[3].done = 0;
         d.ks[3].iters = 0;
@@ -1237,232 +1361,472 @@ __global__ void k_dic_reset(DevCase d)
     clear_word(d.z, i);
 }
 
-__global__ void k_set_ctl(KState *ks, int first, int count, double tol, double rel_tol, int max_iter)
+// ---------------------------------------------------------------------------
+// Mixed precision
+//
+// Pressure (CG): the FP32 recurrence runs uninterrupted (FP32 matrix in
+// difference form, r, p, q; FP64 sums and dots) while the solution is
+// accumulated in FP64 (x += alpha p); whenever the recurrence residual has
+// fallen 10x since the last replacement it is replaced by the true FP64
+// residual b - A x, and convergence is decided on that true residual: when
+// the recurrence residual reaches the tolerance (or the iteration limit is
+// reached) the iteration pauses (done = 2) and the replacement that follows
+// the same iteration checks it.
+// Restarting an FP32 CG from each refined residual instead would throw its
+// Krylov space away, which on these pressure systems multiplies the
+// iteration count several times over.
+//
+// Momentum (BiCG, a few iterations per solve): FP64 iterative refinement
+// around FP32 BiCG solves of A e = s r to a relative reduction eta
+// (s = N / sum|r| keeps the demoted residual O(1)), x += e / s.
+// States: ks[0..3] the FP64 solves, ks[4..6] the FP32 momentum inner solves.
+// ---------------------------------------------------------------------------
+
+// FP32 copies of the assembled matrix values (the topology is shared)
+__global__ void k_mx_cvt(Batch bt, int kind)
 {
-    const int k = threadIdx.x;
-    if (k >= count) return;
-    ks[first + k].tol = tol;
-    ks[first + k].rel_tol = rel_tol;
-    ks[first + k].max_iter = max_iter;
+    CASE_OF(bt);
+    const int t = K.raw * kBlock + threadIdx.x;
+    if (kind == 1) {
+        if (t < d.N) {
+            d.f_pdiag[t] = (float)d.pdiag[t];
+            d.f_pexc[t] = (float)row_sum(d, t, d.pdiag, d.poff, d.poff);
+        }
+        if (t < d.Fi) d.f_poff[t] = (float)d.poff[t];
+    } else {
+        if (t < d.N) d.f_diag[t] = (float)d.mdiag[t];
+        if (t < d.Fi) { d.f_up[t] = (float)d.upper[t]; d.f_lo[t] = (float)d.lower[t]; }
+    }
 }
 
-__global__ void k_set_patch(DevCase d, int pt, double u0, double u1, double u2, double pv)
+// ---- pressure: FP32 recurrence, FP64 solution ---------------------------
+
+// start: r32 = r64 (from the FP64 start kernel), rho = r32.(r32/diag32)
+__global__ void __launch_bounds__(kBlock) k_rr_start(Batch bt)
 {
-    if (threadIdx.x != 0) return;
-    d.patch_uv[3 * pt] = u0;
-    d.patch_uv[3 * pt + 1] = u1;
-    d.patch_uv[3 * pt + 2] = u2;
-    d.patch_pv[pt] = pv;
+    CASE_OF(bt);
+    if (d.ks[3].done) return;
+    const Range rg = block_range(d.N, K);
+    double acc[1] = {0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const float r = (float)d.r[i];
+        d.f_r[i] = r;
+        acc[0] += (double)r * (double)(r / d.f_pdiag[i]);
+    }
+    __shared__ double tot[1];
+    if (reduce_last<1>(acc, d, K, tot) && threadIdx.x == 0) {
+        KState &s = d.ks[3];
+        s.scale = s.nres;     // recurrence residual at the last replacement
+        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+        else s.rho = tot[0];
+    }
 }
 
-inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+// x64 += alpha p32, r32 -= alpha q32; |r32| and rho (FP64 accumulation)
+__global__ void __launch_bounds__(kBlock) k_rr_update(Batch bt)
+{
+    CASE_OF(bt);
+    if (d.ks[3].done) return;
+    const double al = d.ks[3].alpha;
+    const float alf = (float)al;
+    const Range rg = block_range(d.N, K);
+    double acc[2] = {0.0, 0.0};
+    double *__restrict__ x = d.p;
+    const float *__restrict__ p = d.f_p;
+    const float *__restrict__ q = d.f_q;
+    float *__restrict__ r = d.f_r;
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        x[i] += al * (double)p[i];
+        const float ri = r[i] - alf * q[i];
+        r[i] = ri;
+        acc[0] += fabs((double)ri);
+        acc[1] += (double)ri * (double)(ri / d.f_pdiag[i]);
+    }
+    __shared__ double tot[2];
+    if (reduce_last<2>(acc, d, K, tot) && threadIdx.x == 0) {
+        KState &s = d.ks[3];
+        s.iters += 1;
+        s.nres = tot[0] / s.nf;
+        s.first = 0;
+        s.xbar = s.rho;   // rho of the previous iteration (for a replacement)
+        if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
+        else if (s.nres <= s.tol_eff || s.iters >= s.max_iter) s.done = 2;   // verify on the true residual
+        else if (!(tot[1] > 0.0) || !isfinite(tot[1])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else {
+            s.beta = tot[1] / s.rho;
+            s.rho = tot[1];
+        }
+    }
+}
+
+// residual replacement: r64 = b - A64 x64; r32 = r64; taken when the
+// iteration is paused or the recurrence residual fell 10x since the last
+// replacement; rho and beta continue from the true residual
+__global__ void __launch_bounds__(kBlock) k_rr_replace(Batch bt)
+{
+    CASE_OF(bt);
+    const KState &s0 = d.ks[3];
+    if (s0.done == 1) return;
+    if (s0.done == 0 && !(s0.nres < 0.1 * s0.scale)) return;
+    const Range rg = block_range(d.N, K);
+    double acc[2] = {0.0, 0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const double r = d.pb[i] - row_apply<double>(d, i, d.pdiag, d.poff, d.poff, d.p);
+        const float rf = (float)r;
+        d.f_r[i] = rf;
+        acc[0] += fabs(r);
+        acc[1] += (double)rf * (double)(rf / d.f_pdiag[i]);
+    }
+    __shared__ double tot[2];
+    if (reduce_last<2>(acc, d, K, tot) && threadIdx.x == 0) {
+        KState &s = d.ks[3];
+        const double nres = tot[0] / s.nf;
+        s.nres = nres;
+        s.scale = nres;
+        if (!isfinite(nres)) set_done(s, FVM_ENUMERIC);
+        else if (nres <= s.tol_eff) set_done(s, FVM_OK);
+        else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+        else if (!(tot[1] > 0.0) || !isfinite(tot[1])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else {
+            s.beta = s.first ? 0.0 : tot[1] / s.xbar;
+            s.rho = tot[1];
+            s.done = 0;
+        }
+    }
+}
+
+// FP32 pressure update step of the recurrence: p = z + beta p is k_cg_dir<float>;
+// q = A32 p is k_cg_spmv<float>
+
+// ---- momentum: FP64 refinement around restarted FP32 BiCG ----------------
+
+__device__ __forceinline__ double mx_scale(const KState &o, int N) { return (double)N / (o.nres * o.nf); }
+
+// inner start: r_in = s r (FP32), e = 0, inner normalisation sum|r_in|,
+// rho = (r_in/diag).r_in
+__global__ void __launch_bounds__(kBlock) k_mx_inner_init(Batch bt)
+{
+    CASE_OF(bt);
+    int act[3];
+    double sc[3];
+    for (int c = 0; c < 3; ++c) {
+        act[c] = !d.ks[c].done;
+        sc[c] = act[c] ? mx_scale(d.ks[c], d.N) : 0.0;
+    }
+    if (!act[0] && !act[1] && !act[2]) {
+        if (K.raw == 0 && threadIdx.x == 0)
+            for (int c = 0; c < 3; ++c) { set_done(d.ks[4 + c], FVM_OK); d.ks[4 + c].iters = 0; }
+        return;
+    }
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const float dg = d.f_diag[i];
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const long j = c * N + i;
+            const float r = (float)(sc[c] * d.r[j]);
+            d.f_r[j] = r;
+            d.f_rt[j] = r;
+            d.f_x[j] = 0.0f;
+            v[c] += fabs((double)r);
+            v[3 + c] += (double)(r / dg) * (double)r;
+        }
+    }
+    __shared__ double tot[6];
+    if (reduce_last<6>(v, d, K, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            KState &s = d.ks[4 + c];
+            if (!act[c]) { set_done(s, FVM_OK); s.iters = 0; continue; }
+            s.nf = tot[c];
+            s.nres0 = 1.0;
+            s.nres = 1.0;
+            s.tol_eff = fmax(s.tol, s.rel_tol);
+            s.iters = 0;
+            s.done = 0;
+            s.status = FVM_OK;
+            s.first = 1;
+            s.beta = 0.0;
+            if (!isfinite(tot[c]) || !(tot[c] > 0.0)) set_done(s, FVM_ENUMERIC);
+            else if (tot[3 + c] == 0.0 || !isfinite(tot[3 + c])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+            else s.rho = tot[3 + c];
+        }
+    }
+}
+
+// x += e / s (FP64), for the components whose outer loop is still running
+__global__ void k_mx_correct(Batch bt)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    for (int c = 0; c < 3; ++c) {
+        const KState &o = d.ks[c];
+        if (o.done) continue;
+        const double s = mx_scale(o, d.N);
+        const long j = (long)c * d.N + i;
+        d.U[j] += (double)d.f_x[j] / s;
+    }
+}
+
+// outer residual after a correction: r = b - A x (FP64), nres, stop test;
+// the inner iterations are added to the outer count
+__global__ void __launch_bounds__(kBlock) k_mx_resid(Batch bt)
+{
+    CASE_OF(bt);
+    int act[3];
+    for (int c = 0; c < 3; ++c) act[c] = !d.ks[c].done;
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
+    double v[3] = {0, 0, 0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const long j = c * N + i;
+            const double r = d.rhs[j] - row_apply<double>(d, i, d.mdiag, d.upper, d.lower, d.U + c * N);
+            d.r[j] = r;
+            v[c] += fabs(r);
+        }
+    }
+    __shared__ double tot[3];
+    if (reduce_last<3>(v, d, K, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &o = d.ks[c];
+            const KState &in = d.ks[4 + c];
+            o.iters += in.iters;
+            o.nres = tot[c] / o.nf;
+            if (in.status == FVM_ENUMERIC || !isfinite(o.nres)) set_done(o, FVM_ENUMERIC);
+            else if (o.nres <= o.tol_eff) set_done(o, FVM_OK);
+            else if (o.iters >= o.max_iter) set_done(o, FVM_WARN_MAXITER);
+        }
+    }
+}
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Host side: batch descriptors and launchers
 // ---------------------------------------------------------------------------
 
-int grid_for(int n)
+int blocks_for(int n)
 {
-    int g = cdiv(n, kBlock);
-    if (g > kMaxGrid) g = kMaxGrid;
-    if (g >= 8) g = g / 8 * 8;
-    return g < 1 ? 1 : g;
+    const int g = cdiv(n, kBlock);
+    return g < 1 ? 8 : (g + 7) / 8 * 8;
 }
 
-#define LAUNCH_N(kern, n, s, ...)                                                             \
-    do {                                                                                      \
-        if ((n) > 0) hipLaunchKernelGGL(kern, dim3(cdiv((n), kBlock)), dim3(kBlock), 0, s, __VA_ARGS__); \
-    } while (0)
-#define LAUNCH_R(kern, n, s, ...) hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(kBlock), 0, s, __VA_ARGS__)
+int grid_for(int n) { return blocks_for(n); }
 
-void launch_geometry(const DevCase &d, hipStream_t s) { LAUNCH_N(k_geometry, d.F, s, d); }
-void launch_flux_from_U(const DevCase &d, hipStream_t s) { LAUNCH_N(k_flux_from_U, d.F, s, d); }
-void launch_U_in(const DevCase &d, const double *U, hipStream_t s) { LAUNCH_N(k_U_in, d.N, s, d, U); }
-void launch_U_out(const DevCase &d, double *U, hipStream_t s) { LAUNCH_N(k_U_out, d.N, s, d, U); }
-void launch_phi_in(const DevCase &d, const double *phi, hipStream_t s) { LAUNCH_N(k_phi_in, d.F, s, d, phi); }
-void launch_phi_out(const DevCase &d, double *phi, hipStream_t s) { LAUNCH_N(k_phi_out, d.F, s, d, phi); }
-void launch_gather_faces(const DevCase &d, const double *uv, double *out, hipStream_t s)
+void batch_add(BatchSet &bs, const DevCase *dev, const DevCase *host)
 {
-    LAUNCH_N(k_gather_faces, d.F, s, d, uv, out);
-}
-
-void launch_gradU(const DevCase &d, hipStream_t s) { LAUNCH_N(k_gradU, d.N, s, d); }
-void launch_mom_face(const DevCase &d, double nu, int upwind, hipStream_t s)
-{
-    prof_begin("mom_face", s);
-    LAUNCH_N(k_mom_face, d.Fi, s, d, nu, upwind);
-    prof_end("mom_face", s);
-}
-void launch_mom_cell(const DevCase &d, double nu, double dt, double alpha_u, int upwind, hipStream_t s)
-{
-    prof_begin("mom_cell", s);
-    LAUNCH_N(k_mom_cell, d.N, s, d, nu, dt, alpha_u, upwind);
-    prof_end("mom_cell", s);
-}
-void launch_hbya(const DevCase &d, int with_gradp, hipStream_t s)
-{
-    prof_begin("hbya", s);
-    LAUNCH_N(k_hbya, d.N, s, d, with_gradp);
-    prof_end("hbya", s);
-}
-void launch_gradp(const DevCase &d, hipStream_t s) { LAUNCH_N(k_gradp, d.N, s, d); }
-void launch_p_face(const DevCase &d, hipStream_t s)
-{
-    prof_begin("p_face", s);
-    LAUNCH_N(k_p_face, d.F, s, d);
-    prof_end("p_face", s);
-}
-void launch_p_cell(const DevCase &d, double p_ref, hipStream_t s)
-{
-    prof_begin("p_cell", s);
-    LAUNCH_N(k_p_cell, d.N, s, d, p_ref, 1);
-    prof_end("p_cell", s);
-}
-void launch_p_system_from_gamma(const DevCase &d, const double *gam, const double *rhs, double p_ref, hipStream_t s)
-{
-    LAUNCH_N(k_p_face_gamma, d.F, s, d, gam);
-    (void)hipMemcpyAsync(d.pb, rhs, sizeof(double) * (size_t)d.N, hipMemcpyDeviceToDevice, s);
-    LAUNCH_N(k_p_cell, d.N, s, d, p_ref, 0);
-}
-void launch_flux_corr(const DevCase &d, hipStream_t s)
-{
-    prof_begin("flux_corr", s);
-    LAUNCH_N(k_flux_corr, d.F, s, d);
-    prof_end("flux_corr", s);
-}
-void launch_p_relax(const DevCase &d, double alpha_p, hipStream_t s) { LAUNCH_N(k_p_relax, d.N, s, d, alpha_p); }
-void launch_U_corr(const DevCase &d, hipStream_t s)
-{
-    prof_begin("U_corr", s);
-    LAUNCH_N(k_U_corr, d.N, s, d);
-    prof_end("U_corr", s);
-}
-
-void launch_bicg_init(const DevCase &d, hipStream_t s)
-{
-    LAUNCH_R(k_bicg_sumx, d.N, s, d);
-    LAUNCH_R(k_bicg_init, d.N, s, d);
-}
-
-static BiView<double> bi64(const DevCase &d)
-{
-    return BiView<double>{d.mdiag, d.upper, d.lower, d.U, d.r, d.rt, d.pp, d.pt, d.q, d.qt, d.ks};
-}
-
-static BiView<float> bi32(const DevCase &d)
-{
-    return BiView<float>{d.f_diag, d.f_up, d.f_lo, d.f_x, d.f_r, d.f_rt, d.f_p, d.f_pt, d.f_q, d.f_qt, d.ks + 4};
-}
-
-static CGView<double> cg64(const DevCase &d, int dic)
-{
-    return CGView<double>{d.pdiag, d.poff, d.p, d.r, d.pp, d.q, dic ? d.z : nullptr, d.ks + 3};
-}
-
-static CGView<float> cg32(const DevCase &d)
-{
-    return CGView<float>{d.f_pdiag, d.f_poff, d.f_x, d.f_r, d.f_p, d.f_q, nullptr, d.ks + 7};
-}
-
-void launch_bicg_iter(const DevCase &d, hipStream_t s)
-{
-    const BiView<double> v = bi64(d);
-    LAUNCH_N(k_bicg_dir<double>, d.N, s, d, v);
-    prof_begin("bicg_spmv", s);
-    LAUNCH_R(k_bicg_spmv<double>, d.N, s, d, v);
-    prof_end("bicg_spmv", s);
-    LAUNCH_R(k_bicg_update<double>, d.N, s, d, v);
-}
-
-void launch_pcg_init(const DevCase &d, int dic, hipStream_t s)
-{
-    LAUNCH_R(k_pcg_sumx, d.N, s, d);
-    LAUNCH_R(k_pcg_init, d.N, s, d, dic);
-}
-
-void launch_mx_cvt(const DevCase &d, int kind, hipStream_t s)
-{
-    LAUNCH_N(k_mx_cvt, d.N > d.Fi ? d.N : d.Fi, s, d, kind);
-}
-
-void launch_mx_inner_init(const DevCase &d, int kind, hipStream_t s) { LAUNCH_R(k_mx_inner_init, d.N, s, d, kind); }
-
-void launch_mx_inner_iter(const DevCase &d, int kind, hipStream_t s)
-{
-    if (kind == 1) {
-        const CGView<float> v = cg32(d);
-        prof_begin("pcg32_dir", s);
-        LAUNCH_N(k_cg_dir<float>, d.N, s, d, v);
-        prof_end("pcg32_dir", s);
-        prof_begin("pcg32_spmv", s);
-        LAUNCH_R(k_cg_spmv<float>, d.N, s, d, v);
-        prof_end("pcg32_spmv", s);
-        prof_begin("pcg32_update", s);
-        LAUNCH_R(k_cg_update<float>, d.N, s, d, v, 0);
-        prof_end("pcg32_update", s);
-    } else {
-        const BiView<float> v = bi32(d);
-        LAUNCH_N(k_bicg_dir<float>, d.N, s, d, v);
-        prof_begin("bicg32_spmv", s);
-        LAUNCH_R(k_bicg_spmv<float>, d.N, s, d, v);
-        prof_end("bicg32_spmv", s);
-        LAUNCH_R(k_bicg_update<float>, d.N, s, d, v);
+    const int c = bs.n;
+    for (int k = 0; k < SZ_KINDS; ++k) {
+        Batch &b = bs.b[k];
+        b.dc[c] = dev;
+        if (c == 0) b.start[0] = 0;
+        const int n = k == SZ_CELL ? host->N : k == SZ_FACE ? host->F : k == SZ_FACEI ? host->Fi
+                                                                                      : (host->N > host->Fi ? host->N : host->Fi);
+        b.start[c + 1] = b.start[c] + blocks_for(n);
+        b.n = c + 1;
     }
+    bs.host[c] = host;
+    bs.n = c + 1;
 }
 
-void launch_mx_correct_resid(const DevCase &d, int kind, hipStream_t s)
+namespace {
+template <class... P, class... A>
+void run(void (*kern)(Batch, P...), const BatchSet &bs, int kind, hipStream_t s, A... args)
 {
-    LAUNCH_N(k_mx_correct, d.N, s, d, kind);
-    LAUNCH_R(k_mx_resid, d.N, s, d, kind);
+    const Batch &b = bs.b[kind];
+    hipLaunchKernelGGL(kern, dim3(b.start[b.n]), dim3(kBlock), 0, s, b, static_cast<P>(args)...);
 }
 
-void launch_dic_precond(const DevCase &d, int with_setup, hipStream_t s)
+struct Prof {
+    const char *c;
+    hipStream_t s;
+    Prof(const char *cls, hipStream_t st) : c(cls), s(st) { prof_begin(c, s); }
+    ~Prof() { prof_end(c, s); }
+};
+}  // namespace
+
+void launch_geometry(const BatchSet &bs, hipStream_t s) { run(k_geometry, bs, SZ_FACE, s); }
+void launch_flux_from_U(const BatchSet &bs, hipStream_t s) { run(k_flux_from_U, bs, SZ_FACE, s); }
+void launch_U_in(const BatchSet &bs, const double *U, hipStream_t s) { run(k_U_in, bs, SZ_CELL, s, U); }
+void launch_U_out(const BatchSet &bs, double *U, hipStream_t s) { run(k_U_out, bs, SZ_CELL, s, U); }
+void launch_phi_in(const BatchSet &bs, const double *phi, hipStream_t s) { run(k_phi_in, bs, SZ_FACE, s, phi); }
+void launch_phi_out(const BatchSet &bs, double *phi, hipStream_t s) { run(k_phi_out, bs, SZ_FACE, s, phi); }
+void launch_gather_faces(const BatchSet &bs, const double *uv, double *out, hipStream_t s)
 {
-    const int g = cdiv(d.N, kBlock);
+    run(k_gather_faces, bs, SZ_FACE, s, uv, out);
+}
+void launch_p_system_from_gamma(const BatchSet &bs, const double *gam, const double *rhs, hipStream_t s)
+{
+    run(k_p_face_gamma, bs, SZ_FACE, s, gam);
+    (void)hipMemcpyAsync(bs.host[0]->pb, rhs, sizeof(double) * (size_t)bs.host[0]->N, hipMemcpyDeviceToDevice, s);
+    run(k_p_cell, bs, SZ_CELL, s, 0);
+}
+void launch_init_partials(const BatchSet &bs, hipStream_t s) { run(k_fill_sentinel, bs, SZ_CELL, s); }
+void launch_set_patch(const BatchSet &bs, int patch, double u0, double u1, double u2, double pv, hipStream_t s)
+{
+    run(k_set_patch, bs, SZ_CELL, s, patch, u0, u1, u2, pv);
+}
+
+void launch_save(const BatchSet &bs, int restore, hipStream_t s)
+{
+    // 4N + F words per case: sized by the larger of the two kinds below
+    BatchSet t = bs;
+    Batch &b = t.b[SZ_CELL];
+    b.start[0] = 0;
+    for (int c = 0; c < bs.n; ++c) b.start[c + 1] = b.start[c] + blocks_for(4 * bs.host[c]->N + bs.host[c]->F);
+    run(k_save, t, SZ_CELL, s, restore);
+}
+
+void launch_gradU(const BatchSet &bs, hipStream_t s) { run(k_gradU, bs, SZ_CELL, s); }
+void launch_mom_face(const BatchSet &bs, hipStream_t s)
+{
+    Prof p("mom_face", s);
+    run(k_mom_face, bs, SZ_FACEI, s);
+}
+void launch_mom_cell(const BatchSet &bs, int mode, hipStream_t s)
+{
+    Prof p("mom_cell", s);
+    run(k_mom_cell, bs, SZ_CELL, s, mode);
+}
+void launch_hbya(const BatchSet &bs, int with_gradp, hipStream_t s)
+{
+    Prof p("hbya", s);
+    run(k_hbya, bs, SZ_CELL, s, with_gradp);
+}
+void launch_gradp(const BatchSet &bs, hipStream_t s) { run(k_gradp, bs, SZ_CELL, s); }
+void launch_p_face(const BatchSet &bs, hipStream_t s)
+{
+    Prof p("p_face", s);
+    run(k_p_face, bs, SZ_FACE, s);
+}
+void launch_p_cell(const BatchSet &bs, hipStream_t s)
+{
+    Prof p("p_cell", s);
+    run(k_p_cell, bs, SZ_CELL, s, 1);
+}
+void launch_flux_corr(const BatchSet &bs, hipStream_t s)
+{
+    Prof p("flux_corr", s);
+    run(k_flux_corr, bs, SZ_FACE, s);
+}
+void launch_p_relax(const BatchSet &bs, hipStream_t s) { run(k_p_relax, bs, SZ_CELL, s); }
+void launch_U_corr(const BatchSet &bs, hipStream_t s)
+{
+    Prof p("U_corr", s);
+    run(k_U_corr, bs, SZ_CELL, s);
+}
+
+void launch_set_ctl(const BatchSet &bs, int first, int count, int src, double tol, double rel_tol, int max_iter,
+                    hipStream_t s)
+{
+    run(k_set_ctl, bs, SZ_CELL, s, first, count, src, tol, rel_tol, max_iter);
+}
+void launch_gather_ks(const BatchSet &bs, hipStream_t s) { run(k_gather_ks, bs, SZ_CELL, s); }
+
+void launch_bicg_init(const BatchSet &bs, hipStream_t s)
+{
+    run(k_bicg_sumx, bs, SZ_CELL, s);
+    run(k_bicg_init, bs, SZ_CELL, s);
+}
+
+void launch_bicg_iter(const BatchSet &bs, hipStream_t s)
+{
+    run(k_bicg_dir<double>, bs, SZ_CELL, s);
+    {
+        Prof p("bicg_spmv", s);
+        run(k_bicg_spmv<double>, bs, SZ_CELL, s);
+    }
+    run(k_bicg_update<double>, bs, SZ_CELL, s);
+}
+
+void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s)
+{
+    run(k_pcg_sumx, bs, SZ_CELL, s);
+    run(k_pcg_init, bs, SZ_CELL, s, dic);
+}
+
+void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s)
+{
     if (with_setup) {
-        prof_begin("dic_setup", s);
-        hipLaunchKernelGGL(k_dic_sweep<0>, dim3(g), dim3(kBlock), 0, s, d);
-        prof_end("dic_setup", s);
+        Prof p("dic_setup", s);
+        run(k_dic_sweep<0>, bs, SZ_CELL, s);
     }
-    prof_begin("dic_fwd", s);
-    hipLaunchKernelGGL(k_dic_sweep<1>, dim3(g), dim3(kBlock), 0, s, d);
-    prof_end("dic_fwd", s);
-    prof_begin("dic_bwd", s);
-    hipLaunchKernelGGL(k_dic_sweep<2>, dim3(g), dim3(kBlock), 0, s, d);
-    prof_end("dic_bwd", s);
+    {
+        Prof p("dic_fwd", s);
+        run(k_dic_sweep<1>, bs, SZ_CELL, s);
+    }
+    {
+        Prof p("dic_bwd", s);
+        run(k_dic_sweep<2>, bs, SZ_CELL, s);
+    }
 }
 
-void launch_dic_reset(const DevCase &d, hipStream_t s) { LAUNCH_N(k_dic_reset, d.N, s, d); }
+void launch_dic_reset(const BatchSet &bs, hipStream_t s) { run(k_dic_reset, bs, SZ_CELL, s); }
 
-void launch_init_partials(const DevCase &d, hipStream_t s)
+void launch_pcg_iter(const BatchSet &bs, int dic, hipStream_t s)
 {
-    const long n = (long)kMaxRed * d.red_stride;
-    hipLaunchKernelGGL(k_fill_sentinel, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, d.partials, n);
+    {
+        Prof p("pcg_dir", s);
+        run(k_cg_dir<double>, bs, SZ_CELL, s, dic);
+    }
+    {
+        Prof p("pcg_spmv", s);
+        run(k_cg_spmv<double>, bs, SZ_CELL, s, dic);
+    }
+    {
+        Prof p("pcg_update", s);
+        run(k_cg_update, bs, SZ_CELL, s, dic);
+    }
+    if (dic) launch_dic_precond(bs, 0, s);
 }
 
-void launch_pcg_iter(const DevCase &d, int dic, hipStream_t s)
+void launch_mx_cvt(const BatchSet &bs, int kind, hipStream_t s) { run(k_mx_cvt, bs, SZ_MAXNF, s, kind); }
+void launch_mx_inner_init(const BatchSet &bs, int, hipStream_t s) { run(k_mx_inner_init, bs, SZ_CELL, s); }
+void launch_mx_inner_iter(const BatchSet &bs, int, hipStream_t s)
 {
-    const CGView<double> v = cg64(d, dic);
-    prof_begin("pcg_dir", s);
-    LAUNCH_N(k_cg_dir<double>, d.N, s, d, v);
-    prof_end("pcg_dir", s);
-    prof_begin("pcg_spmv", s);
-    LAUNCH_R(k_cg_spmv<double>, d.N, s, d, v);
-    prof_end("pcg_spmv", s);
-    prof_begin("pcg_update", s);
-    LAUNCH_R(k_cg_update<double>, d.N, s, d, v, dic);
-    prof_end("pcg_update", s);
-    if (dic) launch_dic_precond(d, 0, s);
+    run(k_bicg_dir<float>, bs, SZ_CELL, s);
+    {
+        Prof p("bicg32_spmv", s);
+        run(k_bicg_spmv<float>, bs, SZ_CELL, s);
+    }
+    run(k_bicg_update<float>, bs, SZ_CELL, s);
+}
+void launch_mx_correct_resid(const BatchSet &bs, int, hipStream_t s)
+{
+    run(k_mx_correct, bs, SZ_CELL, s);
+    run(k_mx_resid, bs, SZ_CELL, s);
 }
 
-void launch_set_ctl(const DevCase &d, int first, int count, double tol, double rel_tol, int max_iter, hipStream_t s)
+void launch_rr_start(const BatchSet &bs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, s, d.ks, first, count, tol, rel_tol, max_iter);
+    run(k_mx_cvt, bs, SZ_MAXNF, s, 1);
+    run(k_rr_start, bs, SZ_CELL, s);
 }
 
-void launch_set_patch(const DevCase &d, int patch, double u0, double u1, double u2, double pv, hipStream_t s)
+void launch_rr_iter(const BatchSet &bs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_patch, dim3(1), dim3(64), 0, s, d, patch, u0, u1, u2, pv);
+    {
+        Prof p("pcg32_dir", s);
+        run(k_cg_dir<float>, bs, SZ_CELL, s, 0);
+    }
+    {
+        Prof p("pcg32_spmv", s);
+        run(k_cg_spmv<float>, bs, SZ_CELL, s, 0);
+    }
+    {
+        Prof p("pcg32_update", s);
+        run(k_rr_update, bs, SZ_CELL, s);
+    }
+}
+
+void launch_rr_replace(const BatchSet &bs, hipStream_t s)
+{
+    Prof p("pcg_replace", s);
+    run(k_rr_replace, bs, SZ_CELL, s);
 }

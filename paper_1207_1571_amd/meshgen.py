@@ -98,6 +98,41 @@ def _fan_geometry(P: np.ndarray, quads: np.ndarray) -> Tuple[np.ndarray, np.ndar
     return Sf, Cf
 
 
+def _uniform_box(nx, ny, nz, lengths, origin, owner, own_i, nei_i, b_own, p_start, p_size, I, J, K) -> "Mesh":
+    """Closed-form geometry of a uniform, axis-aligned box mesh (the same
+    quantities the triangle-fan / pyramid construction gives, without the
+    per-vertex work)."""
+    h = np.array([lengths[0] / nx, lengths[1] / ny, lengths[2] / nz])
+    org = np.asarray(origin, dtype=np.float64)
+    N = nx * ny * nz
+    ijk = np.stack([I, J, K], axis=1).astype(np.float64)
+    C = org + (ijk + 0.5) * h
+    V = np.full(N, h[0] * h[1] * h[2])
+    area = np.array([h[1] * h[2], h[0] * h[2], h[0] * h[1]])
+    Fi = own_i.shape[0]
+    d = nei_i - own_i
+    axis = np.where(d == 1, 0, np.where(d == nx, 1, 2))
+    if nx == 1:
+        axis = np.where(d == nx * ny, 2, 1) if ny > 1 else np.full(Fi, 2)
+    if nx > 1 and ny == 1:
+        axis = np.where(d == 1, 0, 2)
+    Sf_i = np.zeros((Fi, 3))
+    Sf_i[np.arange(Fi), axis] = area[axis]
+    Cf_i = C[own_i].copy()
+    Cf_i[np.arange(Fi), axis] += 0.5 * h[axis]
+    Sf_b, Cf_b = [], []
+    for side, cells in zip(SIDES, b_own):
+        ax = "xyz".index(side[0])
+        sgn = -1.0 if side.endswith("min") else 1.0
+        S = np.zeros((cells.shape[0], 3)); S[:, ax] = sgn * area[ax]
+        Cf = C[cells].copy(); Cf[:, ax] += sgn * 0.5 * h[ax]
+        Sf_b.append(S); Cf_b.append(Cf)
+    return Mesh(owner=owner, neighbour=nei_i.astype(np.int32), Sf=np.concatenate([Sf_i] + Sf_b),
+                Cf=np.concatenate([Cf_i] + Cf_b), C=C, V=V, patch_names=list(SIDES),
+                patch_start=np.array(p_start, np.int32), patch_size=np.array(p_size, np.int32),
+                shape=(nx, ny, nz), lengths=tuple(float(x) for x in lengths), lex_of_cell=np.arange(N, dtype=np.int64))
+
+
 def box_mesh(nx: int, ny: int, nz: int,
              lengths: Tuple[float, float, float] = (1.0, 1.0, 1.0),
              origin: Tuple[float, float, float] = (0.0, 0.0, 0.0),
@@ -196,6 +231,8 @@ def box_mesh(nx: int, ny: int, nz: int,
 
     owner = np.concatenate([own_i] + b_own).astype(np.int32)
     quads = np.concatenate([quad_i] + b_quad)
+    if jitter == 0.0 and grading is None:
+        return _uniform_box(nx, ny, nz, lengths, origin, owner, own_i, nei_i, b_own, p_start, p_size, I, J, K)
     Sf, Cf = _fan_geometry(Pf, quads)
 
     # cell geometry: pyramids on each face about the cell vertex mean
@@ -212,8 +249,9 @@ def box_mesh(nx: int, ny: int, nz: int,
         dC = Cf[sel] - mc[cc]
         pv = np.einsum("ij,ij->i", S, dC) / 3.0
         pc = mc[cc] + 0.75 * dC
-        np.add.at(V, cc, pv)
-        np.add.at(Cacc, cc, pv[:, None] * pc)
+        V += np.bincount(cc, weights=pv, minlength=N)
+        for k in range(3):
+            Cacc[:, k] += np.bincount(cc, weights=pv * pc[:, k], minlength=N)
     C = Cacc / V[:, None]
     return Mesh(owner=owner, neighbour=nei_i.astype(np.int32), Sf=Sf, Cf=Cf, C=C, V=V,
                 patch_names=list(SIDES), patch_start=np.array(p_start, np.int32),

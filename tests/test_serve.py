@@ -1,0 +1,191 @@
+"""Serving loop scheduling, against a fake backend on a virtual clock.
+
+The fake backend implements the same case API as the GPU backend
+(footprint / create / advance / finish); advancing a group of cases costs
+virtual time, so admission, arrival order, the memory budget and continuous
+batching can be checked exactly on the CPU.
+"""
+import dataclasses
+
+import pytest
+
+from paper_1207_1571_amd.serve import Request, Server, summarize
+
+
+@dataclasses.dataclass
+class _Mesh:
+    n_cells: int
+
+
+@dataclasses.dataclass
+class _Spec:
+    mesh: _Mesh
+
+
+class FakeBackend:
+    """Each group advance costs `step_cost` virtual seconds per step plus a
+    per-launch overhead; records residency to check the budget."""
+
+    def __init__(self, clock, bytes_per_cell=600, step_cost=1e-3, overhead=1e-4, fail_rid=None):
+        self.clock = clock
+        self.bpc = bytes_per_cell
+        self.step_cost = step_cost
+        self.overhead = overhead
+        self.fail_rid = fail_rid
+        self.resident = {}
+        self.max_resident_bytes = 0
+        self.max_resident_cases = 0
+        self.groups = []
+        self.created_at = {}
+
+    def footprint(self, spec):
+        return spec.mesh.n_cells * self.bpc
+
+    def create(self, spec):
+        case = object()
+        self.resident[id(case)] = self.footprint(spec)
+        self.created_at[id(case)] = self.clock.t
+        self.max_resident_bytes = max(self.max_resident_bytes, sum(self.resident.values()))
+        self.max_resident_cases = max(self.max_resident_cases, len(self.resident))
+        case_spec[id(case)] = spec
+        return case
+
+    def advance(self, cases, n_steps):
+        self.groups.append((self.clock.t, len(cases), n_steps))
+        self.clock.t += self.overhead + n_steps * self.step_cost
+        out = []
+        for c in cases:
+            rid = getattr(case_spec[id(c)], "rid", None)
+            st = -3 if rid is not None and rid == self.fail_rid else 0
+            out.append({"p": [{"iters": 5}] * n_steps, "status": st})
+        return out
+
+    def finish(self, case):
+        del self.resident[id(case)]
+        return None
+
+
+case_spec = {}
+
+
+class VClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+def _spec(n_cells, rid=None):
+    s = _Spec(_Mesh(n_cells))
+    if rid is not None:
+        s.rid = rid
+    return s
+
+
+def _server(backend, clock, budget, **kw):
+    return Server(backend, budget, clock=clock, sleep=clock.sleep, **kw)
+
+
+def test_all_requests_complete_and_latency_accounts_steps():
+    clk = VClock()
+    be = FakeBackend(clk)
+    reqs = [Request(i, 0.01 * i, _spec(1000 + 10 * i), 20) for i in range(12)]
+    res = _server(be, clk, 10**9, slots=4, group=2, chunk=5).run(reqs)
+    assert sorted(r.rid for r in res) == list(range(12))
+    for r in res:
+        assert r.admitted_s >= r.arrival_s
+        assert r.done_s > r.admitted_s
+        # every case needs at least n_steps steps of its own group
+        assert r.latency_s >= 20 * be.step_cost
+        assert r.p_iters == 5 * 20
+        assert r.status == 0
+    s = summarize(res)
+    assert s["n"] == 12 and s["failed"] == 0
+    assert s["p50_s"] <= s["p99_s"] <= s["max_s"]
+
+
+def test_arrivals_are_honoured():
+    clk = VClock()
+    be = FakeBackend(clk)
+    reqs = [Request(0, 0.0, _spec(100), 3), Request(1, 5.0, _spec(100), 3)]
+    res = {r.rid: r for r in _server(be, clk, 10**9).run(reqs)}
+    assert res[1].admitted_s >= 5.0
+    # the server was idle in between: request 0 finished long before
+    assert res[0].done_s < 1.0
+
+
+def test_budget_holds_requests_in_queue():
+    clk = VClock()
+    be = FakeBackend(clk, bytes_per_cell=1000)
+    # each case needs 1 MB, the budget holds two
+    reqs = [Request(i, 0.0, _spec(1000), 10) for i in range(6)]
+    res = _server(be, clk, 2_000_000, slots=32, group=8, chunk=10).run(reqs)
+    assert len(res) == 6
+    assert be.max_resident_bytes <= 2_000_000
+    assert be.max_resident_cases == 2
+    # later requests waited for memory to free up
+    adm = sorted(r.admitted_s for r in res)
+    assert adm[2] > adm[0]
+
+
+def test_request_larger_than_budget_is_rejected():
+    clk = VClock()
+    be = FakeBackend(clk, bytes_per_cell=1000)
+    with pytest.raises(ValueError):
+        _server(be, clk, 10_000).run([Request(0, 0.0, _spec(1000), 1)])
+
+
+def test_slots_limit_resident_cases():
+    clk = VClock()
+    be = FakeBackend(clk)
+    reqs = [Request(i, 0.0, _spec(100), 4) for i in range(10)]
+    _server(be, clk, 10**9, slots=3, group=3, chunk=2).run(reqs)
+    assert be.max_resident_cases == 3
+    assert all(g[1] <= 3 for g in be.groups)
+
+
+def test_continuous_batching_admits_while_others_run():
+    clk = VClock()
+    be = FakeBackend(clk, step_cost=1e-2)
+    # a long request first, then short ones arriving while it runs
+    reqs = [Request(0, 0.0, _spec(100), 100)] + [Request(i, 0.05 * i, _spec(100), 5) for i in range(1, 5)]
+    res = {r.rid: r for r in _server(be, clk, 10**9, slots=8, group=8, chunk=5).run(reqs)}
+    for i in range(1, 5):
+        # admitted before the long request finished, and finished before it
+        assert res[i].admitted_s < res[0].done_s
+        assert res[i].done_s < res[0].done_s
+    # shared launches: some group held more than one case
+    assert max(g[1] for g in be.groups) > 1
+
+
+def test_round_robin_serves_every_resident_case():
+    clk = VClock()
+    be = FakeBackend(clk)
+    reqs = [Request(i, 0.0, _spec(100), 6) for i in range(6)]
+    res = _server(be, clk, 10**9, slots=6, group=2, chunk=2).run(reqs)
+    # with groups of 2 over 6 resident cases, completion is interleaved,
+    # not one case after another: the first completion comes after at least
+    # one advance of every other pair
+    first_done = min(r.done_s for r in res)
+    assert first_done >= 3 * 2 * be.step_cost
+
+
+def test_failed_case_is_reported_and_released():
+    clk = VClock()
+    be = FakeBackend(clk, fail_rid=1)
+    reqs = [Request(i, 0.0, _spec(100, rid=i), 10) for i in range(3)]
+    res = {r.rid: r for r in _server(be, clk, 10**9, chunk=2).run(reqs)}
+    assert res[1].status < 0
+    assert res[0].status == 0 and res[2].status == 0
+    assert not be.resident
+    assert summarize(list(res.values()))["failed"] == 1
+
+
+def test_bad_server_parameters():
+    clk = VClock()
+    with pytest.raises(ValueError):
+        _server(FakeBackend(clk), clk, 10, slots=0)
