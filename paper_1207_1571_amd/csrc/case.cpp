@@ -196,6 +196,14 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
         d.f_rt = b.take<float>(3 * N); d.f_p = b.take<float>(3 * N); d.f_pt = b.take<float>(3 * N);
         d.f_q = b.take<float>(3 * N); d.f_qt = b.take<float>(3 * N);
     }
+    {
+        const size_t ns = (N + kBlock - 1) / kBlock, W = (size_t)m.sell_W;
+        d.sell_W = m.sell_W;
+        d.sell_mode = b.take<int32_t>(ns); d.sell_off = b.take<int32_t>(ns * W);
+        d.sell_fe = b.take<int32_t>(ns * W * kBlock); d.sell_col = b.take<int32_t>(ns * W * kBlock);
+        if (mixed) d.f_sell_val = b.take<float>(ns * W * kBlock);
+        else d.sell_val = b.take<double>(ns * W * kBlock);
+    }
     d.red_stride = (int32_t)(((N + kBlock - 1) / kBlock + 7) / 8 * 8);
     d.red_stride2 = (d.red_stride + kGroup - 1) / kGroup;
     d.partials = b.take<double>((size_t)kMaxRed * d.red_stride);
@@ -381,6 +389,8 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     UPCHK(up(d.tmpC, m->C, s));
     UPCHK(up(d.tmpCf, m->Cf, s));
     if (d.lvl_start) { UPCHK(up(d.lvl_start, m->lvl_start, s)); UPCHK(up(d.lvl_cells, m->lvl_cells, s)); }
+    UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s));
+    UPCHK(up(d.sell_fe, m->sell_fe, s)); UPCHK(up(d.sell_col, m->sell_col, s));
     UPCHK(hipMemsetAsync(d.ticket, 0, 64 * sizeof(unsigned int), s));
     UPCHK(hipMemsetAsync(d.gticket, 0, d.red_stride2 * sizeof(unsigned int), s));
     UPCHK(hipMemsetAsync(d.ks, 0, kNumKs * sizeof(KState), s));

@@ -38,6 +38,17 @@ struct fvm_mesh {
     // level schedule of the lower-triangular dependency graph (DIC sweeps):
     // cells of level l are lvl_cells[lvl_start[l] .. lvl_start[l+1])
     std::vector<int32_t> lvl_start, lvl_cells;
+    // row-sliced copy of the off-diagonal structure (sliced ELL): slice s =
+    // cells [256 s, 256 s + 256), sell_W slots per cell, entry (s, k, lane) at
+    // (s * sell_W + k) * 256 + lane; a cell's entries in ascending column.
+    // sell_fe: 2 f + 0 for an owned face f (coefficient multiplies the
+    // neighbour: upper), 2 f + 1 for a neighbour-side face (lower), -1 for
+    // padding.  A slice whose column offsets j - i take at most sell_W
+    // values is "regular" (sell_mode 0): slot k holds offset sell_off[s, k]
+    // for every cell of the slice and no column is stored; otherwise
+    // (sell_mode 1) columns are explicit in sell_col (padding: the cell).
+    int32_t sell_W = 0;
+    std::vector<int32_t> sell_mode, sell_off, sell_fe, sell_col;
 };
 
 // ---------------------------------------------------------------------------
@@ -108,6 +119,11 @@ struct DevCase {
     double *dstar;                               // [N] DIC diagonal
     int32_t *lvl_start, *lvl_cells;              // DIC level schedule
     int32_t n_levels;
+    // sliced-ELL copy of the pressure matrix (structure as in fvm_mesh)
+    int32_t sell_W;
+    int32_t *sell_mode, *sell_off, *sell_fe, *sell_col;
+    double *sell_val;                            // FP64 values (FP64 cases)
+    float *f_sell_val;                           // FP32 values (mixed cases)
     // FP32 copies (mixed precision)
     float *f_diag, *f_up, *f_lo, *f_pdiag, *f_poff;
     float *f_pexc;   // pressure row sums diag_i + sum_f off_f (FP64 sum, rounded)

@@ -728,7 +728,8 @@ enum { V_FP64 = 0, V_FP32 = 1 };
 template <class T>
 struct CGArr {
     const T *diag, *off;
-    const T *exc;   // FP32 only: row sums, for the difference form of A p
+    const T *exc;    // FP32 only: row sums, for the difference form of A p
+    const T *sval;   // sliced-ELL off-diagonal values
     T *x, *r, *p, *q;
     const double *z;
     KState *ks;
@@ -740,14 +741,14 @@ __device__ __forceinline__ CGArr<T> cg_arrays(const DevCase &d, int dic);
 template <>
 __device__ __forceinline__ CGArr<double> cg_arrays<double>(const DevCase &d, int dic)
 {
-    return CGArr<double>{d.pdiag, d.poff, nullptr, d.p, d.r, d.pp, d.q, dic ? d.z : nullptr, d.ks + 3};
+    return CGArr<double>{d.pdiag, d.poff, nullptr, d.sell_val, d.p, d.r, d.pp, d.q, dic ? d.z : nullptr, d.ks + 3};
 }
 
 // FP32 recurrence of the mixed-precision pressure CG (x is FP64: not here)
 template <>
 __device__ __forceinline__ CGArr<float> cg_arrays<float>(const DevCase &d, int)
 {
-    return CGArr<float>{d.f_pdiag, d.f_poff, d.f_pexc, d.f_x, d.f_r, d.f_p, d.f_q, nullptr, d.ks + 3};
+    return CGArr<float>{d.f_pdiag, d.f_poff, d.f_pexc, d.f_sell_val, d.f_x, d.f_r, d.f_p, d.f_q, nullptr, d.ks + 3};
 }
 
 template <class T>
@@ -984,41 +985,41 @@ __global__ void k_cg_dir(Batch bt, int dic)
     v.p[i] = s.first ? z : z + (T)s.beta * v.p[i];
 }
 
-// (A32 p)_i in difference form: sum_f off_f p_j + (exc_i - sum_f off_f) p_i,
-// with exc_i the FP64 row sum rounded once.  Rounding diag and off to FP32
-// separately would perturb every row sum by O(eps32 diag): on a pressure
-// system whose only non-zero row sums are a few boundary or reference cells
-// that moves the smallest eigenvalues by O(1) and stalls CG.  Here the FP32
-// operator is a graph Laplacian of the rounded face weights plus the rounded
-// row sums, spectrally within (1 +- eps32) of the FP64 one.  Products of
-// FP32 values are exact in FP64 and the sums are FP64.
-__device__ __forceinline__ float row_apply_diff(const DevCase &d, int i, const float *__restrict__ exc,
-                                                const float *__restrict__ off, const float *__restrict__ x)
+// Pressure matrix values into the sliced-ELL copy (start of every pressure
+// solve): FP64 cases fill sell_val, mixed cases the FP32 f_sell_val.  The
+// pressure matrix is symmetric: both sides of a face take poff.
+__global__ void __launch_bounds__(kBlock) k_sell_fill(Batch bt)
 {
-    double acc = 0.0, so = 0.0;
-    const int f0 = d.own_start[i], f1 = d.own_start[i + 1];
-    for (int f = f0; f < f1; ++f) {
-        acc += (double)off[f] * (double)x[d.nei[f]];
-        so += (double)off[f];
+    CASE_OF(bt);
+    const Range rg = block_range(d.N, K);
+    if (rg.beg >= rg.end) return;
+    const size_t base = (size_t)(rg.beg / kBlock) * d.sell_W * kBlock + threadIdx.x;
+    for (int k = 0; k < d.sell_W; ++k) {
+        const size_t e = base + (size_t)k * kBlock;
+        const int fe = d.sell_fe[e];
+        const double a = fe < 0 ? 0.0 : d.poff[fe >> 1];
+        if (d.f_sell_val) d.f_sell_val[e] = (float)a;
+        else d.sell_val[e] = a;
     }
-    const int k0 = d.nbr_start[i], k1 = d.nbr_start[i + 1];
-    for (int k = k0; k < k1; ++k) {
-        const int f = d.losort[k];
-        acc += (double)off[f] * (double)x[d.own[f]];
-        so += (double)off[f];
-    }
-    return (float)(acc + ((double)exc[i] - so) * (double)x[i]);
 }
 
-// q = A p, p.q -> alpha.  One block = 256 consecutive cells.  The products
-// of the block's owned faces and of its neighbour-side faces are formed by
-// face-parallel, coalesced passes into LDS; each cell then sums its faces
-// from LDS in the fixed order (owned faces, then neighbour-side faces).
-// Blocks whose face ranges exceed the staging buffers fall back to the
-// per-cell gather (same order, same result).  FP64: diag p_i + sum; FP32:
-// the difference form above.
-constexpr int kStage = 4 * kBlock;
-
+// q = A p, p.q -> alpha, on the sliced-ELL copy: one block = one slice of
+// 256 consecutive cells, one cell per thread; slot k of the slice is one
+// coalesced stream of coefficients, and in a regular slice the gathered
+// p[i + off_k] are consecutive too.  Padding entries hold 0 (their column
+// is clamped into the mesh).  The cell sums its entries in ascending
+// column order after the diagonal term.
+//
+// FP32 (mixed precision) uses the difference form
+//   (A32 p)_i = sum_k a_k p_j + (exc_i - sum_k a_k) p_i,
+// exc_i being the FP64 row sum rounded once.  Rounding the diagonal and the
+// off-diagonals to FP32 separately would perturb every row sum by
+// O(eps32 diag): on a pressure system whose only non-zero row sums are a few
+// boundary or reference cells that moves the smallest eigenvalues by O(1)
+// and stalls CG.  In difference form the FP32 operator is the graph
+// Laplacian of the rounded face weights plus the rounded row sums,
+// spectrally within (1 +- eps32) of the FP64 one.  Products of FP32 values
+// are exact in FP64 and the sums are FP64.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
 {
@@ -1026,59 +1027,39 @@ __global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
     CASE_OF(bt);
     const CGArr<T> v = cg_arrays<T>(d, dic);
     if (v.ks->done) return;
-    __shared__ double prodO[kStage], prodN[kStage];
-    __shared__ float offO[kDiff ? kStage : 1], offN[kDiff ? kStage : 1];
     const Range rg = block_range(d.N, K);
     const int i = rg.beg + threadIdx.x;
     double acc[1] = {0.0};
-    if (rg.beg < rg.end) {
+    if (i < rg.end) {
+        const int W = d.sell_W;
+        const int sl = rg.beg / kBlock;
+        const size_t base = (size_t)sl * W * kBlock + threadIdx.x;
+        const T *__restrict__ val = v.sval + base;
         const T *__restrict__ p = v.p;
-        const T *__restrict__ off = v.off;
-        const int *__restrict__ nei = d.nei;
-        const int *__restrict__ own = d.own;
-        const int *__restrict__ losort = d.losort;
-        const int F0 = d.own_start[rg.beg], F1 = d.own_start[rg.end];
-        const int K0 = d.nbr_start[rg.beg], K1 = d.nbr_start[rg.end];
-        const bool staged = F1 - F0 <= kStage && K1 - K0 <= kStage;
-        if (staged) {
-            for (int t = threadIdx.x; t < F1 - F0; t += kBlock) {
-                const int f = F0 + t;
-                const T a = off[f];
-                prodO[t] = (double)a * (double)p[nei[f]];
-                if (kDiff) offO[t] = (float)a;
+        const double pi = (double)p[i];
+        double qa = kDiff ? 0.0 : (double)v.diag[i] * pi, so = 0.0;
+        if (d.sell_mode[sl] == 0) {
+            const int *__restrict__ off = d.sell_off + (size_t)sl * W;
+            const int last = d.N - 1;
+#pragma unroll 6
+            for (int k = 0; k < W; ++k) {
+                const T a = val[(size_t)k * kBlock];
+                const int j = min(max(i + off[k], 0), last);
+                qa += (double)a * (double)p[j];
+                if (kDiff) so += (double)a;
             }
-            for (int t = threadIdx.x; t < K1 - K0; t += kBlock) {
-                const int f = losort[K0 + t];
-                const T a = off[f];
-                prodN[t] = (double)a * (double)p[own[f]];
-                if (kDiff) offN[t] = (float)a;
+        } else {
+            const int *__restrict__ col = d.sell_col + base;
+#pragma unroll 6
+            for (int k = 0; k < W; ++k) {
+                const T a = val[(size_t)k * kBlock];
+                qa += (double)a * (double)p[col[(size_t)k * kBlock]];
+                if (kDiff) so += (double)a;
             }
         }
-        __syncthreads();
-        if (i < rg.end) {
-            T q;
-            if (staged) {
-                const int a0 = d.own_start[i], a1 = d.own_start[i + 1];
-                const int b0 = d.nbr_start[i], b1 = d.nbr_start[i + 1];
-                if (kDiff) {
-                    double qa = 0.0, so = 0.0;
-                    for (int f = a0; f < a1; ++f) { qa += prodO[f - F0]; so += (double)offO[f - F0]; }
-                    for (int k = b0; k < b1; ++k) { qa += prodN[k - K0]; so += (double)offN[k - K0]; }
-                    q = (T)(qa + ((double)v.exc[i] - so) * (double)p[i]);
-                } else {
-                    double qa = (double)v.diag[i] * (double)p[i];
-                    for (int f = a0; f < a1; ++f) qa += prodO[f - F0];
-                    for (int k = b0; k < b1; ++k) qa += prodN[k - K0];
-                    q = (T)qa;
-                }
-            } else if constexpr (kDiff) {
-                q = row_apply_diff(d, i, v.exc, off, p);
-            } else {
-                q = row_apply<T>(d, i, v.diag, off, off, p);
-            }
-            v.q[i] = q;
-            acc[0] = (double)p[i] * (double)q;
-        }
+        const T q = kDiff ? (T)(qa + ((double)v.exc[i] - so) * pi) : (T)qa;
+        v.q[i] = q;
+        acc[0] = pi * (double)q;
     }
     __shared__ double tot[1];
     if (reduce_last<1>(acc, d, K, tot) && threadIdx.x == 0) {
@@ -1747,6 +1728,7 @@ void launch_bicg_iter(const BatchSet &bs, hipStream_t s)
 
 void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s)
 {
+    run(k_sell_fill, bs, SZ_CELL, s);
     run(k_pcg_sumx, bs, SZ_CELL, s);
     run(k_pcg_init, bs, SZ_CELL, s, dic);
 }

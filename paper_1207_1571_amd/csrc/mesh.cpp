@@ -25,6 +25,60 @@ namespace {
 
 bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
+// Sliced-ELL structure of the off-diagonal part (see fvm_mesh).  Slot
+// order is ascending column in both slice modes, so a cell sums its entries
+// in the same order whether its slice is regular or explicit.
+void build_sell(fvm_mesh *m)
+{
+    const int32_t N = m->N;
+    const int32_t ns = (N + kBlock - 1) / kBlock;
+    int32_t W = 0;
+    for (int32_t i = 0; i < N; ++i)
+        W = std::max(W, (m->own_start[i + 1] - m->own_start[i]) + (m->nbr_start[i + 1] - m->nbr_start[i]));
+    W = std::max(W, 1);
+    m->sell_W = W;
+    const size_t E = (size_t)ns * W * kBlock;
+    m->sell_mode.assign(ns, 0);
+    m->sell_off.assign((size_t)ns * W, 0);
+    m->sell_fe.assign(E, -1);
+    m->sell_col.assign(E, 0);
+    std::vector<std::pair<int32_t, int32_t>> ent;   // (column, code) of one cell
+    std::vector<int32_t> offs;
+    for (int32_t s = 0; s < ns; ++s) {
+        const int32_t i0 = s * kBlock, i1 = std::min(N, i0 + kBlock);
+        offs.clear();
+        for (int32_t i = i0; i < i1; ++i) {
+            for (int32_t f = m->own_start[i]; f < m->own_start[i + 1]; ++f) offs.push_back(m->nei[f] - i);
+            for (int32_t k = m->nbr_start[i]; k < m->nbr_start[i + 1]; ++k) offs.push_back(m->own[m->losort[k]] - i);
+        }
+        std::sort(offs.begin(), offs.end());
+        offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+        const bool regular = (int32_t)offs.size() <= W;
+        m->sell_mode[s] = regular ? 0 : 1;
+        if (regular)
+            for (size_t k = 0; k < offs.size(); ++k) m->sell_off[(size_t)s * W + k] = offs[k];
+        for (int32_t i = i0; i < i1; ++i) {
+            ent.clear();
+            for (int32_t f = m->own_start[i]; f < m->own_start[i + 1]; ++f) ent.push_back({m->nei[f], 2 * f});
+            for (int32_t k = m->nbr_start[i]; k < m->nbr_start[i + 1]; ++k) {
+                const int32_t f = m->losort[k];
+                ent.push_back({m->own[f], 2 * f + 1});
+            }
+            std::sort(ent.begin(), ent.end());
+            const int32_t lane = i - i0;
+            for (int32_t k = 0; k < W; ++k) m->sell_col[((size_t)s * W + k) * kBlock + lane] = i;
+            for (size_t e = 0; e < ent.size(); ++e) {
+                int32_t k = (int32_t)e;
+                if (regular)
+                    k = (int32_t)(std::lower_bound(offs.begin(), offs.end(), ent[e].first - i) - offs.begin());
+                const size_t at = ((size_t)s * W + k) * kBlock + lane;
+                m->sell_fe[at] = ent[e].second;
+                m->sell_col[at] = ent[e].first;
+            }
+        }
+    }
+}
+
 fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
 {
     if (!d || d->n_cells < 1 || d->n_internal_faces < 0 || d->n_faces < d->n_internal_faces || d->n_patches < 0)
@@ -165,6 +219,7 @@ fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
     m->lvl_cells.resize(N);
     fill.assign(m->lvl_start.begin(), m->lvl_start.end() - 1);
     for (int32_t i = 0; i < N; ++i) m->lvl_cells[fill[lev[i]]++] = i;
+    build_sell(m);
     return FVM_OK;
 }
 
