@@ -53,7 +53,7 @@ def algorithmic_bytes(cls: str, N: int, Fi: int, dic: bool) -> float:
         "dic_setup": 16 * N + 16 * Fi,             # diag, D* out; lower faces
         "bicg_spmv": 104 * N + 24 * Fi,            # 3 components, A and A^T
         "pcg32_spmv": 12 * N + 12 * Fi,            # FP32 inner: diag, x, y + coefficient + 2 int32
-        "pcg32_update": 28 * N,
+        "pcg32_update": 36 * N,                    # x (FP64) in/out, p, r, q, diag (FP32) in; r out
         "pcg32_dir": 16 * N,
         "bicg32_spmv": 52 * N + 16 * Fi,
         "mom_face": 32 * Fi,                       # phi, w, dl in; upper, lower out
@@ -122,7 +122,7 @@ def cav200_section(fvm, wl, steps, log):
         del pc
         pre = "pcg32" if prec == wl.MIXED else "pcg"
         it_us = sum(k[c]["mean_us"] for c in (pre + "_dir", pre + "_spmv", pre + "_update") if c in k)
-        it_bytes = (112 * N + 16 * Fi) if prec == wl.FP64 else (56 * N + 12 * Fi)
+        it_bytes = (112 * N + 16 * Fi) if prec == wl.FP64 else (64 * N + 12 * Fi)
         res[name] = dict(ms_per_step=round(1e3 * wall / steps, 2), cell_updates_per_s=round(N * steps / wall, 1),
                          p_iters_total=p_iters, ms_per_p_solve=round(1e3 * wall / (2 * steps), 2),
                          spmv_GBps=k.get(pre + "_spmv", {}).get("alg_GBps"),
@@ -138,6 +138,36 @@ def cav200_section(fvm, wl, steps, log):
     return res
 
 
+def serve_section(fvm, wl, n_requests, n_steps, log):
+    """Serving stream (cavity/duct cases, cube side log-uniform 16..96,
+    Re U(10, 1000), Poisson arrivals at 40 req/s), reduced to `n_requests`
+    requests of `n_steps` PISO steps, run once in FP64 and once mixed: p50 /
+    p99 time from arrival to converged result, throughput."""
+    import torch
+    from paper_1207_1571_amd.serve import GpuBackend, Request, Server, summarize
+    reqs = wl.serve_stream(n_requests=n_requests, n_steps=n_steps)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    out = dict(workload=f"serve: {n_requests} requests of the 512-request stream (seed 5; cavity/duct, side "
+                        f"log-uniform 16..96, Re U(10,1000), Poisson 40 req/s), {n_steps} PISO steps each, "
+                        f"tol 1e-6, Jacobi; slots 32, groups of 16, 10 steps per advance",
+               budget_bytes=budget)
+    for name, prec in (("fp64", wl.FP64), ("mixed", wl.MIXED)):
+        t = time.perf_counter()
+        specs = [wl.serve_case(r, precision=prec) for r in reqs]
+        log(f"serve {name}: {len(specs)} case meshes in {time.perf_counter() - t:.1f}s")
+        be = GpuBackend()
+        res = Server(be, budget, slots=32, group=16, chunk=10).run(
+            [Request(r.rid, r.arrival_s, s, r.n_steps) for r, s in zip(reqs, specs)])
+        torch.cuda.synchronize()
+        sm = summarize(res)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sm.items()}
+        log(f"serve {name}: p50 {sm['p50_s']:.3f}s p99 {sm['p99_s']:.3f}s, makespan {sm['makespan_s']:.2f}s, "
+            f"{sm['cell_updates_per_s']:.4g} cell-updates/s, failed {sm['failed']}")
+        del be, specs, res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +177,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cav200-steps", type=int, default=20, help="steps of the 200^3 FP64-vs-mixed section (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving section (0: skip)")
+    ap.add_argument("--serve-steps", type=int, default=20, help="PISO steps per serving request")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for memory counters)")
     args = ap.parse_args()
@@ -210,6 +242,7 @@ def main():
         log("kernel classes: " + json.dumps(kernels))
     del mesh
     cav200 = cav200_section(fvm, wl, args.cav200_steps, log) if args.cav200_steps > 0 else None
+    serving = serve_section(fvm, wl, args.serve_requests, args.serve_steps, log) if args.serve_requests > 0 else None
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
     roofline = None
     if dom:
@@ -247,6 +280,7 @@ def main():
                    "cells": N, "internal_faces": Fi, "precision": "fp64"},
         "pcg_spmv_GBps": spmv["alg_GBps"] if spmv else None,
         "cav200": cav200,
+        "serving": serving,
         "p_iters_last_step": p_iters_last,
         "roofline": roofline,
         "kernels": kernels,

@@ -259,11 +259,19 @@ def dic_apply(case: Case, gamma, r, z, dstar=None):
                                ct.c_void_p(_stream_ptr(case.stream))))
 
 
-def piso_batch(cases: Sequence[Case], n_steps: int, stream=None):
+def piso_batch(cases: Sequence[Case], n_steps: int, stream=None, raise_on_case_failure: bool = True):
+    """piso_step_batch.  A case whose solve failed is rolled back and left out
+    of the remaining steps; its info carries the negative status.  With
+    raise_on_case_failure=False such per-case failures are returned in the
+    infos instead of raised (argument and device errors still raise)."""
     arr = (ct.c_void_p * len(cases))(*[c.handle for c in cases])
     infos = (FvmStepInfo * max(1, len(cases)))()
-    st = _check(lib().piso_step_batch(arr, len(cases), n_steps, ct.c_void_p(_stream_ptr(stream)), infos))
-    return st, [infos[i].as_dict() for i in range(len(cases))]
+    st = lib().piso_step_batch(arr, len(cases), n_steps, ct.c_void_p(_stream_ptr(stream)), infos)
+    out = [infos[i].as_dict() for i in range(len(cases))]
+    case_failure = st < 0 and any(o["status"] < 0 for o in out) and st not in (-1, -2, -4)
+    if not (case_failure and not raise_on_case_failure):
+        _check(st)
+    return st, out
 
 
 def profile_enable(on: bool):

@@ -45,7 +45,7 @@ class Result:
     n_steps: int
     bytes: int
     status: int
-    p_iters: int
+    p_iters: int                 # pressure CG iterations of the last step of each advance
     fields: Optional[tuple] = None
 
     @property
@@ -54,7 +54,10 @@ class Result:
 
 
 class GpuBackend:
-    """Cases in libfvm; advances groups of resident cases with piso_step_batch."""
+    """Cases in libfvm; advances groups of resident cases with piso_step_batch.
+
+    The host mesh (validation, canonical faces, sliced-ELL structure) built
+    to price a request is kept and reused when the request is admitted."""
 
     def __init__(self, device="cuda", keep_fields: bool = False):
         import torch
@@ -64,17 +67,21 @@ class GpuBackend:
         self.device = device
         self.keep_fields = keep_fields
         self.stream = torch.cuda.Stream(device=device)   # default priority
+        self._meshes: Dict[int, object] = {}
 
     def footprint(self, spec) -> int:
-        m = self.fvm.Mesh(spec.mesh, spec.bcs)
+        m = self._meshes.get(id(spec))
+        if m is None:
+            m = self._meshes[id(spec)] = self.fvm.Mesh(spec.mesh, spec.bcs)
         return self.fvm.workspace_bytes(m, self.fvm.opts_from_case(spec))
 
     def create(self, spec):
+        mesh = self._meshes.pop(id(spec), None)
         with self.torch.cuda.stream(self.stream):
-            return self.fvm.Case(spec, device=self.device, stream=self.stream)
+            return self.fvm.Case(spec, device=self.device, stream=self.stream, mesh=mesh)
 
     def advance(self, cases: Sequence, n_steps: int) -> List[dict]:
-        st, infos = self.fvm.piso_batch(list(cases), n_steps, stream=self.stream)
+        st, infos = self.fvm.piso_batch(list(cases), n_steps, stream=self.stream, raise_on_case_failure=False)
         return infos
 
     def finish(self, case):

@@ -1,0 +1,98 @@
+"""Serving on the GPU: each case's result is the same alone and in the mix.
+
+Cases of different kinds and sizes arrive at different times; the server
+admits them as slots free up and advances the resident ones together in
+shared launches, so the group a case is advanced with changes while it runs.
+The fields of every case must equal, bit for bit, those of the same case
+run alone through piso_step (the kernels reduce per case in a fixed order
+and a case's block-to-XCD placement does not depend on the batch), and so
+also lie within the mixed-precision tolerance of 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1207_1571_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _requests(precision, n_steps):
+    rng = np.random.default_rng(11)
+    specs = []
+    for rid, (kind, n) in enumerate([("cavity", 9), ("duct", 7), ("cavity", 12), ("duct", 10), ("cavity", 6),
+                                      ("cavity", 11)]):
+        req = wl.ServeRequest(rid, 0.0, kind, n, float(rng.uniform(10.0, 1000.0)), 0.2 / n, n_steps)
+        specs.append(wl.serve_case(req, precision=precision))
+    return specs
+
+
+@pytest.mark.parametrize("precision", [wl.MIXED, wl.FP64])
+def test_alone_equals_in_the_mix(precision):
+    import torch
+    from paper_1207_1571_amd import fvm
+    from paper_1207_1571_amd.serve import GpuBackend, Request, Server
+
+    n_steps = 6
+    specs = _requests(precision, n_steps)
+    alone = {}
+    for rid, spec in enumerate(specs):
+        _say(f"alone rid={rid} N={spec.mesh.n_cells} precision={precision}")
+        c = fvm.Case(spec)
+        st, info = c.piso(n_steps)
+        assert st == 0
+        alone[rid] = c.get_state_numpy()
+        c.close()
+    torch.cuda.synchronize()
+
+    # arrivals spread out so that cases join while others are resident; at
+    # most 3 resident, advanced 2 steps at a time in groups of up to 3
+    arrivals = [0.0, 0.0, 0.01, 0.03, 0.06, 0.09]
+    reqs = [Request(rid, arrivals[rid], spec, n_steps) for rid, spec in enumerate(specs)]
+    be = GpuBackend(keep_fields=True)
+    budget = sum(be.footprint(s) for s in specs)
+    _say(f"mix: {len(reqs)} requests, budget {budget} bytes")
+    groups = []
+    orig_advance = be.advance
+
+    def advance(cases, steps):
+        groups.append(tuple(id(c) for c in cases))
+        return orig_advance(cases, steps)
+
+    be.advance = advance
+    res = Server(be, budget, slots=3, group=3, chunk=2).run(reqs)
+    assert len(res) == len(specs)
+    # the batch composition changed while cases were resident
+    assert len(set(groups)) > 1 and max(len(g) for g in groups) > 1
+    for r in res:
+        assert r.status == 0, r
+        U, p, phi = r.fields
+        Ua, pa, phia = alone[r.rid]
+        for name, a, b in (("U", U, Ua), ("p", p, pa), ("phi", phi, phia)):
+            nb = np.linalg.norm(b)
+            rel = np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+            assert rel <= 1e-6, (r.rid, name, rel)
+            assert np.array_equal(a, b), (r.rid, name, rel)
+
+
+def test_budget_admission_on_device():
+    """A budget that holds only the largest case admits one case at a time,
+    and every case still completes."""
+    from paper_1207_1571_amd.serve import GpuBackend, Request, Server
+
+    allspecs = _requests(wl.MIXED, 2)
+    specs = [allspecs[i] for i in (0, 3, 5)]   # 9^3, 10^3, 11^3: no two fit in the largest one's footprint
+    be = GpuBackend()
+    foot = [be.footprint(s) for s in specs]
+    assert max(foot) < sum(sorted(foot)[:2])
+    reqs = [Request(rid, 0.0, s, 2) for rid, s in enumerate(specs)]
+    res = Server(be, max(foot), slots=8, group=8, chunk=2).run(reqs)
+    assert sorted(r.rid for r in res) == [0, 1, 2]
+    spans = sorted((r.admitted_s, r.done_s) for r in res)
+    for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
+        assert a1 >= d0   # never two resident at once
