@@ -91,6 +91,27 @@ def profile_classes(fvm, case, steps, N, Fi, dic):
     return out
 
 
+def vs_spmv(k, spmv_cls):
+    """Assembly operators' device time per call relative to one SpMV (the
+    analogue of the paper's Table 3 normalisation)."""
+    if spmv_cls not in k or not k[spmv_cls]["mean_us"]:
+        return None
+    sp = k[spmv_cls]["mean_us"]
+
+    def per_call(*names):
+        if not all(n in k for n in names):
+            return None
+        return round(sum(k[n]["mean_us"] for n in names) / sp, 2)
+
+    return {
+        "momentum assembly (convection + Laplacian: mom_face + mom_cell)": per_call("mom_face", "mom_cell"),
+        "H operator and rAU (hbya)": per_call("hbya"),
+        "pressure Laplacian + flux divergence (p_face + p_cell)": per_call("p_face", "p_cell"),
+        "flux correction (flux_corr)": per_call("flux_corr"),
+        "Gauss gradient of p + velocity correction (U_corr)": per_call("U_corr"),
+    }
+
+
 def cav200_section(fvm, wl, steps, log):
     """200^3 cavity, FP64 and mixed (FP32 inner + FP64 refinement), `steps`
     PISO steps each from rest: time per step, pressure iterations, SpMV and
@@ -128,7 +149,7 @@ def cav200_section(fvm, wl, steps, log):
                          spmv_GBps=k.get(pre + "_spmv", {}).get("alg_GBps"),
                          spmv_mean_us=k.get(pre + "_spmv", {}).get("mean_us"),
                          cg_iter_us=round(it_us, 2), cg_iter_GBps=round(it_bytes / (it_us * 1e-6) / 1e9, 1) if it_us else None,
-                         kernels=k)
+                         assembly_vs_spmv=vs_spmv(k, pre + "_spmv"), kernels=k)
         log(f"cav200 {name}: {res[name]['ms_per_step']} ms/step, p iters {p_iters}, SpMV {res[name]['spmv_GBps']} GB/s, "
             f"CG iteration {res[name]['cg_iter_GBps']} GB/s")
     rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
@@ -283,6 +304,7 @@ def main():
         "serving": serving,
         "p_iters_last_step": p_iters_last,
         "roofline": roofline,
+        "assembly_vs_spmv": vs_spmv(kernels, "pcg_spmv") if kernels else None,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

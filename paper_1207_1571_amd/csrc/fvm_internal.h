@@ -153,7 +153,9 @@ struct Batch {
     int32_t start[kMaxBatch + 1];
     int32_t n;
 };
-enum { SZ_CELL = 0, SZ_FACE = 1, SZ_FACEI = 2, SZ_MAXNF = 3, SZ_KINDS = 4 };
+// grid kinds: one block per 256 cells / faces / internal faces / max(N, Fi),
+// and per 512 / 1024 cells for kernels that take 2 / 4 cells per thread
+enum { SZ_CELL = 0, SZ_FACE = 1, SZ_FACEI = 2, SZ_MAXNF = 3, SZ_CELL2 = 4, SZ_CELL4 = 5, SZ_KINDS = 6 };
 struct BatchSet {
     Batch b[SZ_KINDS];
     const DevCase *host[kMaxBatch];   // host copies (sizes, pointers) of the same cases

@@ -971,18 +971,38 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt)
 
 // ---- CG ----------------------------------------------------------------
 
+// Streaming kernels take U cells per thread (grid SZ_CELL2 / SZ_CELL4): all
+// loads of a thread are issued before the first use, so every wave keeps U
+// times more bytes in flight than with one cell per thread.
+
 // p = z + beta p (Jacobi z = r/diag; DIC z from the sweeps)
-template <class T>
-__global__ void k_cg_dir(Batch bt, int dic)
+template <class T, int U>
+__global__ void __launch_bounds__(kBlock) k_cg_dir(Batch bt, int dic)
 {
     CASE_OF(bt);
     const CGArr<T> v = cg_arrays<T>(d, dic);
     const KState &s = *v.ks;
     if (s.done) return;
-    const int i = K.raw * kBlock + threadIdx.x;
-    if (i >= d.N) return;
-    const T z = v.z ? (T)v.z[i] : v.r[i] / v.diag[i];
-    v.p[i] = s.first ? z : z + (T)s.beta * v.p[i];
+    const bool first = s.first;
+    const T beta = (T)s.beta;
+    const Range rg = block_range(d.N, K);
+    T *__restrict__ p = v.p;
+    for (int base = rg.beg; base < rg.end; base += U * kBlock) {
+        T zv[U], pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < rg.end) {
+                zv[u] = v.z ? (T)v.z[i] : v.r[i] / v.diag[i];
+                pv[u] = first ? (T)0 : p[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < rg.end) p[i] = first ? zv[u] : zv[u] + beta * pv[u];
+        }
+    }
 }
 
 // Pressure matrix values into the sliced-ELL copy (start of every pressure
@@ -1021,45 +1041,54 @@ __global__ void __launch_bounds__(kBlock) k_sell_fill(Batch bt)
 // spectrally within (1 +- eps32) of the FP64 one.  Products of FP32 values
 // are exact in FP64 and the sums are FP64.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
+__device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v, int sl, int i)
 {
     constexpr bool kDiff = sizeof(T) == 4;
+    const int W = d.sell_W;
+    const size_t base = (size_t)sl * W * kBlock + threadIdx.x;
+    const T *__restrict__ val = v.sval + base;
+    const T *__restrict__ p = v.p;
+    const double pi = (double)p[i];
+    double qa = kDiff ? 0.0 : (double)v.diag[i] * pi, so = 0.0;
+    if (d.sell_mode[sl] == 0) {
+        const int *__restrict__ off = d.sell_off + (size_t)sl * W;
+        const int last = d.N - 1;
+#pragma unroll 6
+        for (int k = 0; k < W; ++k) {
+            const T a = val[(size_t)k * kBlock];
+            const int j = min(max(i + off[k], 0), last);
+            qa += (double)a * (double)p[j];
+            if (kDiff) so += (double)a;
+        }
+    } else {
+        const int *__restrict__ col = d.sell_col + base;
+#pragma unroll 6
+        for (int k = 0; k < W; ++k) {
+            const T a = val[(size_t)k * kBlock];
+            qa += (double)a * (double)p[col[(size_t)k * kBlock]];
+            if (kDiff) so += (double)a;
+        }
+    }
+    const T q = kDiff ? (T)(qa + ((double)v.exc[i] - so) * pi) : (T)qa;
+    v.q[i] = q;
+    return pi * (double)q;
+}
+
+// S slices per block (grid SZ_CELL for S = 1, SZ_CELL2 for S = 2)
+template <class T, int S>
+__global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
+{
     CASE_OF(bt);
     const CGArr<T> v = cg_arrays<T>(d, dic);
     if (v.ks->done) return;
     const Range rg = block_range(d.N, K);
-    const int i = rg.beg + threadIdx.x;
     double acc[1] = {0.0};
-    if (i < rg.end) {
-        const int W = d.sell_W;
-        const int sl = rg.beg / kBlock;
-        const size_t base = (size_t)sl * W * kBlock + threadIdx.x;
-        const T *__restrict__ val = v.sval + base;
-        const T *__restrict__ p = v.p;
-        const double pi = (double)p[i];
-        double qa = kDiff ? 0.0 : (double)v.diag[i] * pi, so = 0.0;
-        if (d.sell_mode[sl] == 0) {
-            const int *__restrict__ off = d.sell_off + (size_t)sl * W;
-            const int last = d.N - 1;
-#pragma unroll 6
-            for (int k = 0; k < W; ++k) {
-                const T a = val[(size_t)k * kBlock];
-                const int j = min(max(i + off[k], 0), last);
-                qa += (double)a * (double)p[j];
-                if (kDiff) so += (double)a;
-            }
-        } else {
-            const int *__restrict__ col = d.sell_col + base;
-#pragma unroll 6
-            for (int k = 0; k < W; ++k) {
-                const T a = val[(size_t)k * kBlock];
-                qa += (double)a * (double)p[col[(size_t)k * kBlock]];
-                if (kDiff) so += (double)a;
-            }
+    for (int base = rg.beg; base < rg.end; base += S * kBlock) {
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < rg.end) acc[0] += spmv_cell<T>(d, v, (base + u * kBlock) / kBlock, i);
         }
-        const T q = kDiff ? (T)(qa + ((double)v.exc[i] - so) * pi) : (T)qa;
-        v.q[i] = q;
-        acc[0] = pi * (double)q;
     }
     __shared__ double tot[1];
     if (reduce_last<1>(acc, d, K, tot) && threadIdx.x == 0) {
@@ -1070,6 +1099,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
 }
 
 // FP64: x += alpha p, r -= alpha q, |r| -> stop test; Jacobi: rho, beta
+template <int U>
 __global__ void __launch_bounds__(kBlock) k_cg_update(Batch bt, int dic)
 {
     CASE_OF(bt);
@@ -1082,12 +1112,27 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Batch bt, int dic)
     double *__restrict__ rr = v.r;
     const double *__restrict__ p = v.p;
     const double *__restrict__ q = v.q;
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        x[i] += al * p[i];
-        const double r = rr[i] - al * q[i];
-        rr[i] = r;
-        acc[0] += fabs(r);
-        if (!dic) acc[1] += r * (r / v.diag[i]);
+    for (int base = rg.beg; base < rg.end; base += U * kBlock) {
+        double xv[U], rv[U], pv[U], qv[U], dv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < rg.end) {
+                xv[u] = x[i]; rv[u] = rr[i]; pv[u] = p[i]; qv[u] = q[i];
+                dv[u] = dic ? 1.0 : v.diag[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < rg.end) {
+                x[i] = xv[u] + al * pv[u];
+                const double r = rv[u] - al * qv[u];
+                rr[i] = r;
+                acc[0] += fabs(r);
+                if (!dic) acc[1] += r * (r / dv[u]);
+            }
+        }
     }
     __shared__ double tot[2];
     if (reduce_last<2>(acc, d, K, tot) && threadIdx.x == 0) {
@@ -1162,20 +1207,27 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(Batch bt, int dic)
 }
 
 // ---------------------------------------------------------------------------
-// DIC triangular sweeps, sync-free in level order
+// DIC triangular sweeps, sync-free in level order, on one XCD
 //
 // The diagonal-only incomplete Cholesky factor D* and the two triangular
 // solves of M = (D* + L) D*^-1 (D* + U) are recurrences over the lower
 // (upper) neighbours of each cell.  Cells are processed in the order of the
-// dependency levels computed at mesh ingest; tiles of 256 cells are claimed
-// through an atomic ticket, so every dependency of a tile lies in a tile that
-// has already been claimed by a running or finished block.  A value is
-// published with one 64-bit device-scope store into an array pre-filled with
-// the NaN sentinel: the value is its own ready flag, so no fence is needed and
-// a reader polls exactly the word it consumes.  Polling is bounded: past the
-// limit the value is published as NaN, which the solver reports as a
-// breakdown instead of hanging.  Per cell the sums run over neighbours in
-// ascending index.
+// dependency levels computed at mesh ingest, in tiles of 256 cells claimed
+// through an atomic ticket, so every dependency of a tile lies in a tile
+// that has already been claimed by a running block.
+//
+// A sweep is a chain of as many dependent steps as there are levels, so its
+// time is set by the latency of handing a value from one CU to another.  The
+// sweep therefore runs on a single XCD: the first block of the launch elects
+// its XCD, blocks on the other XCDs leave at once, and the elected XCD's
+// blocks stay resident and claim tiles until none are left.  A value is
+// published with a plain 64-bit store into an array pre-filled with a NaN
+// sentinel; it lands in the XCD's L2, where device-scope loads from the same
+// XCD see it (about half the latency of a store written through to memory).
+// The value is its own ready flag, so no fence is needed and a reader polls
+// exactly the word it consumes.  Polling is bounded: past the limit the
+// value is published as NaN, which the solver reports as a breakdown instead
+// of hanging.  Per cell the sums run over neighbours in ascending index.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ bool dic_try(const double *a, int j, double &v)
@@ -1187,12 +1239,16 @@ __device__ __forceinline__ bool dic_try(const double *a, int j, double &v)
     return true;
 }
 
+// plain (XCD-local) 64-bit store of a published value
 __device__ __forceinline__ void dic_put(double *a, int i, double v)
 {
     unsigned long long b = (unsigned long long)__double_as_longlong(v);
     if (b == kSentinel) b = kQNaN;
-    __hip_atomic_store(reinterpret_cast<unsigned long long *>(a + i), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(a + i), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+// hardware XCD (XCC) id of the executing wave
+__device__ __forceinline__ unsigned int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u; }
 
 // MODE 0: D*_i = A_ii - sum_{j<i} a_ij^2 / D*_j
 // MODE 1: y_i = (r_i - sum_{j<i} a_ij y_j) / D*_i      (also clears z)
@@ -1206,13 +1262,8 @@ __device__ __forceinline__ void dic_put(double *a, int i, double v)
 constexpr int kDicDeps = 8;
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_dic_sweep(Batch bt)
+__device__ __forceinline__ double dic_tile(const DevCase &d, int tile)
 {
-    CASE_OF(bt);
-    if (d.ks[3].done) return;
-    __shared__ int tile;
-    if (threadIdx.x == 0) tile = (int)atomicAdd(&d.ticket[1], 1u);
-    __syncthreads();
     const int n = d.N;
     const int pos = tile * kBlock + threadIdx.x;
     const bool live = pos < n;
@@ -1302,12 +1353,42 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(Batch bt)
         if (__all(fin)) break;
         __builtin_amdgcn_s_sleep(1);
     }
+    return part;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_dic_sweep(Batch bt)
+{
+    CASE_OF(bt);
+    if (d.ks[3].done) return;
+    __shared__ int s_on, s_tile;
+    if (threadIdx.x == 0) {
+        // elect the XCD of the first block to arrive (ticket[5] = xcc + 1)
+        const unsigned int x = xcc_id() + 1u;
+        unsigned int e = 0u;
+        __hip_atomic_compare_exchange_strong(&d.ticket[5], &e, x, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        s_on = e == 0u || e == x;
+    }
+    __syncthreads();
+    double part = 0.0;
+    if (s_on) {
+        for (;;) {
+            if (threadIdx.x == 0) s_tile = (int)atomicAdd(&d.ticket[1], 1u);
+            __syncthreads();
+            const int tile = s_tile;
+            __syncthreads();
+            if ((long)tile * kBlock >= d.N) break;
+            part += dic_tile<MODE>(d, tile);
+        }
+    }
     if (MODE == 2) {
         double v[1] = {part};
         __shared__ double tot[1];
         if (reduce_last<1>(v, d, K, tot) && threadIdx.x == 0) {
             KState &s = d.ks[3];
             __hip_atomic_store(&d.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&d.ticket[5], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
             else if (s.iters == 0) s.rho = tot[0];
             else {
@@ -1322,6 +1403,7 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(Batch bt)
             if (t == (unsigned int)K.G - 1) {
                 __hip_atomic_store(&d.ticket[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&d.ticket[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&d.ticket[5], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -1403,7 +1485,11 @@ __global__ void __launch_bounds__(kBlock) k_rr_start(Batch bt)
     }
 }
 
-// x64 += alpha p32, r32 -= alpha q32; |r32| and rho (FP64 accumulation)
+// x64 += alpha p32, r32 -= alpha q32; |r32| and rho (FP64 accumulation).
+// The solution stays FP64: an FP32 solution increment would carry rounding
+// noise of relative size eps32, which A amplifies by up to its condition
+// number in the true residual.
+template <int U>
 __global__ void __launch_bounds__(kBlock) k_rr_update(Batch bt)
 {
     CASE_OF(bt);
@@ -1415,13 +1501,27 @@ __global__ void __launch_bounds__(kBlock) k_rr_update(Batch bt)
     double *__restrict__ x = d.p;
     const float *__restrict__ p = d.f_p;
     const float *__restrict__ q = d.f_q;
+    const float *__restrict__ dg = d.f_pdiag;
     float *__restrict__ r = d.f_r;
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        x[i] += al * (double)p[i];
-        const float ri = r[i] - alf * q[i];
-        r[i] = ri;
-        acc[0] += fabs((double)ri);
-        acc[1] += (double)ri * (double)(ri / d.f_pdiag[i]);
+    for (int base = rg.beg; base < rg.end; base += U * kBlock) {
+        double xv[U];
+        float pv[U], qv[U], rv[U], dv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < rg.end) { xv[u] = x[i]; pv[u] = p[i]; qv[u] = q[i]; rv[u] = r[i]; dv[u] = dg[i]; }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kBlock + threadIdx.x;
+            if (i < rg.end) {
+                x[i] = xv[u] + al * (double)pv[u];
+                const float ri = rv[u] - alf * qv[u];
+                r[i] = ri;
+                acc[0] += fabs((double)ri);
+                acc[1] += (double)ri * (double)(ri / dv[u]);
+            }
+        }
     }
     __shared__ double tot[2];
     if (reduce_last<2>(acc, d, K, tot) && threadIdx.x == 0) {
@@ -1607,8 +1707,12 @@ void batch_add(BatchSet &bs, const DevCase *dev, const DevCase *host)
         Batch &b = bs.b[k];
         b.dc[c] = dev;
         if (c == 0) b.start[0] = 0;
-        const int n = k == SZ_CELL ? host->N : k == SZ_FACE ? host->F : k == SZ_FACEI ? host->Fi
-                                                                                      : (host->N > host->Fi ? host->N : host->Fi);
+        int n = host->N > host->Fi ? host->N : host->Fi;
+        if (k == SZ_CELL) n = host->N;
+        else if (k == SZ_FACE) n = host->F;
+        else if (k == SZ_FACEI) n = host->Fi;
+        else if (k == SZ_CELL2) n = (host->N + 1) / 2;
+        else if (k == SZ_CELL4) n = (host->N + 3) / 4;
         b.start[c + 1] = b.start[c] + blocks_for(n);
         b.n = c + 1;
     }
@@ -1755,15 +1859,15 @@ void launch_pcg_iter(const BatchSet &bs, int dic, hipStream_t s)
 {
     {
         Prof p("pcg_dir", s);
-        run(k_cg_dir<double>, bs, SZ_CELL, s, dic);
+        run(k_cg_dir<double, 4>, bs, SZ_CELL4, s, dic);
     }
     {
         Prof p("pcg_spmv", s);
-        run(k_cg_spmv<double>, bs, SZ_CELL, s, dic);
+        run(k_cg_spmv<double, 1>, bs, SZ_CELL, s, dic);
     }
     {
         Prof p("pcg_update", s);
-        run(k_cg_update, bs, SZ_CELL, s, dic);
+        run(k_cg_update<2>, bs, SZ_CELL2, s, dic);
     }
     if (dic) launch_dic_precond(bs, 0, s);
 }
@@ -1795,15 +1899,15 @@ void launch_rr_iter(const BatchSet &bs, hipStream_t s)
 {
     {
         Prof p("pcg32_dir", s);
-        run(k_cg_dir<float>, bs, SZ_CELL, s, 0);
+        run(k_cg_dir<float, 4>, bs, SZ_CELL4, s, 0);
     }
     {
         Prof p("pcg32_spmv", s);
-        run(k_cg_spmv<float>, bs, SZ_CELL, s, 0);
+        run(k_cg_spmv<float, 2>, bs, SZ_CELL2, s, 0);
     }
     {
         Prof p("pcg32_update", s);
-        run(k_rr_update, bs, SZ_CELL, s);
+        run(k_rr_update<4>, bs, SZ_CELL4, s);
     }
 }
 
