@@ -188,6 +188,7 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
     if (dic) {
         d.y = b.take<double>(N); d.z = b.take<double>(N); d.dstar = b.take<double>(N);
         d.lvl_start = b.take<int32_t>(m.lvl_start.size()); d.lvl_cells = b.take<int32_t>(N);
+        d.lvl_pos = b.take<int32_t>(N); d.lvl_of = b.take<int32_t>(N);
     }
     if (mixed) {
         d.f_diag = b.take<float>(N); d.f_up = b.take<float>(Fi); d.f_lo = b.take<float>(Fi);
@@ -388,7 +389,10 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     UPCHK(up(d.V, m->V, s));
     UPCHK(up(d.tmpC, m->C, s));
     UPCHK(up(d.tmpCf, m->Cf, s));
-    if (d.lvl_start) { UPCHK(up(d.lvl_start, m->lvl_start, s)); UPCHK(up(d.lvl_cells, m->lvl_cells, s)); }
+    if (d.lvl_start) {
+        UPCHK(up(d.lvl_start, m->lvl_start, s)); UPCHK(up(d.lvl_cells, m->lvl_cells, s));
+        UPCHK(up(d.lvl_pos, m->lvl_pos, s)); UPCHK(up(d.lvl_of, m->lvl_of, s));
+    }
     UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s));
     UPCHK(up(d.sell_fe, m->sell_fe, s)); UPCHK(up(d.sell_col, m->sell_col, s));
     UPCHK(hipMemsetAsync(d.ticket, 0, 64 * sizeof(unsigned int), s));

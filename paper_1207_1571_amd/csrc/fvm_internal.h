@@ -36,8 +36,10 @@ struct fvm_mesh {
     bool nonorth = false;
     bool has_fixed_p = false;
     // level schedule of the lower-triangular dependency graph (DIC sweeps):
-    // cells of level l are lvl_cells[lvl_start[l] .. lvl_start[l+1])
-    std::vector<int32_t> lvl_start, lvl_cells;
+    // cells of level l are lvl_cells[lvl_start[l] .. lvl_start[l+1]); lvl_pos
+    // is the inverse permutation (position of cell i in lvl_cells), lvl_of the
+    // level of each cell
+    std::vector<int32_t> lvl_start, lvl_cells, lvl_pos, lvl_of;
     // row-sliced copy of the off-diagonal structure (sliced ELL): slice s =
     // cells [256 s, 256 s + 256), sell_W slots per cell, entry (s, k, lane) at
     // (s * sell_W + k) * 256 + lane; a cell's entries in ascending column.
@@ -117,7 +119,7 @@ struct DevCase {
     double *r, *rt, *pp, *pt, *q, *qt;           // [3][N] each (CG uses component 0)
     double *y, *z;                               // [N] DIC forward / backward sweep outputs
     double *dstar;                               // [N] DIC diagonal
-    int32_t *lvl_start, *lvl_cells;              // DIC level schedule
+    int32_t *lvl_start, *lvl_cells, *lvl_pos, *lvl_of;   // DIC level schedule
     int32_t n_levels;
     // sliced-ELL copy of the pressure matrix (structure as in fvm_mesh)
     int32_t sell_W;

@@ -1261,11 +1261,22 @@ __device__ __forceinline__ unsigned int xcc_id() { return __builtin_amdgcn_s_get
 // dependencies take a streaming path that consumes them one at a time.
 constexpr int kDicDeps = 8;
 
+// Blocks claim tiles of 256 consecutive entries of the level order (reversed
+// for MODE 2); each wave of the block takes 64 of them.  Before its lanes
+// poll, a wave waits on a single word: the last cell (in processing order)
+// of the level before the level of its latest outside dependency.  The wave
+// thus starts polling about one level before its inputs complete: waves far
+// ahead of the front poll one address instead of up to 64 x kDicDeps, which
+// keeps the XCD's L2 free for the hand-over traffic at the front, while the
+// front itself is not delayed by the gate.
+constexpr int kChunk = 64;
+
 template <int MODE>
-__device__ __forceinline__ double dic_tile(const DevCase &d, int tile)
+__device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
 {
     const int n = d.N;
-    const int pos = tile * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int pos = chunk * kChunk + lane;
     const bool live = pos < n;
     const int i = live ? (MODE == 2 ? d.lvl_cells[n - 1 - pos] : d.lvl_cells[pos]) : 0;
     int k0, k1;
@@ -1278,6 +1289,7 @@ __device__ __forceinline__ double dic_tile(const DevCase &d, int tile)
     const bool fast = nd <= kDicDeps;
     int js[kDicDeps];
     double as[kDicDeps], vs[kDicDeps];
+    int gate = -1;   // processing position of the latest dependency before this chunk
 #pragma unroll
     for (int t = 0; t < kDicDeps; ++t) {
         js[t] = 0; as[t] = 0.0; vs[t] = 0.0;
@@ -1285,6 +1297,24 @@ __device__ __forceinline__ double dic_tile(const DevCase &d, int tile)
             const int f = MODE == 2 ? k0 + t : d.losort[k0 + t];
             js[t] = MODE == 2 ? d.nei[f] : d.own[f];
             as[t] = d.poff[f];
+            const int q = MODE == 2 ? n - 1 - d.lvl_pos[js[t]] : d.lvl_pos[js[t]];
+            if (q < chunk * kChunk && q > gate) gate = q;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) gate = max(gate, __shfl_xor(gate, o, 64));
+    if (gate >= 0) {
+        // the gate cell: last cell, in processing order, of the level one
+        // step before that of the latest outside dependency
+        const int gl = d.lvl_of[MODE == 2 ? d.lvl_cells[n - 1 - gate] : d.lvl_cells[gate]];
+        int gp = -1;   // forward position of the gate cell
+        if (MODE == 2) { if (gl + 1 < d.n_levels) gp = d.lvl_start[gl + 1]; }
+        else if (gl >= 1) gp = d.lvl_start[gl] - 1;
+        if (gp >= 0) {
+            // every lane loads the same word: one request per wave
+            const int gc = d.lvl_cells[gp];
+            double v;
+            for (int sp = 0; sp < kSpinLimit && !dic_try(src, gc, v); ++sp) __builtin_amdgcn_s_sleep(1);
         }
     }
     const double dsi = (MODE != 0 && live) ? d.dstar[i] : 1.0;
@@ -1373,13 +1403,15 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(Batch bt)
     __syncthreads();
     double part = 0.0;
     if (s_on) {
+        // the block claims tiles until none are left; the waves of a tile
+        // work on consecutive cells (shared cache lines)
         for (;;) {
             if (threadIdx.x == 0) s_tile = (int)atomicAdd(&d.ticket[1], 1u);
             __syncthreads();
             const int tile = s_tile;
             __syncthreads();
             if ((long)tile * kBlock >= d.N) break;
-            part += dic_tile<MODE>(d, tile);
+            part += dic_chunk<MODE>(d, tile * kWaves + (threadIdx.x >> 6));
         }
     }
     if (MODE == 2) {

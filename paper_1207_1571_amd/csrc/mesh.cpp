@@ -219,6 +219,9 @@ fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
     m->lvl_cells.resize(N);
     fill.assign(m->lvl_start.begin(), m->lvl_start.end() - 1);
     for (int32_t i = 0; i < N; ++i) m->lvl_cells[fill[lev[i]]++] = i;
+    m->lvl_pos.resize(N);
+    for (int32_t k = 0; k < N; ++k) m->lvl_pos[m->lvl_cells[k]] = k;
+    m->lvl_of = lev;
     build_sell(m);
     return FVM_OK;
 }
