@@ -91,6 +91,25 @@ def profile_classes(fvm, case, steps, N, Fi, dic):
     return out
 
 
+def measured_traffic(kernel_class: str, workload: str):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summaries under profiles/ (copy-calibrated), if they were taken on the
+    current kernel source; else None."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1207_1571_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if not line.startswith("traffic-json:"):
+                continue
+            rec = json.loads(line.split(":", 1)[1])
+            if (rec.get("kernel_class") == kernel_class and rec.get("workload") == workload
+                    and rec.get("kernels_hip_sha256") == sha):
+                return float(rec["bytes_per_launch"])
+    return None
+
+
 def vs_spmv(k, spmv_cls):
     """Assembly operators' device time per call relative to one SpMV (the
     analogue of the paper's Table 3 normalisation)."""
@@ -112,7 +131,7 @@ def vs_spmv(k, spmv_cls):
     }
 
 
-def cav200_section(fvm, wl, steps, log):
+def cav200_section(fvm, wl, steps, log, profile_steps=2):
     """200^3 cavity, FP64 and mixed (FP32 inner + FP64 refinement), `steps`
     PISO steps each from rest: time per step, pressure iterations, SpMV and
     CG-iteration bandwidth, and the mixed-vs-FP64 field difference."""
@@ -131,16 +150,20 @@ def cav200_section(fvm, wl, steps, log):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         p_iters = 0
-        for _ in range(steps):
+        for k in range(steps):
             st, info = c.piso(1)
             p_iters += sum(s["iters"] for s in info["p"])
+            if steps <= 5 or (k + 1) % 5 == 0:
+                log(f"cav200 {name}: step {k + 1}/{steps}, p iters so far {p_iters}")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         fields[name] = c.get_state_numpy()
         del c
-        pc = fvm.Case(sp, mesh=mesh)
-        k = profile_classes(fvm, pc, 2, N, Fi, False)
-        del pc
+        k = {}
+        if profile_steps > 0:
+            pc = fvm.Case(sp, mesh=mesh)
+            k = profile_classes(fvm, pc, profile_steps, N, Fi, False)
+            del pc
         pre = "pcg32" if prec == wl.MIXED else "pcg"
         it_us = sum(k[c]["mean_us"] for c in (pre + "_dir", pre + "_spmv", pre + "_update") if c in k)
         it_bytes = (112 * N + 16 * Fi) if prec == wl.FP64 else (64 * N + 12 * Fi)
@@ -198,6 +221,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cav200-steps", type=int, default=20, help="steps of the 200^3 FP64-vs-mixed section (0: skip)")
+    ap.add_argument("--cav200-profile-steps", type=int, default=2,
+                    help="steps of the per-kernel-class timing pass of the 200^3 section (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving section (0: skip)")
     ap.add_argument("--serve-steps", type=int, default=20, help="PISO steps per serving request")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -262,14 +287,22 @@ def main():
         del pc
         log("kernel classes: " + json.dumps(kernels))
     del mesh
-    cav200 = cav200_section(fvm, wl, args.cav200_steps, log) if args.cav200_steps > 0 else None
+    cav200 = (cav200_section(fvm, wl, args.cav200_steps, log, args.cav200_profile_steps)
+              if args.cav200_steps > 0 else None)
     serving = serve_section(fvm, wl, args.serve_requests, args.serve_steps, log) if args.serve_requests > 0 else None
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
     roofline = None
     if dom:
         ach = kernels[dom]["alg_GBps"]
+        tb = measured_traffic(dom, f"cav{args.n}")
         roofline = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(ach / HBM_PEAK_GBS, 4) if ach else None, traffic=None)
+                        frac=round(ach / HBM_PEAK_GBS, 4) if ach else None,
+                        traffic=tb,
+                        traffic_GBps=round(tb / (kernels[dom]["mean_us"] * 1e-6) / 1e9, 1) if tb else None,
+                        algorithmic_bytes=algorithmic_bytes(dom, N, Fi, spec.p_ctl.precond == wl.PC_DIC))
+        if dom.startswith("dic"):
+            roofline["note"] = ("dependency-latency bound: the sweep is a chain of one step per level of the "
+                                "lower-triangular graph; HBM fraction shown for reference")
     spmv = kernels.get("pcg_spmv")
 
     cpu = None
