@@ -604,13 +604,17 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
         if (st != FVM_OK) return st;
     } else if (kind == 1) {
         // FP32 CG recurrence, FP64 solution; the replacement kernel follows
-        // every iteration and does nothing unless the device state asks for
-        // a replacement (paused at the tolerance or the iteration limit, or
-        // the recurrence residual fell 10x since the last one)
+        // every kReplaceEvery-th iteration and does nothing unless the device
+        // state asks for a replacement (paused at the tolerance or the
+        // iteration limit, or the recurrence residual fell 10x since the last
+        // one).  Iterations enqueued while paused are no-ops, so the launch
+        // limit is a multiple of max_iter; the device enforces max_iter.
+        constexpr int kReplaceEvery = 4;
         launch_rr_start(bs, s);
-        st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 2, [&] {
+        long k = 0;
+        st = iterate_until_done(g, first, count, predicted_iters(g, kind), (max_iter + 2) * kReplaceEvery, [&] {
             launch_rr_iter(bs, s);
-            launch_rr_replace(bs, s);
+            if (++k % kReplaceEvery == 0) launch_rr_replace(bs, s);
         }, res);
         if (st != FVM_OK) return st;
     } else {

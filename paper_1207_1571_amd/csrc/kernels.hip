@@ -1465,8 +1465,8 @@ __global__ void k_dic_reset(Batch bt)
 // fallen 10x since the last replacement it is replaced by the true FP64
 // residual b - A x, and convergence is decided on that true residual: when
 // the recurrence residual reaches the tolerance (or the iteration limit is
-// reached) the iteration pauses (done = 2) and the replacement that follows
-// the same iteration checks it.
+// reached) the iteration pauses (done = 2) until the next replacement
+// (launched after every few iterations) checks it.
 // Restarting an FP32 CG from each refined residual instead would throw its
 // Krylov space away, which on these pressure systems multiplies the
 // iteration count several times over.
@@ -1946,5 +1946,5 @@ void launch_rr_iter(const BatchSet &bs, hipStream_t s)
 void launch_rr_replace(const BatchSet &bs, hipStream_t s)
 {
     Prof p("pcg_replace", s);
-    run(k_rr_replace, bs, SZ_CELL, s);
+    run(k_rr_replace, bs, SZ_CELL4, s);
 }
