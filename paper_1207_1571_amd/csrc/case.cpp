@@ -186,9 +186,14 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
         d.tmpC = kbase; d.tmpCf = kbase + 3 * N;
     }
     if (dic) {
-        d.y = b.take<double>(N); d.z = b.take<double>(N); d.dstar = b.take<double>(N);
+        d.z = b.take<double>(N); d.dstar = b.take<double>(N);
+        d.dq = b.take<double>(N); d.yq = b.take<double>(N); d.zq = b.take<double>(N);
         d.lvl_start = b.take<int32_t>(m.lvl_start.size()); d.lvl_cells = b.take<int32_t>(N);
-        d.lvl_pos = b.take<int32_t>(N); d.lvl_of = b.take<int32_t>(N);
+        d.dW_lo = m.dW_lo; d.dW_hi = m.dW_hi;
+        d.dl_pos = b.take<int32_t>((size_t)m.dW_lo * N); d.dl_face = b.take<int32_t>((size_t)m.dW_lo * N);
+        d.du_pos = b.take<int32_t>((size_t)m.dW_hi * N); d.du_face = b.take<int32_t>((size_t)m.dW_hi * N);
+        d.lev_pos = b.take<int32_t>(N);
+        d.dl_val = b.take<double>((size_t)m.dW_lo * N); d.du_val = b.take<double>((size_t)m.dW_hi * N);
     }
     if (mixed) {
         d.f_diag = b.take<float>(N); d.f_up = b.take<float>(Fi); d.f_lo = b.take<float>(Fi);
@@ -391,7 +396,9 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     UPCHK(up(d.tmpCf, m->Cf, s));
     if (d.lvl_start) {
         UPCHK(up(d.lvl_start, m->lvl_start, s)); UPCHK(up(d.lvl_cells, m->lvl_cells, s));
-        UPCHK(up(d.lvl_pos, m->lvl_pos, s)); UPCHK(up(d.lvl_of, m->lvl_of, s));
+        UPCHK(up(d.dl_pos, m->dl_pos, s)); UPCHK(up(d.dl_face, m->dl_face, s));
+        UPCHK(up(d.du_pos, m->du_pos, s)); UPCHK(up(d.du_face, m->du_face, s));
+        UPCHK(up(d.lev_pos, m->lev_pos, s));
     }
     UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s));
     UPCHK(up(d.sell_fe, m->sell_fe, s)); UPCHK(up(d.sell_col, m->sell_col, s));

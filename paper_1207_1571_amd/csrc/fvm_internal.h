@@ -40,6 +40,12 @@ struct fvm_mesh {
     // is the inverse permutation (position of cell i in lvl_cells), lvl_of the
     // level of each cell
     std::vector<int32_t> lvl_start, lvl_cells, lvl_pos, lvl_of;
+    // DIC dependencies in level order: for position q (cell lvl_cells[q]),
+    // lower dependency k (ascending neighbour index) at dl_*[k * N + q],
+    // upper ones at du_*[k * N + q]; *_pos = position of the neighbour,
+    // *_face = its face, -1 past the cell's count; lev_pos[q] = level of q
+    int32_t dW_lo = 0, dW_hi = 0;
+    std::vector<int32_t> dl_pos, dl_face, du_pos, du_face, lev_pos;
     // row-sliced copy of the off-diagonal structure (sliced ELL): slice s =
     // cells [256 s, 256 s + 256), sell_W slots per cell, entry (s, k, lane) at
     // (s * sell_W + k) * 256 + lane; a cell's entries in ascending column.
@@ -117,10 +123,17 @@ struct DevCase {
     double *rAU, *HbyA, *gradp, *phiH, *gam, *pdiag, *poff, *pb, *tno;
     // Krylov work vectors
     double *r, *rt, *pp, *pt, *q, *qt;           // [3][N] each (CG uses component 0)
-    double *y, *z;                               // [N] DIC forward / backward sweep outputs
-    double *dstar;                               // [N] DIC diagonal
-    int32_t *lvl_start, *lvl_cells, *lvl_pos, *lvl_of;   // DIC level schedule
+    double *z;                                   // [N] DIC preconditioned residual (cell order)
+    double *dstar;                               // [N] DIC diagonal (cell order, for diagnostics)
+    int32_t *lvl_start, *lvl_cells;              // DIC level schedule
     int32_t n_levels;
+    // DIC dependencies in level order (see fvm_mesh), their coefficients
+    // (refilled at the start of every solve) and the values published by the
+    // sweeps, indexed by level position: D*, y (forward), z (backward)
+    int32_t dW_lo, dW_hi;
+    int32_t *dl_pos, *dl_face, *du_pos, *du_face, *lev_pos;
+    double *dl_val, *du_val;
+    double *dq, *yq, *zq;
     // sliced-ELL copy of the pressure matrix (structure as in fvm_mesh)
     int32_t sell_W;
     int32_t *sell_mode, *sell_off, *sell_fe, *sell_col;

@@ -127,23 +127,42 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (&lds)[NV][kWa
 // would compile to a write-back of the whole L2 of the XCD; instead each
 // value is published by one device-scope atomic store, and the reader waits
 // on the slot itself, then refills it with the sentinel.
-__device__ __forceinline__ double slot_take(double *slot)
+// device-scope accesses through global-address-space pointers (a flat
+// access would also wait on the LDS counter)
+typedef __attribute__((address_space(1))) unsigned long long gword;
+__device__ __forceinline__ unsigned long long gld(const void *a)
 {
-    unsigned long long *w = reinterpret_cast<unsigned long long *>(slot);
-    unsigned long long b = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int spin = 0; b == kSentinel && spin < kSpinLimit; ++spin) {
-        __builtin_amdgcn_s_sleep(1);
-        b = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const gword *)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gst(void *a, unsigned long long v)
+{
+    __hip_atomic_store((gword *)a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// take NV published slots slot + k * stride (all loads issued before the
+// first comparison), re-arming each with the sentinel
+template <int NV>
+__device__ __forceinline__ void slots_take(double *slot, int stride, double (&out)[NV])
+{
+    unsigned long long b[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) b[k] = gld(slot + (long)k * stride);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        for (int spin = 0; b[k] == kSentinel && spin < kSpinLimit; ++spin) {
+            __builtin_amdgcn_s_sleep(1);
+            b[k] = gld(slot + (long)k * stride);
+        }
+        gst(slot + (long)k * stride, kSentinel);
+        out[k] = b[k] == kSentinel ? __longlong_as_double((long long)kQNaN) : __longlong_as_double((long long)b[k]);
     }
-    __hip_atomic_store(w, kSentinel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return b == kSentinel ? __longlong_as_double((long long)kQNaN) : __longlong_as_double((long long)b);
 }
 
 __device__ __forceinline__ void slot_put(double *slot, double v)
 {
     unsigned long long b = (unsigned long long)__double_as_longlong(v);
     if (b == kSentinel) b = kQNaN;
-    __hip_atomic_store(reinterpret_cast<unsigned long long *>(slot), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gst(slot, b);
 }
 
 // Two-level grid reduction.  Level 1: each block publishes its partials and
@@ -171,8 +190,8 @@ __device__ bool reduce_last(double (&v)[NV], const DevCase &d, const Blk &K, dou
     if (!stage) return false;
     double g[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-        g[k] = (int)threadIdx.x < gsize ? slot_take(&d.partials[k * d.red_stride + grp * kGroup + threadIdx.x]) : 0.0;
+    for (int k = 0; k < NV; ++k) g[k] = 0.0;
+    if ((int)threadIdx.x < gsize) slots_take<NV>(&d.partials[grp * kGroup + threadIdx.x], d.red_stride, g);
     block_sum(g, lds);
     if (threadIdx.x == 0) {
         __hip_atomic_store(&d.gticket[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -185,9 +204,12 @@ __device__ bool reduce_last(double (&v)[NV], const DevCase &d, const Blk &K, dou
     if (stage != 2) return false;
     double a[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        a[k] = 0.0;
-        for (int j = threadIdx.x; j < ngrp; j += kBlock) a[k] += slot_take(&d.partials2[k * d.red_stride2 + j]);
+    for (int k = 0; k < NV; ++k) a[k] = 0.0;
+    for (int j = threadIdx.x; j < ngrp; j += kBlock) {
+        double t[NV];
+        slots_take<NV>(&d.partials2[j], d.red_stride2, t);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) a[k] += t[k];
     }
     block_sum(a, lds);
     if (threadIdx.x == 0) {
@@ -1180,9 +1202,9 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(Batch bt, int dic)
         v[1] += fabs(r);
         if (!dic) v[2] += r * (r / d.pdiag[i]);
         else {
-            clear_word(d.dstar, i);
-            clear_word(d.y, i);
-            clear_word(d.z, i);
+            clear_word(d.dq, i);
+            clear_word(d.yq, i);
+            clear_word(d.zq, i);
         }
     }
     __shared__ double tot[3];
@@ -1230,10 +1252,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(Batch bt, int dic)
 // of hanging.  Per cell the sums run over neighbours in ascending index.
 // ---------------------------------------------------------------------------
 
+// device-scope load of a published word
+__device__ __forceinline__ unsigned long long dic_ld(const double *a, int j) { return gld(a + j); }
+
 __device__ __forceinline__ bool dic_try(const double *a, int j, double &v)
 {
-    const unsigned long long b =
-        __hip_atomic_load(reinterpret_cast<const unsigned long long *>(a + j), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long b = dic_ld(a, j);
     if (b == kSentinel) return false;
     v = __longlong_as_double((long long)b);
     return true;
@@ -1271,56 +1295,92 @@ constexpr int kDicDeps = 8;
 // front itself is not delayed by the gate.
 constexpr int kChunk = 64;
 
+// DIC coefficients in level order, refilled at the start of every solve
+// (the pressure matrix is symmetric: both triangles read poff)
+__global__ void __launch_bounds__(kBlock) k_dic_fill(Batch bt)
+{
+    CASE_OF(bt);
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
+    for (int q = rg.beg + threadIdx.x; q < rg.end; q += kBlock) {
+        for (int k = 0; k < d.dW_lo; ++k) {
+            const int f = d.dl_face[k * N + q];
+            d.dl_val[k * N + q] = f >= 0 ? d.poff[f] : 0.0;
+        }
+        for (int k = 0; k < d.dW_hi; ++k) {
+            const int f = d.du_face[k * N + q];
+            d.du_val[k * N + q] = f >= 0 ? d.poff[f] : 0.0;
+        }
+    }
+}
+
+// One wave processes 64 consecutive positions of the processing order (the
+// level order, reversed for MODE 2).  Dependencies, their coefficients and
+// the published values are all indexed by level position, so a lane's loads
+// are coalesced slot streams and a level's inputs form one contiguous range.
 template <int MODE>
 __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
 {
     const int n = d.N;
+    const long N = n;
     const int lane = threadIdx.x & 63;
-    const int pos = chunk * kChunk + lane;
-    const bool live = pos < n;
-    const int i = live ? (MODE == 2 ? d.lvl_cells[n - 1 - pos] : d.lvl_cells[pos]) : 0;
-    int k0, k1;
-    double acc;
-    const double *src;
-    if (MODE == 2) { k0 = d.own_start[i]; k1 = d.own_start[i + 1]; acc = 0.0; src = d.z; }
-    else { k0 = d.nbr_start[i]; k1 = d.nbr_start[i + 1]; acc = MODE == 0 ? d.pdiag[i] : d.r[i]; src = MODE == 0 ? d.dstar : d.y; }
-    if (!live) k1 = k0;
-    const int nd = k1 - k0;
-    const bool fast = nd <= kDicDeps;
+    const int q = chunk * kChunk + lane;          // processing position
+    const bool live = q < n;
+    const int fq = live ? (MODE == 2 ? n - 1 - q : q) : 0;   // level position
+    const int i = live ? d.lvl_cells[fq] : 0;
+    const int W = MODE == 2 ? d.dW_hi : d.dW_lo;
+    const int *__restrict__ DP = MODE == 2 ? d.du_pos : d.dl_pos;
+    const double *__restrict__ DV = MODE == 2 ? d.du_val : d.dl_val;
+    double *const src = MODE == 0 ? d.dq : (MODE == 1 ? d.yq : d.zq);
+    // all slots are loaded at once (independent loads); a cell's
+    // dependencies fill slots 0..nd-1
+    const bool fast = W <= kDicDeps;
     int js[kDicDeps];
     double as[kDicDeps], vs[kDicDeps];
+#pragma unroll
+    for (int t = 0; t < kDicDeps; ++t) {
+        js[t] = -1; as[t] = 0.0; vs[t] = 0.0;
+        if (live && fast && t < W) {
+            js[t] = DP[t * N + fq];
+            as[t] = DV[t * N + fq];
+        }
+    }
+    int nd = 0;
+    if (fast) {
+#pragma unroll
+        for (int t = 0; t < kDicDeps; ++t) nd += js[t] >= 0 ? 1 : 0;
+    } else if (live) {
+        while (nd < W && DP[nd * N + fq] >= 0) ++nd;
+    }
     int gate = -1;   // processing position of the latest dependency before this chunk
 #pragma unroll
     for (int t = 0; t < kDicDeps; ++t) {
-        js[t] = 0; as[t] = 0.0; vs[t] = 0.0;
-        if (fast && t < nd) {
-            const int f = MODE == 2 ? k0 + t : d.losort[k0 + t];
-            js[t] = MODE == 2 ? d.nei[f] : d.own[f];
-            as[t] = d.poff[f];
-            const int q = MODE == 2 ? n - 1 - d.lvl_pos[js[t]] : d.lvl_pos[js[t]];
-            if (q < chunk * kChunk && q > gate) gate = q;
+        if (js[t] >= 0) {
+            const int pd = MODE == 2 ? n - 1 - js[t] : js[t];
+            if (pd < chunk * kChunk && pd > gate) gate = pd;
         }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) gate = max(gate, __shfl_xor(gate, o, 64));
     if (gate >= 0) {
-        // the gate cell: last cell, in processing order, of the level one
+        // the gate: last position, in processing order, of the level one
         // step before that of the latest outside dependency
-        const int gl = d.lvl_of[MODE == 2 ? d.lvl_cells[n - 1 - gate] : d.lvl_cells[gate]];
-        int gp = -1;   // forward position of the gate cell
+        const int gl = d.lev_pos[MODE == 2 ? n - 1 - gate : gate];
+        int gp = -1;
         if (MODE == 2) { if (gl + 1 < d.n_levels) gp = d.lvl_start[gl + 1]; }
         else if (gl >= 1) gp = d.lvl_start[gl] - 1;
         if (gp >= 0) {
             // every lane loads the same word: one request per wave
-            const int gc = d.lvl_cells[gp];
             double v;
-            for (int sp = 0; sp < kSpinLimit && !dic_try(src, gc, v); ++sp) __builtin_amdgcn_s_sleep(1);
+            for (int sp = 0; sp < kSpinLimit && !dic_try(src, gp, v); ++sp) __builtin_amdgcn_s_sleep(1);
         }
     }
-    const double dsi = (MODE != 0 && live) ? d.dstar[i] : 1.0;
-    const double yi = (MODE == 2 && live) ? d.y[i] : 0.0;
+    double acc = 0.0;
+    if (live && MODE != 2) acc = MODE == 0 ? d.pdiag[i] : d.r[i];
+    const double dsi = (MODE != 0 && live) ? d.dq[fq] : 1.0;
+    const double yi = (MODE == 2 && live) ? d.yq[fq] : 0.0;
     unsigned int missing = fast ? (nd >= 32 ? 0xffffffffu : ((1u << nd) - 1u)) : 0u;
-    int k = k0;               // streaming path cursor
+    int k = 0;                // streaming path cursor
     double part = 0.0;
     bool fin = !live;
     int spins = 0;
@@ -1331,13 +1391,18 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
         if (!fin) {
             bool ready;
             if (fast) {
+                // issue every dependency load of the lane before the first
+                // comparison, so that they overlap instead of each waiting
+                // for the previous one
+                unsigned long long bv[kDicDeps];
 #pragma unroll
-                for (int t = 0; t < kDicDeps; ++t) {
-                    if (missing & (1u << t)) {
-                        double v;
-                        if (dic_try(src, js[t], v)) { vs[t] = v; missing &= ~(1u << t); }
+                for (int t = 0; t < kDicDeps; ++t) bv[t] = t < nd ? dic_ld(src, js[t]) : 0ull;
+#pragma unroll
+                for (int t = 0; t < kDicDeps; ++t)
+                    if (((missing >> t) & 1u) && bv[t] != kSentinel) {
+                        vs[t] = __longlong_as_double((long long)bv[t]);
+                        missing &= ~(1u << t);
                     }
-                }
                 ready = missing == 0u;
                 if (ready) {
 #pragma unroll
@@ -1351,12 +1416,10 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
                 }
             } else {
                 ready = true;
-                while (k < k1) {
-                    const int f = MODE == 2 ? k : d.losort[k];
-                    const int j = MODE == 2 ? d.nei[f] : d.own[f];
+                while (k < nd) {
                     double v;
-                    if (!dic_try(src, j, v)) { ready = false; break; }
-                    const double a = d.poff[f];
+                    if (!dic_try(src, DP[k * N + fq], v)) { ready = false; break; }
+                    const double a = DV[k * N + fq];
                     if (MODE == 0) acc -= a * a / v;
                     else if (MODE == 1) acc -= a * v;
                     else acc += a * v;
@@ -1364,18 +1427,23 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
                 }
             }
             if (ready) {
-                if (MODE == 0) dic_put(d.dstar, i, acc);
-                else if (MODE == 1) { dic_put(d.y, i, acc / dsi); clear_word(d.z, i); }
+                if (MODE == 0) { dic_put(d.dq, fq, acc); d.dstar[i] = acc; }
+                else if (MODE == 1) { dic_put(d.yq, fq, acc / dsi); clear_word(d.zq, fq); }
                 else {
                     const double zi = yi - acc / dsi;
-                    dic_put(d.z, i, zi);
-                    clear_word(d.y, i);
+                    dic_put(d.zq, fq, zi);
+                    d.z[i] = zi;
+                    clear_word(d.yq, fq);
                     part = d.r[i] * zi;
                 }
                 fin = true;
             } else if (++spins > kSpinLimit) {
-                dic_put(MODE == 0 ? d.dstar : (MODE == 1 ? d.y : d.z), i, __longlong_as_double((long long)kQNaN));
-                if (MODE == 2) part = __longlong_as_double((long long)kQNaN);
+                dic_put(src, fq, __longlong_as_double((long long)kQNaN));
+                if (MODE == 0) d.dstar[i] = __longlong_as_double((long long)kQNaN);
+                if (MODE == 2) {
+                    d.z[i] = __longlong_as_double((long long)kQNaN);
+                    part = __longlong_as_double((long long)kQNaN);
+                }
                 d.ticket[8] = 1u;
                 fin = true;
             }
@@ -1451,9 +1519,9 @@ __global__ void k_dic_reset(Batch bt)
         d.ks[3].status = FVM_OK;
     }
     if (i >= d.N) return;
-    clear_word(d.dstar, i);
-    clear_word(d.y, i);
-    clear_word(d.z, i);
+    clear_word(d.dq, i);
+    clear_word(d.yq, i);
+    clear_word(d.zq, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -1873,6 +1941,7 @@ void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s)
 {
     if (with_setup) {
         Prof p("dic_setup", s);
+        run(k_dic_fill, bs, SZ_CELL, s);
         run(k_dic_sweep<0>, bs, SZ_CELL, s);
     }
     {

@@ -222,6 +222,34 @@ fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
     m->lvl_pos.resize(N);
     for (int32_t k = 0; k < N; ++k) m->lvl_pos[m->lvl_cells[k]] = k;
     m->lvl_of = lev;
+    // dependencies in level order
+    {
+        int32_t wl = 0, wh = 0;
+        for (int32_t i = 0; i < N; ++i) {
+            wl = std::max(wl, m->nbr_start[i + 1] - m->nbr_start[i]);
+            wh = std::max(wh, m->own_start[i + 1] - m->own_start[i]);
+        }
+        m->dW_lo = std::max(wl, 1);
+        m->dW_hi = std::max(wh, 1);
+        m->dl_pos.assign((size_t)m->dW_lo * N, -1); m->dl_face.assign((size_t)m->dW_lo * N, -1);
+        m->du_pos.assign((size_t)m->dW_hi * N, -1); m->du_face.assign((size_t)m->dW_hi * N, -1);
+        m->lev_pos.resize(N);
+        for (int32_t q = 0; q < N; ++q) {
+            const int32_t i = m->lvl_cells[q];
+            m->lev_pos[q] = lev[i];
+            int32_t k = 0;
+            for (int32_t t = m->nbr_start[i]; t < m->nbr_start[i + 1]; ++t, ++k) {
+                const int32_t f = m->losort[t];
+                m->dl_pos[(size_t)k * N + q] = m->lvl_pos[m->own[f]];
+                m->dl_face[(size_t)k * N + q] = f;
+            }
+            k = 0;
+            for (int32_t f = m->own_start[i]; f < m->own_start[i + 1]; ++f, ++k) {
+                m->du_pos[(size_t)k * N + q] = m->lvl_pos[m->nei[f]];
+                m->du_face[(size_t)k * N + q] = f;
+            }
+        }
+    }
     build_sell(m);
     return FVM_OK;
 }
