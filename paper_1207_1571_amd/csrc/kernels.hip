@@ -1281,16 +1281,17 @@ __device__ __forceinline__ unsigned int xcc_id() { return __builtin_amdgcn_s_get
 // A cell's dependency list (neighbour index and coefficient) is read into
 // registers before polling, so each poll round is one batch of independent
 // device-scope loads of the values still missing; once all are present the
-// sum is formed in ascending neighbour order.  Cells with more than kDicDeps
-// dependencies take a streaming path that consumes them one at a time.
-constexpr int kDicDeps = 8;
+// sum is formed in ascending neighbour order.  D register slots (4 for hex
+// meshes, else 8; fewer registers keep more waves resident); meshes whose
+// cells have more than D dependencies take a streaming path that consumes
+// them one at a time.
 
 // Blocks claim tiles of 256 consecutive entries of the level order (reversed
 // for MODE 2); each wave of the block takes 64 of them.  Before its lanes
 // poll, a wave waits on a single word: the last cell (in processing order)
 // of the level before the level of its latest outside dependency.  The wave
 // thus starts polling about one level before its inputs complete: waves far
-// ahead of the front poll one address instead of up to 64 x kDicDeps, which
+// ahead of the front poll one address instead of up to 64 x D, which
 // keeps the XCD's L2 free for the hand-over traffic at the front, while the
 // front itself is not delayed by the gate.
 constexpr int kChunk = 64;
@@ -1318,7 +1319,7 @@ __global__ void __launch_bounds__(kBlock) k_dic_fill(Batch bt)
 // level order, reversed for MODE 2).  Dependencies, their coefficients and
 // the published values are all indexed by level position, so a lane's loads
 // are coalesced slot streams and a level's inputs form one contiguous range.
-template <int MODE>
+template <int MODE, int D>
 __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
 {
     const int n = d.N;
@@ -1334,11 +1335,11 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     double *const src = MODE == 0 ? d.dq : (MODE == 1 ? d.yq : d.zq);
     // all slots are loaded at once (independent loads); a cell's
     // dependencies fill slots 0..nd-1
-    const bool fast = W <= kDicDeps;
-    int js[kDicDeps];
-    double as[kDicDeps], vs[kDicDeps];
+    const bool fast = W <= D;
+    int js[D];
+    double as[D], vs[D];
 #pragma unroll
-    for (int t = 0; t < kDicDeps; ++t) {
+    for (int t = 0; t < D; ++t) {
         js[t] = -1; as[t] = 0.0; vs[t] = 0.0;
         if (live && fast && t < W) {
             js[t] = DP[t * N + fq];
@@ -1348,13 +1349,13 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     int nd = 0;
     if (fast) {
 #pragma unroll
-        for (int t = 0; t < kDicDeps; ++t) nd += js[t] >= 0 ? 1 : 0;
+        for (int t = 0; t < D; ++t) nd += js[t] >= 0 ? 1 : 0;
     } else if (live) {
         while (nd < W && DP[nd * N + fq] >= 0) ++nd;
     }
     int gate = -1;   // processing position of the latest dependency before this chunk
 #pragma unroll
-    for (int t = 0; t < kDicDeps; ++t) {
+    for (int t = 0; t < D; ++t) {
         if (js[t] >= 0) {
             const int pd = MODE == 2 ? n - 1 - js[t] : js[t];
             if (pd < chunk * kChunk && pd > gate) gate = pd;
@@ -1394,11 +1395,11 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
                 // issue every dependency load of the lane before the first
                 // comparison, so that they overlap instead of each waiting
                 // for the previous one
-                unsigned long long bv[kDicDeps];
+                unsigned long long bv[D];
 #pragma unroll
-                for (int t = 0; t < kDicDeps; ++t) bv[t] = t < nd ? dic_ld(src, js[t]) : 0ull;
+                for (int t = 0; t < D; ++t) bv[t] = t < nd ? dic_ld(src, js[t]) : 0ull;
 #pragma unroll
-                for (int t = 0; t < kDicDeps; ++t)
+                for (int t = 0; t < D; ++t)
                     if (((missing >> t) & 1u) && bv[t] != kSentinel) {
                         vs[t] = __longlong_as_double((long long)bv[t]);
                         missing &= ~(1u << t);
@@ -1406,7 +1407,7 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
                 ready = missing == 0u;
                 if (ready) {
 #pragma unroll
-                    for (int t = 0; t < kDicDeps; ++t) {
+                    for (int t = 0; t < D; ++t) {
                         if (t < nd) {
                             if (MODE == 0) acc -= as[t] * as[t] / vs[t];
                             else if (MODE == 1) acc -= as[t] * vs[t];
@@ -1454,8 +1455,8 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     return part;
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_dic_sweep(Batch bt)
+template <int MODE, int D>
+__global__ void __launch_bounds__(kBlock, D == 4 ? 6 : 4) k_dic_sweep(Batch bt)
 {
     CASE_OF(bt);
     if (d.ks[3].done) return;
@@ -1479,7 +1480,7 @@ __global__ void __launch_bounds__(kBlock) k_dic_sweep(Batch bt)
             const int tile = s_tile;
             __syncthreads();
             if ((long)tile * kBlock >= d.N) break;
-            part += dic_chunk<MODE>(d, tile * kWaves + (threadIdx.x >> 6));
+            part += dic_chunk<MODE, D>(d, tile * kWaves + (threadIdx.x >> 6));
         }
     }
     if (MODE == 2) {
@@ -1937,21 +1938,30 @@ void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s)
     run(k_pcg_init, bs, SZ_CELL, s, dic);
 }
 
-void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s)
+template <int D>
+void dic_sweeps(const BatchSet &bs, int with_setup, hipStream_t s)
 {
     if (with_setup) {
         Prof p("dic_setup", s);
         run(k_dic_fill, bs, SZ_CELL, s);
-        run(k_dic_sweep<0>, bs, SZ_CELL, s);
+        run(k_dic_sweep<0, D>, bs, SZ_CELL, s);
     }
     {
         Prof p("dic_fwd", s);
-        run(k_dic_sweep<1>, bs, SZ_CELL, s);
+        run(k_dic_sweep<1, D>, bs, SZ_CELL, s);
     }
     {
         Prof p("dic_bwd", s);
-        run(k_dic_sweep<2>, bs, SZ_CELL, s);
+        run(k_dic_sweep<2, D>, bs, SZ_CELL, s);
     }
+}
+
+void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s)
+{
+    int w = 0;
+    for (int c = 0; c < bs.n; ++c) w = std::max(w, std::max(bs.host[c]->dW_lo, bs.host[c]->dW_hi));
+    if (w <= 4) dic_sweeps<4>(bs, with_setup, s);
+    else dic_sweeps<8>(bs, with_setup, s);
 }
 
 void launch_dic_reset(const BatchSet &bs, hipStream_t s) { run(k_dic_reset, bs, SZ_CELL, s); }

@@ -279,6 +279,60 @@ def test_dic_apply_matches_oracle(shape, perm, rcm):
     assert bad.size == 0
 
 
+def _long_range_mesh(n, reach):
+    """Cells on a line (unit cubes at x = i + 1/2) with the regular faces
+    between neighbours and extra faces of area 0.1 between cells i and i + k
+    for k = 2..reach, so a cell has up to `reach` lower and upper neighbours;
+    the two end faces form the only patch."""
+    own, nei, S, Cf = [], [], [], []
+    for i in range(n):
+        for k in range(1, reach + 1):
+            if i + k < n:
+                a = 1.0 if k == 1 else 0.1
+                own.append(i); nei.append(i + k)
+                S.append((a, 0.0, 0.0)); Cf.append((i + 0.5 + k / 2.0, 0.5, 0.5))
+    Fi = len(own)
+    own += [0, n - 1]
+    S += [(-1.0, 0.0, 0.0), (1.0, 0.0, 0.0)]
+    Cf += [(0.0, 0.5, 0.5), (float(n), 0.5, 0.5)]
+    C = np.array([(i + 0.5, 0.5, 0.5) for i in range(n)])
+    return mg.Mesh(owner=np.array(own, np.int32), neighbour=np.array(nei, np.int32), Sf=np.array(S),
+                   Cf=np.array(Cf), C=C, V=np.ones(n), patch_names=["ends"],
+                   patch_start=np.array([Fi], np.int32), patch_size=np.array([2], np.int32), shape=(n, 1, 1),
+                   lex_of_cell=np.arange(n))
+
+
+@pytest.mark.parametrize("reach,perm", [(6, None), (11, 9)])
+def test_dic_apply_many_dependencies(reach, perm):
+    """Cells with more dependencies than the 4 register slots (reach 6 in
+    natural order: at most 6 per side, the 8-slot variant) or than 8 (reach
+    11, permuted: the streaming path)."""
+    import torch
+    from paper_1207_1571_amd import fvm
+    m = _long_range_mesh(300, reach)
+    if perm is not None:
+        m = mg.random_permutation(m, perm)
+    bcs = [wl.PatchBC(wl.FIXED, wl.FIXED)]
+    case = wl.CaseSpec(name="long-range", mesh=m, bcs=bcs, nu=0.1, dt=0.01, p_ref_cell=0,
+                       p_ctl=wl.SolverCtl(1e-10, precond=wl.PC_DIC), u_ctl=wl.SolverCtl(1e-10))
+    Fi = m.n_internal
+    rng = np.random.default_rng(8)
+    gamma = rng.uniform(0.5, 2.0, m.n_faces)
+    r = rng.normal(size=m.n_cells)
+    pk = np.full(m.n_faces - Fi, wl.FIXED, np.int32)
+    diag, offd, _ = orc.pressure_system(m, gamma, pk, np.zeros(m.n_faces - Fi), pin_cell=case.p_ref_cell,
+                                        p_ref=case.p_ref_value)
+    ds_o, z_o = orc.dic(m.owner[:Fi].copy(), m.neighbour.copy(), diag, offd, r)
+    c = fvm.Case(case)
+    zg = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
+    dg = torch.empty(m.n_cells, dtype=torch.float64, device="cuda")
+    fvm.dic_apply(c, torch.from_numpy(gamma).cuda(), torch.from_numpy(r).cuda(), zg, dg)
+    zg, dg = zg.cpu().numpy(), dg.cpu().numpy()
+    _say(f"  reach {reach}: max |D* diff| {np.abs(dg - ds_o).max():.2e}, max |z diff| {np.abs(zg - z_o).max():.2e}")
+    assert np.all(np.isfinite(dg)) and np.all(np.abs(dg - ds_o) <= 1e-12 * np.abs(ds_o))
+    assert np.all(np.isfinite(zg)) and np.all(np.abs(zg - z_o) <= 1e-10 * np.abs(z_o).max())
+
+
 TOL_MIXED = 1e-6
 
 
