@@ -52,6 +52,7 @@ def algorithmic_bytes(cls: str, N: int, Fi: int, dic: bool) -> float:
         "dic_bwd": 32 * N + 16 * Fi,               # y, D*, r, z out; upper faces
         "dic_setup": 16 * N + 16 * Fi,             # diag, D* out; lower faces
         "bicg_spmv": 104 * N + 24 * Fi,            # 3 components, A and A^T
+        "bicgstab_spmv": 80 * N + 12 * Fi,         # 3 components: x in, y out, r~ or s in; diag, upper, lower, 2 int32
         "pcg32_spmv": 12 * N + 12 * Fi,            # FP32 inner: diag, x, y + coefficient + 2 int32
         "pcg32_update": 36 * N,                    # x (FP64) in/out, p, r, q, diag (FP32) in; r out
         "pcg32_dir": 16 * N,

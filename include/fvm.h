@@ -60,6 +60,11 @@ enum { FVM_PC_JACOBI = 0, FVM_PC_DIC = 1 };
  * iterations run in FP32 inside an FP64 residual-refinement loop. */
 enum { FVM_FP64 = 0, FVM_MIXED = 1 };
 enum { FVM_CONV_LINEAR = 0, FVM_CONV_UPWIND = 1 };
+/* Momentum solver: bi-conjugate gradients (A and A^T products per
+ * iteration), or BiCGStab (two A products per iteration, no A^T; the
+ * method the paper's GPU solver uses for momentum, Section 4.2), both
+ * Jacobi-preconditioned after Barrett et al.  BiCGStab is FP64 only. */
+enum { FVM_SOLVER_BICG = 0, FVM_SOLVER_BICGSTAB = 1 };
 
 typedef struct fvm_mesh fvm_mesh;
 typedef struct fvm_case fvm_case;
@@ -111,6 +116,8 @@ typedef struct {
     int32_t p_ref_cell;    /* caller's cell index */
     int32_t inner_max_iter;
     fvm_solver_ctl p_ctl, u_ctl;
+    int32_t u_solver;      /* FVM_SOLVER_* for the momentum equation */
+    int32_t reserved;      /* must be 0 */
 } fvm_case_opts;
 
 typedef struct {

@@ -58,7 +58,7 @@ typedef struct {
     double nu, dt, alpha_u, alpha_p, p_ref_value;
     double p_tol, p_rel_tol, u_tol, u_rel_tol;
     int32_t n_corr, n_non_orth_corr, convection, p_ref_cell;
-    int32_t p_max_iter, p_precond, u_max_iter, pad;
+    int32_t p_max_iter, p_precond, u_max_iter, u_solver;   /* u_solver: 0 BiCG, 1 BiCGStab */
 } orc_opts;
 
 typedef struct { int32_t iters, status; double res_initial, res_final; } orc_solve_info;
@@ -484,6 +484,81 @@ done:
 }
 
 /* ------------------------------------------------------------------------
+ * Preconditioned BiCGSTAB (Barrett et al., Sec. 2.3.8) with Jacobi M and
+ * shadow residual r~ = r0.  Per iteration: rho = r~.r; p = r (first) or
+ * r + beta (p - omega v) with beta = (rho / rho_old)(alpha / omega);
+ * p^ = M^-1 p; v = A p^; alpha = rho / (r~.v); s = r - alpha v; if s passes
+ * the stopping test, x += alpha p^ and stop; else s^ = M^-1 s; t = A s^;
+ * omega = (t.s) / (t.t); x += alpha p^ + omega s^; r = s - omega t.
+ * Stopping test as pcg() (normalised L1 residual, also on s).  Breakdown
+ * (rho == 0, r~.v == 0, t.t == 0, omega == 0, non-finite) -> ST_ENUMERIC.
+ * ---------------------------------------------------------------------- */
+static int pbicgstab(const ldu *A, const double *b, double *x, double tol, double rel_tol, int32_t max_iter,
+                     orc_solve_info *info)
+{
+    int32_t N = A->N;
+    double *r = dalloc(N), *rt = dalloc(N), *p = dalloc(N), *v = dalloc(N);
+    double *sv = dalloc(N), *t = dalloc(N), *ph = dalloc(N), *sh = dalloc(N);
+    int st = ST_OK;
+    info->iters = 0;
+    amul(A, x, v);
+    for (int32_t i = 0; i < N; ++i) { r[i] = b[i] - v[i]; rt[i] = r[i]; }
+    double nf = norm_factor(A, x, b, v);
+    double nres = sumabs(N, r) / nf;
+    info->res_initial = nres;
+    info->res_final = nres;
+    double tol_eff = fmax(tol, rel_tol * nres);
+    if (!isfinite(nres)) { st = ST_ENUMERIC; goto done; }
+    if (nres <= tol_eff) goto done;
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    st = ST_MAXITER;
+    for (int32_t it = 1; it <= max_iter; ++it) {
+        double rho = sumdot(N, rt, r);
+        if (rho == 0.0 || !isfinite(rho)) { st = ST_ENUMERIC; info->iters = it; break; }
+        if (it == 1) {
+            for (int32_t i = 0; i < N; ++i) p[i] = r[i];
+        } else {
+            double beta = (rho / rho_old) * (alpha / omega);
+            for (int32_t i = 0; i < N; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+        for (int32_t i = 0; i < N; ++i) ph[i] = p[i] / A->diag[i];
+        amul(A, ph, v);
+        double rtv = sumdot(N, rt, v);
+        if (rtv == 0.0 || !isfinite(rtv)) { st = ST_ENUMERIC; info->iters = it; break; }
+        alpha = rho / rtv;
+        for (int32_t i = 0; i < N; ++i) sv[i] = r[i] - alpha * v[i];
+        double ns = sumabs(N, sv) / nf;
+        info->iters = it;
+        if (!isfinite(ns)) { info->res_final = ns; st = ST_ENUMERIC; break; }
+        if (ns <= tol_eff) {
+            for (int32_t i = 0; i < N; ++i) { x[i] += alpha * ph[i]; r[i] = sv[i]; }
+            info->res_final = ns;
+            st = ST_OK;
+            break;
+        }
+        for (int32_t i = 0; i < N; ++i) sh[i] = sv[i] / A->diag[i];
+        amul(A, sh, t);
+        double tt = sumdot(N, t, t), ts = sumdot(N, t, sv);
+        if (tt == 0.0 || !isfinite(tt) || !isfinite(ts)) { st = ST_ENUMERIC; break; }
+        omega = ts / tt;
+        for (int32_t i = 0; i < N; ++i) {
+            x[i] += alpha * ph[i] + omega * sh[i];
+            r[i] = sv[i] - omega * t[i];
+        }
+        nres = sumabs(N, r) / nf;
+        info->res_final = nres;
+        if (!isfinite(nres)) { st = ST_ENUMERIC; break; }
+        if (nres <= tol_eff) { st = ST_OK; break; }
+        if (omega == 0.0) { st = ST_ENUMERIC; break; }
+        rho_old = rho;
+    }
+done:
+    free(r); free(rt); free(p); free(v); free(sv); free(t); free(ph); free(sh);
+    info->status = st;
+    return st;
+}
+
+/* ------------------------------------------------------------------------
  * Momentum matrix (one matrix for all three components).
  * Internal face f, P owner, N neighbour, face flux F = phi_f, weight w
  * (upwind: w = 1 if F >= 0 else 0):
@@ -739,7 +814,8 @@ static int32_t momentum_solve(work *w, const orc_opts *o, double *U, orc_step_in
             w->rhs[i] = w->src[3 * i + c] - m->V[i] * w->gradp[3 * i + c];
             w->xc[i] = U[3 * i + c];
         }
-        pbicg(&A, w->rhs, w->xc, o->u_tol, o->u_rel_tol, o->u_max_iter, &info->u[c]);
+        if (o->u_solver == 1) pbicgstab(&A, w->rhs, w->xc, o->u_tol, o->u_rel_tol, o->u_max_iter, &info->u[c]);
+        else pbicg(&A, w->rhs, w->xc, o->u_tol, o->u_rel_tol, o->u_max_iter, &info->u[c]);
         worst_status(&st, info->u[c].status);
         for (int32_t i = 0; i < w->N; ++i) U[3 * i + c] = w->xc[i];
     }
@@ -864,6 +940,14 @@ int orc_pbicg(int32_t N, int32_t Fi, const int32_t *own, const int32_t *nei, con
 {
     ldu A = {N, Fi, own, nei, diag, upper, lower};
     return pbicg(&A, b, x, tol, rel_tol, max_iter, info);
+}
+
+int orc_pbicgstab(int32_t N, int32_t Fi, const int32_t *own, const int32_t *nei, const double *diag, const double *upper,
+              const double *lower, const double *b, double *x, double tol, double rel_tol, int32_t max_iter,
+              orc_solve_info *info)
+{
+    ldu A = {N, Fi, own, nei, diag, upper, lower};
+    return pbicgstab(&A, b, x, tol, rel_tol, max_iter, info);
 }
 
 int orc_dic(int32_t N, int32_t Fi, const int32_t *own, const int32_t *nei, const double *diag, const double *offd,

@@ -37,7 +37,7 @@ class OrcOpts(ct.Structure):
                 ("u_tol", ct.c_double), ("u_rel_tol", ct.c_double), ("n_corr", ct.c_int32),
                 ("n_non_orth_corr", ct.c_int32), ("convection", ct.c_int32), ("p_ref_cell", ct.c_int32),
                 ("p_max_iter", ct.c_int32), ("p_precond", ct.c_int32), ("u_max_iter", ct.c_int32),
-                ("pad", ct.c_int32)]
+                ("u_solver", ct.c_int32)]
 
 
 class OrcSolveInfo(ct.Structure):
@@ -89,6 +89,7 @@ def lib():
                               ct.c_int32, ct.c_int32, SI]
         L.orc_pbicg.argtypes = [ct.c_int32, ct.c_int32, i32p, i32p, f64p, f64p, f64p, f64p, f64p, ct.c_double,
                                 ct.c_double, ct.c_int32, SI]
+        L.orc_pbicgstab.argtypes = L.orc_pbicg.argtypes
         L.orc_dic.argtypes = [ct.c_int32, ct.c_int32, i32p, i32p, f64p, f64p, f64p, f64p, f64p]
         L.orc_nres.argtypes = [ct.c_int32, ct.c_int32, i32p, i32p, f64p, f64p, f64p, f64p, f64p]
         L.orc_nres.restype = ct.c_double
@@ -150,7 +151,8 @@ class OMesh:
 def opts_from_case(case) -> OrcOpts:
     return OrcOpts(case.nu, case.dt, case.alpha_u, case.alpha_p, case.p_ref_value, case.p_ctl.tol,
                    case.p_ctl.rel_tol, case.u_ctl.tol, case.u_ctl.rel_tol, case.n_corr, case.n_non_orth_corr,
-                   case.convection, case.p_ref_cell, case.p_ctl.max_iter, case.p_ctl.precond, case.u_ctl.max_iter, 0)
+                   case.convection, case.p_ref_cell, case.p_ctl.max_iter, case.p_ctl.precond, case.u_ctl.max_iter,
+                   case.u_solver)
 
 
 # ---------------------------------------------------------------------------
@@ -261,6 +263,14 @@ def pbicg(own, nei, diag, upper, lower, b, x0, tol, rel_tol=0.0, max_iter=10000)
     info = OrcSolveInfo()
     lib().orc_pbicg(diag.shape[0], nei.shape[0], _i(own), _i(nei), _f(diag), _f(upper), _f(lower), _f(b), _f(x), tol,
                     rel_tol, max_iter, ct.byref(info))
+    return x, info.as_dict()
+
+
+def pbicgstab(own, nei, diag, upper, lower, b, x0, tol, rel_tol=0.0, max_iter=10000):
+    x = np.array(x0, np.float64)
+    info = OrcSolveInfo()
+    lib().orc_pbicgstab(diag.shape[0], nei.shape[0], _i(own), _i(nei), _f(diag), _f(upper), _f(lower), _f(b), _f(x),
+                        tol, rel_tol, max_iter, ct.byref(info))
     return x, info.as_dict()
 
 

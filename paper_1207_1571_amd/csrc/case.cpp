@@ -177,12 +177,16 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
     d.rAU = b.take<double>(N); d.HbyA = b.take<double>(3 * N); d.gradp = b.take<double>(3 * N);
     d.phiH = b.take<double>(F); d.gam = b.take<double>(F); d.pdiag = b.take<double>(N); d.poff = b.take<double>(Fi);
     d.pb = b.take<double>(N);
-    // Krylov vectors; the setup temporaries (cell and face centres) alias them
-    const size_t kv = std::max(18 * N, 3 * N + 3 * F);
+    // Krylov vectors; the setup temporaries (cell and face centres) alias them.
+    // BiCGStab: r, r~, p, v, s, t in r..qt, and p^, s^ after them
+    const bool stab = o.u_solver == FVM_SOLVER_BICGSTAB;
+    d.u_stab = stab;
+    const size_t kv = std::max((stab ? 24 : 18) * N, 3 * N + 3 * F);
     double *kbase = b.take<double>(kv);
     if (kbase) {
         d.r = kbase; d.rt = kbase + 3 * N; d.pp = kbase + 6 * N; d.pt = kbase + 9 * N; d.q = kbase + 12 * N;
         d.qt = kbase + 15 * N;
+        if (stab) { d.ph = kbase + 18 * N; d.sh = kbase + 21 * N; }
         d.tmpC = kbase; d.tmpCf = kbase + 3 * N;
     }
     if (dic) {
@@ -241,6 +245,11 @@ fvm_status check_opts(const fvm_mesh *m, const fvm_case_opts *o)
         return fvm_fail(FVM_EINVAL, "case: tolerances must be >= 0");
     if (o->convection != FVM_CONV_LINEAR && o->convection != FVM_CONV_UPWIND)
         return fvm_fail(FVM_EINVAL, "case: bad convection scheme");
+    if (o->u_solver != FVM_SOLVER_BICG && o->u_solver != FVM_SOLVER_BICGSTAB)
+        return fvm_fail(FVM_EINVAL, "case: bad momentum solver");
+    if (o->u_solver == FVM_SOLVER_BICGSTAB && o->precision != FVM_FP64)
+        return fvm_fail(FVM_EINVAL, "case: the BiCGStab momentum solver is FP64 only");
+    if (o->reserved != 0) return fvm_fail(FVM_EINVAL, "case: reserved option field must be 0");
     return FVM_OK;
 }
 
@@ -599,13 +608,15 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
     for (auto *c : g.cs)
         max_iter = std::max<long>(max_iter, ctl_src == 2 ? ctl->max_iter : kind == 0 ? c->o.u_ctl.max_iter : c->o.p_ctl.max_iter);
     launch_set_ctl(bs, first, count, ctl_src, ctl ? ctl->tol : 0.0, ctl ? ctl->rel_tol : 0.0, ctl ? ctl->max_iter : 0, s);
-    if (kind == 0) launch_bicg_init(bs, s);
+    if (kind == 0) launch_bicg_init(bs, c0->o.u_solver == FVM_SOLVER_BICGSTAB, s);
     else launch_pcg_init(bs, dic, s);
     fvm_status st;
     if (!mixed) {
         if (dic) launch_dic_precond(bs, 1, s);
+        const bool stab = kind == 0 && c0->o.u_solver == FVM_SOLVER_BICGSTAB;
         st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 1, [&] {
-            if (kind == 0) launch_bicg_iter(bs, s);
+            if (stab) launch_bicgstab_iter(bs, s);
+            else if (kind == 0) launch_bicg_iter(bs, s);
             else launch_pcg_iter(bs, dic, s);
         }, res);
         if (st != FVM_OK) return st;
@@ -860,8 +871,9 @@ extern "C" fvm_status piso_step_batch(fvm_case *const *cases, int32_t n, int32_t
         if (!(c->o.dt > 0.0)) return fvm_fail(FVM_EINVAL, "piso: dt must be > 0");
         const fvm_case *a = cases[0];
         if (c->o.precision != a->o.precision || c->o.n_corr != a->o.n_corr ||
-            c->o.n_non_orth_corr != a->o.n_non_orth_corr || c->o.p_ctl.precond != a->o.p_ctl.precond)
-            return fvm_fail(FVM_EINVAL, "batch: cases must share precision, correctors and preconditioner");
+            c->o.n_non_orth_corr != a->o.n_non_orth_corr || c->o.p_ctl.precond != a->o.p_ctl.precond ||
+            c->o.u_solver != a->o.u_solver)
+            return fvm_fail(FVM_EINVAL, "batch: cases must share precision, correctors, preconditioner and momentum solver");
         for (int j = 0; j < i; ++j)
             if (cases[j] == c) return fvm_fail(FVM_EINVAL, "batch: a case appears twice");
     }

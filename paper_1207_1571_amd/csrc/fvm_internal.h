@@ -74,13 +74,14 @@ struct KState {
     double xbar;
     double tol, rel_tol;
     double scale;     // mixed precision: scaling of the demoted residual
-    double pad0;
+    double omega;     // BiCGStab
     int32_t iters;
     int32_t done;     // 1: converged / stopped / failed; every iteration kernel is then a no-op
     int32_t status;   // FVM_OK, FVM_WARN_MAXITER, FVM_ENUMERIC
     int32_t max_iter;
     int32_t first;    // 1 before the first direction update
-    int32_t pad[3];
+    int32_t half;     // BiCGStab: the half-step residual s passed the stopping test
+    int32_t pad[2];
 };
 static_assert(sizeof(KState) == 128, "KState layout");
 
@@ -123,6 +124,8 @@ struct DevCase {
     double *rAU, *HbyA, *gradp, *phiH, *gam, *pdiag, *poff, *pb, *tno;
     // Krylov work vectors
     double *r, *rt, *pp, *pt, *q, *qt;           // [3][N] each (CG uses component 0)
+    double *ph, *sh;                             // [3][N] BiCGStab: preconditioned p and s
+    int32_t u_stab;                              // momentum solver is BiCGStab
     double *z;                                   // [N] DIC preconditioned residual (cell order)
     double *dstar;                               // [N] DIC diagonal (cell order, for diagnostics)
     int32_t *lvl_start, *lvl_cells;              // DIC level schedule
@@ -221,8 +224,10 @@ void launch_set_ctl(const BatchSet &bs, int first, int count, int src, double to
 void launch_gather_ks(const BatchSet &bs, hipStream_t s);
 
 // Krylov: momentum BiCG on the three components (FP64)
-void launch_bicg_init(const BatchSet &bs, hipStream_t s);
+void launch_bicg_init(const BatchSet &bs, int stab, hipStream_t s);
 void launch_bicg_iter(const BatchSet &bs, hipStream_t s);
+// Krylov: momentum BiCGStab on the three components (FP64)
+void launch_bicgstab_iter(const BatchSet &bs, hipStream_t s);
 // Krylov: pressure CG (FP64), Jacobi or DIC
 void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s);
 void launch_pcg_iter(const BatchSet &bs, int dic, hipStream_t s);

@@ -946,7 +946,9 @@ __global__ void __launch_bounds__(kBlock) k_bicg_sumx(Batch bt)
 }
 
 // FP64 start: r = b - A x, r~ = r, normalisation, first rho = z.r~
-__global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt)
+// momentum solve start: r = b - A x, r~ = r; normalisation; rho = z.r~
+// (BiCG) or r.r~ (BiCGStab, stab != 0)
+__global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt, int stab)
 {
     CASE_OF(bt);
     const Range rg = block_range(d.N, K);
@@ -966,8 +968,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt)
             d.rt[c * N + i] = r;
             v[c] += fabs(ax - xb[c] * a1) + fabs(b - xb[c] * a1);
             v[3 + c] += fabs(r);
-            const double z = r / dg;
-            v[6 + c] += z * r;
+            v[6 + c] += stab ? r * r : (r / dg) * r;
         }
     }
     __shared__ double tot[9];
@@ -983,12 +984,176 @@ __global__ void __launch_bounds__(kBlock) k_bicg_init(Batch bt)
             s.status = FVM_OK;
             s.first = 1;
             s.beta = 0.0;
+            s.omega = 1.0;
+            s.half = 0;
             if (!isfinite(s.nres0)) set_done(s, FVM_ENUMERIC);
             else if (s.nres0 <= s.tol_eff) set_done(s, FVM_OK);
             else if (tot[6 + c] == 0.0 || !isfinite(tot[6 + c])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
             else s.rho = tot[6 + c];
         }
     }
+}
+
+// ---- BiCGStab (Barrett et al., Jacobi; three components) ----------------
+// vectors: r, r~ = rt, p = pp, v = q, s = pt, t = qt, p^ = ph, s^ = sh
+
+// p = r (first iteration) or r + beta (p - omega v); p^ = p / diag
+__global__ void k_bs_dir(Batch bt)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const long N = d.N;
+    const double dg = d.mdiag[i];
+    for (int c = 0; c < 3; ++c) {
+        const KState &s = d.ks[c];
+        if (s.done) continue;
+        const long j = c * N + i;
+        const double p = s.first ? d.r[j] : d.r[j] + s.beta * (d.pp[j] - s.omega * d.q[j]);
+        d.pp[j] = p;
+        d.ph[j] = p / dg;
+    }
+}
+
+// v = A p^; r~.v -> alpha = rho / (r~.v)
+__global__ void __launch_bounds__(kBlock) k_bs_spmv_v(Batch bt)
+{
+    CASE_OF(bt);
+    int act[3];
+    for (int c = 0; c < 3; ++c) act[c] = !d.ks[c].done;
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock)
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const double v = row_apply<double>(d, i, d.mdiag, d.upper, d.lower, d.ph + c * N);
+            d.q[c * N + i] = v;
+            acc[c] += d.rt[c * N + i] * v;
+        }
+    __shared__ double tot[3];
+    if (reduce_last<3>(acc, d, K, tot) && threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = d.ks[c];
+            if (tot[c] == 0.0 || !isfinite(tot[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else s.alpha = s.rho / tot[c];
+        }
+}
+
+// s = r - alpha v, s^ = s / diag; |s| -> the half-step stopping test
+__global__ void __launch_bounds__(kBlock) k_bs_s(Batch bt)
+{
+    CASE_OF(bt);
+    int act[3];
+    double al[3];
+    for (int c = 0; c < 3; ++c) { act[c] = !d.ks[c].done; al[c] = d.ks[c].alpha; }
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const double dg = d.mdiag[i];
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const long j = c * N + i;
+            const double sv = d.r[j] - al[c] * d.q[j];
+            d.pt[j] = sv;
+            d.sh[j] = sv / dg;
+            acc[c] += fabs(sv);
+        }
+    }
+    __shared__ double tot[3];
+    if (reduce_last<3>(acc, d, K, tot) && threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = d.ks[c];
+            s.iters += 1;
+            const double ns = tot[c] / s.nf;
+            if (!isfinite(ns)) { s.nres = ns; set_done(s, FVM_ENUMERIC); }
+            else if (ns <= s.tol_eff) { s.nres = ns; s.half = 1; }
+        }
+}
+
+// t = A s^; t.t and t.s -> omega (not for a system stopped at the half step)
+__global__ void __launch_bounds__(kBlock) k_bs_spmv_t(Batch bt)
+{
+    CASE_OF(bt);
+    int act[3];
+    for (int c = 0; c < 3; ++c) act[c] = !d.ks[c].done && !d.ks[c].half;
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock)
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const double t = row_apply<double>(d, i, d.mdiag, d.upper, d.lower, d.sh + c * N);
+            d.qt[c * N + i] = t;
+            acc[c] += t * t;
+            acc[3 + c] += t * d.pt[c * N + i];
+        }
+    __shared__ double tot[6];
+    if (reduce_last<6>(acc, d, K, tot) && threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = d.ks[c];
+            if (tot[c] == 0.0 || !isfinite(tot[c]) || !isfinite(tot[3 + c])) set_done(s, FVM_ENUMERIC);
+            else s.omega = tot[3 + c] / tot[c];
+        }
+}
+
+// half step: x += alpha p^, r = s, stop; else x += alpha p^ + omega s^,
+// r = s - omega t; |r| -> stop test; rho = r~.r, beta for the next step
+__global__ void __launch_bounds__(kBlock) k_bs_update(Batch bt)
+{
+    CASE_OF(bt);
+    int act[3], half[3];
+    double al[3], om[3];
+    for (int c = 0; c < 3; ++c) {
+        act[c] = !d.ks[c].done;
+        half[c] = d.ks[c].half;
+        al[c] = d.ks[c].alpha;
+        om[c] = d.ks[c].omega;
+    }
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock)
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const long j = c * N + i;
+            if (half[c]) {
+                d.U[j] += al[c] * d.ph[j];
+                d.r[j] = d.pt[j];
+            } else {
+                d.U[j] += al[c] * d.ph[j] + om[c] * d.sh[j];
+                const double r = d.pt[j] - om[c] * d.qt[j];
+                d.r[j] = r;
+                acc[c] += fabs(r);
+                acc[3 + c] += d.rt[j] * r;
+            }
+        }
+    __shared__ double tot[6];
+    if (reduce_last<6>(acc, d, K, tot) && threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = d.ks[c];
+            s.first = 0;
+            if (half[c]) { s.half = 0; set_done(s, FVM_OK); continue; }
+            s.nres = tot[c] / s.nf;
+            if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
+            else if (s.nres <= s.tol_eff) set_done(s, FVM_OK);
+            else if (s.omega == 0.0) set_done(s, FVM_ENUMERIC);
+            else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+            else if (tot[3 + c] == 0.0 || !isfinite(tot[3 + c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else {
+                s.beta = (tot[3 + c] / s.rho) * (s.alpha / s.omega);
+                s.rho = tot[3 + c];
+            }
+        }
 }
 
 // ---- CG ----------------------------------------------------------------
@@ -1915,10 +2080,25 @@ void launch_set_ctl(const BatchSet &bs, int first, int count, int src, double to
 }
 void launch_gather_ks(const BatchSet &bs, hipStream_t s) { run(k_gather_ks, bs, SZ_CELL, s); }
 
-void launch_bicg_init(const BatchSet &bs, hipStream_t s)
+void launch_bicg_init(const BatchSet &bs, int stab, hipStream_t s)
 {
     run(k_bicg_sumx, bs, SZ_CELL, s);
-    run(k_bicg_init, bs, SZ_CELL, s);
+    run(k_bicg_init, bs, SZ_CELL, s, stab);
+}
+
+void launch_bicgstab_iter(const BatchSet &bs, hipStream_t s)
+{
+    run(k_bs_dir, bs, SZ_CELL, s);
+    {
+        Prof p("bicgstab_spmv", s);
+        run(k_bs_spmv_v, bs, SZ_CELL, s);
+    }
+    run(k_bs_s, bs, SZ_CELL, s);
+    {
+        Prof p("bicgstab_spmv", s);
+        run(k_bs_spmv_t, bs, SZ_CELL, s);
+    }
+    run(k_bs_update, bs, SZ_CELL, s);
 }
 
 void launch_bicg_iter(const BatchSet &bs, hipStream_t s)

@@ -46,7 +46,7 @@ class FvmCaseOpts(ct.Structure):
                 ("p_ref_value", ct.c_double), ("inner_rel_tol", ct.c_double), ("n_corr", ct.c_int32),
                 ("n_non_orth_corr", ct.c_int32), ("convection", ct.c_int32), ("precision", ct.c_int32),
                 ("p_ref_cell", ct.c_int32), ("inner_max_iter", ct.c_int32), ("p_ctl", FvmSolverCtl),
-                ("u_ctl", FvmSolverCtl)]
+                ("u_ctl", FvmSolverCtl), ("u_solver", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class FvmSolveInfo(ct.Structure):
@@ -170,7 +170,8 @@ def opts_from_case(case) -> FvmCaseOpts:
                        case.n_corr, case.n_non_orth_corr, case.convection, case.precision, case.p_ref_cell,
                        case.inner_max_iter,
                        FvmSolverCtl(case.p_ctl.tol, case.p_ctl.rel_tol, case.p_ctl.max_iter, case.p_ctl.precond),
-                       FvmSolverCtl(case.u_ctl.tol, case.u_ctl.rel_tol, case.u_ctl.max_iter, case.u_ctl.precond))
+                       FvmSolverCtl(case.u_ctl.tol, case.u_ctl.rel_tol, case.u_ctl.max_iter, case.u_ctl.precond),
+                       getattr(case, "u_solver", 0), 0)
 
 
 def workspace_bytes(mesh: Mesh, opts: FvmCaseOpts) -> int:

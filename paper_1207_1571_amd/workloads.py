@@ -24,6 +24,7 @@ FIXED, ZERO_GRAD, EMPTY = 0, 1, 2
 PC_JACOBI, PC_DIC = 0, 1
 FP64, MIXED = 0, 1
 CONV_LINEAR, CONV_UPWIND = 0, 1
+SOLVER_BICG, SOLVER_BICGSTAB = 0, 1   # momentum solver
 
 
 @dataclass
@@ -61,6 +62,7 @@ class CaseSpec:
     precision: int = FP64
     inner_rel_tol: float = 1e-3
     inner_max_iter: int = 2000
+    u_solver: int = SOLVER_BICG
     p_ctl: SolverCtl = field(default_factory=lambda: SolverCtl(1e-6))
     u_ctl: SolverCtl = field(default_factory=lambda: SolverCtl(1e-6))
     mode: str = "piso"            # "piso" | "simple"

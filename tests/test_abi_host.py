@@ -132,10 +132,20 @@ def test_option_checks():
     bad = [dict(nu=0.0), dict(n_corr=0), dict(n_corr=4, n_non_orth_corr=4), dict(p_ref_cell=m.n_cells),
            dict(precision=7), dict(convection=9), dict(p_ctl=wl.SolverCtl(1e-6, max_iter=0)),
            dict(u_ctl=wl.SolverCtl(-1.0)), dict(precision=wl.MIXED, p_ctl=wl.SolverCtl(1e-6, precond=wl.PC_DIC)),
-           dict(precision=wl.MIXED, inner_rel_tol=1.0), dict(u_ctl=wl.SolverCtl(1e-6, precond=wl.PC_DIC))]
+           dict(precision=wl.MIXED, inner_rel_tol=1.0), dict(u_ctl=wl.SolverCtl(1e-6, precond=wl.PC_DIC)),
+           dict(u_solver=7), dict(u_solver=wl.SOLVER_BICGSTAB, precision=wl.MIXED)]
     for kw in bad:
         with pytest.raises(fvm.FvmError):
             fvm.workspace_bytes(m, _opts(c, **kw))
+
+
+def test_bicgstab_option_accepted_and_sized():
+    """BiCGStab keeps two more Krylov vectors per component (p^, s^)."""
+    c = wl.cavity((8, 8, 8), Re=10.0, dt=0.01)
+    m = _mesh(c)
+    base = fvm.workspace_bytes(m, fvm.opts_from_case(c))
+    stab = fvm.workspace_bytes(m, _opts(c, u_solver=wl.SOLVER_BICGSTAB))
+    assert stab - base == 6 * 8 * m.n_cells
 
 
 def test_workspace_planner():

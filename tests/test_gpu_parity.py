@@ -128,6 +128,16 @@ def test_piso_jittered_duct_nonorth_correctors():
     _parity(case, 3, what="PISO jittered, 1 non-orth corrector")
 
 
+def test_bicgstab_momentum_parity():
+    """The BiCGStab momentum solver (the paper's GPU choice) against the
+    oracle's: PISO on a renumbered 3-D cavity, SIMPLE on the jittered duct."""
+    case = wl.cavity((9, 7, 5), Re=300.0, dt=0.01, perm_seed=3, tol=1e-9).with_(u_solver=wl.SOLVER_BICGSTAB)
+    _parity(case, 4, what="BiCGStab cavity")
+    duct = wl.duct256((32, 8, 8)).with_(p_ctl=wl.SolverCtl(1e-12, 0.0), u_ctl=wl.SolverCtl(1e-12, 0.0),
+                                        u_solver=wl.SOLVER_BICGSTAB)
+    _parity(duct, 8, simple=True, res_tol=0.0, what="BiCGStab SIMPLE duct")
+
+
 def test_solve_pressure_parity():
     import torch
     from paper_1207_1571_amd import fvm

@@ -327,6 +327,68 @@ def test_T12_bicg_equals_cg_on_symmetric_jacobi():
         assert np.abs(x1 - x2).max() <= 1e-12 * np.abs(x1).max()
 
 
+# --------------------------------------------------------------------- T17
+
+@pytest.mark.parametrize("ci", range(5))
+def test_T17_bicgstab_vs_dense_solve(ci):
+    """PBiCGStab (Barrett Sec. 2.3.8, Jacobi) on the non-symmetric momentum
+    matrix against a dense solve."""
+    case = _tiny_cases()[ci]
+    rng = np.random.default_rng(40 + ci)
+    oc = _warm_state(case, rng)
+    m = case.mesh
+    Fi = m.n_internal
+    own, nei = m.owner[:Fi].copy(), m.neighbour.copy()
+    diag, up, lo, src = orc.momentum_system(m, case.bcs, case.nu, case.dt, 0, oc.phi, oc.U, oc.U)
+    N = m.n_cells
+    A = np.zeros((N, N)); A[np.arange(N), np.arange(N)] = diag
+    A[own, nei] = up; A[nei, own] = lo
+    b = src[:, 0] + rng.normal(size=N)
+    x, info = orc.pbicgstab(own, nei, diag, up, lo, b, np.zeros(N), 1e-15, max_iter=500)
+    assert info["status"] == 0, info
+    xd = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xd) <= 1e-11 * np.linalg.norm(xd)
+
+
+def test_T17_bicgstab_terminates_with_two_eigenvalues():
+    """With Jacobi, M^-1 A = B for A = D B (B unit-diagonal); B made of
+    identical 2x2 non-symmetric blocks has two distinct eigenvalues, so the
+    BiCG polynomial underlying BiCGStab terminates in at most two steps; a
+    diagonal system is solved in the first half step."""
+    nb = 20
+    N = 2 * nb
+    rng = np.random.default_rng(5)
+    D = rng.uniform(1.0, 3.0, N)
+    own = np.arange(0, N, 2, dtype=np.int32)
+    nei = own + 1
+    a, c = 0.4, -0.7          # block [[1, a], [c, 1]]: eigenvalues 1 +- sqrt(a c) (complex pair)
+    up = D[own] * a
+    lo = D[nei] * c
+    A = np.diag(D); A[own, nei] = up; A[nei, own] = lo
+    b = rng.normal(size=N)
+    x, info = orc.pbicgstab(own, nei, D, up, lo, b, np.zeros(N), 1e-13, max_iter=50)
+    assert info["status"] == 0 and info["iters"] <= 2, info
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-12 * np.linalg.norm(x)
+    e = np.zeros(0, np.int32)
+    x, info = orc.pbicgstab(e, e, D, np.zeros(0), np.zeros(0), b, np.zeros(N), 1e-14, max_iter=50)
+    assert info["status"] == 0 and info["iters"] == 1, info
+    assert np.abs(x - b / D).max() <= 1e-15 * np.abs(b / D).max()
+
+
+@pytest.mark.parametrize("ci", range(5))
+def test_T17_piso_step_with_bicgstab_vs_dense_restatement(ci):
+    case = _tiny_cases()[ci].with_(u_solver=wl.SOLVER_BICGSTAB)
+    rng = np.random.default_rng(10 + ci)
+    oc = _warm_state(case, rng)
+    U0, p0, phi0 = oc.U.copy(), oc.p.copy(), oc.phi.copy()
+    st, info = oc.piso(1)
+    assert st == 0, info
+    Ud, pd, phid = dense_ref.piso_step(case.mesh, case.bcs, case.nu, case.dt, case.n_corr, case.p_ref_cell,
+                                       case.p_ref_value, U0, p0, phi0)
+    assert np.linalg.norm(oc.U - Ud) <= 1e-10 * np.linalg.norm(Ud)
+    assert np.linalg.norm(oc.p - pd) <= 1e-10 * max(np.linalg.norm(pd), 1e-30)
+
+
 # --------------------------------------------------------------------- T13
 
 def test_T13_dic_exact_on_tridiagonal_and_jacobi_on_diagonal():
