@@ -183,6 +183,37 @@ def cav200_section(fvm, wl, steps, log, profile_steps=2):
     return res
 
 
+def tp_section(fvm, wl, steps, log):
+    """tp1M: the transient 2-D pipe, 3200 x 300 cells (960 000), sinusoidal
+    inlet set before every step, `steps` PISO steps from rest (the paper
+    runs 5000), FP64, PCG-Jacobi / PBiCG-Jacobi tol 1e-6."""
+    import numpy as np
+    import torch
+    t = time.perf_counter()
+    spec = wl.tp1m(n_steps=steps)
+    mesh = fvm.Mesh(spec.mesh, spec.bcs)
+    N, Fi = mesh.n_cells, mesh.n_internal
+    log(f"tp1M mesh: {N} cells, {mesh.n_faces} faces in {time.perf_counter() - t:.1f}s")
+    c = fvm.Case(spec, mesh=mesh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p_iters = 0
+    for k in range(steps):
+        c.set_patch_value(0, wl.tp1m_inlet(k), 0.0)
+        st, info = c.piso(1)
+        p_iters += sum(s["iters"] for s in info["p"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    U, p, phi = c.get_state_numpy()
+    del c
+    res = dict(workload=f"tp1M: 2-D pipe 3200x300 ({N} cells, {mesh.n_faces} faces), nu 3.3e-6, inlet 0.01 sin(pi t), "
+                        f"dt 0.1 ms, {steps} PISO steps from rest, FP64, Jacobi PCG/PBiCG tol 1e-6",
+               ms_per_step=round(1e3 * wall / steps, 2), cell_updates_per_s=round(N * steps / wall, 1),
+               p_iters_per_step=round(p_iters / steps, 1), finite=bool(np.isfinite(U).all() and np.isfinite(p).all()))
+    log(f"tp1M: {res['ms_per_step']} ms/step, {res['p_iters_per_step']} pressure CG iterations per step")
+    return res
+
+
 def serve_section(fvm, wl, n_requests, n_steps, log):
     """Serving stream (cavity/duct cases, cube side log-uniform 16..96,
     Re U(10, 1000), Poisson arrivals at 40 req/s), reduced to `n_requests`
@@ -224,6 +255,7 @@ def main():
     ap.add_argument("--cav200-steps", type=int, default=20, help="steps of the 200^3 FP64-vs-mixed section (0: skip)")
     ap.add_argument("--cav200-profile-steps", type=int, default=2,
                     help="steps of the per-kernel-class timing pass of the 200^3 section (0: skip)")
+    ap.add_argument("--tp-steps", type=int, default=10, help="PISO steps of the tp1M transient pipe section (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving section (0: skip)")
     ap.add_argument("--serve-steps", type=int, default=20, help="PISO steps per serving request")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -291,6 +323,7 @@ def main():
     cav200 = (cav200_section(fvm, wl, args.cav200_steps, log, args.cav200_profile_steps)
               if args.cav200_steps > 0 else None)
     serving = serve_section(fvm, wl, args.serve_requests, args.serve_steps, log) if args.serve_requests > 0 else None
+    tp = tp_section(fvm, wl, args.tp_steps, log) if args.tp_steps > 0 else None
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
     roofline = None
     if dom:
@@ -336,6 +369,7 @@ def main():
         "pcg_spmv_GBps": spmv["alg_GBps"] if spmv else None,
         "cav200": cav200,
         "serving": serving,
+        "tp1m": tp,
         "p_iters_last_step": p_iters_last,
         "roofline": roofline,
         "assembly_vs_spmv": vs_spmv(kernels, "pcg_spmv") if kernels else None,

@@ -169,6 +169,34 @@ def cav200(n: int = 200, n_steps: int = 20, precision: int = FP64) -> CaseSpec:
                   name=f"cav{n}")
 
 
+def tp1m(nx: int = 3200, ny: int = 300, n_steps: int = 5000, tol: float = 1e-6) -> CaseSpec:
+    """Transient 2-D pipe (plane channel) 0.16 m x 0.02 m, nx x ny x 1 cells
+    (depth one cell height), nu = 3.3e-6, inlet u_in(t) = 0.01 sin(2 pi 0.5 t)
+    set before every step (tp1m_inlet), p = 0 at the outlet, no-slip walls,
+    PISO dt = 0.1 ms, 2 correctors, PCG-Jacobi / PBiCG-Jacobi at tol."""
+    L, H = 0.16, 0.02
+    mesh = mg.box_mesh(nx, ny, 1, lengths=(L, H, H / ny))
+    bcs = []
+    for side in mesh.patch_names:
+        if side == "xmin":
+            bcs.append(PatchBC(FIXED, ZERO_GRAD, (0.0, 0.0, 0.0)))
+        elif side == "xmax":
+            bcs.append(PatchBC(ZERO_GRAD, FIXED, (0.0, 0.0, 0.0), 0.0))
+        elif side in ("zmin", "zmax"):
+            bcs.append(PatchBC(EMPTY, EMPTY))
+        else:
+            bcs.append(PatchBC(FIXED, ZERO_GRAD))
+    return CaseSpec(name=f"tp{nx}x{ny}", mesh=mesh, bcs=bcs, nu=3.3e-6, dt=1e-4, mode="piso", n_steps=n_steps,
+                    p_ctl=SolverCtl(tol), u_ctl=SolverCtl(tol))
+
+
+def tp1m_inlet(step: int, dt: float = 1e-4, u0: float = 0.01, freq: float = 0.5) -> Tuple[float, float, float]:
+    """Inlet velocity for PISO step `step` (0-based): the value at the new
+    time level t = (step + 1) dt of the implicit step."""
+    t = (step + 1) * dt
+    return (u0 * math.sin(2.0 * math.pi * freq * t), 0.0, 0.0)
+
+
 @dataclass
 class ServeRequest:
     rid: int

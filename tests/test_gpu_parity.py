@@ -219,6 +219,28 @@ def test_time_dependent_patch_value():
     assert _rel(Ug, oc.U) <= TOL_FP64 and _rel(pg, oc.p) <= TOL_FP64
 
 
+def test_transient_pipe_sinusoidal_inlet_parity():
+    """The transient pipe (tp1M's geometry, viscosity and time step at a
+    reduced 160 x 15 resolution): the inlet velocity follows the sinusoid,
+    set through fvm_case_set_patch_value before every step."""
+    from paper_1207_1571_amd import fvm
+    case = wl.tp1m(nx=160, ny=15, tol=1e-10)
+    c = fvm.Case(case)
+    oc = orc.OracleCase(case)
+    for k in range(6):
+        u = wl.tp1m_inlet(2500 + 400 * k)      # sweeps through the sinusoid
+        c.set_patch_value(0, u, 0.0)
+        case.bcs[0].u_value = u
+        oc = orc.OracleCase(case, U=oc.U, p=oc.p, phi=oc.phi)
+        st, info = c.piso(1)
+        st_o, info_o = oc.piso(1)
+        assert st == st_o == 0
+        assert _counts(info) == _counts(info_o), (_counts(info), _counts(info_o))
+    Ug, pg, phig = c.get_state_numpy()
+    _say(f"  transient pipe: relL2 U {_rel(Ug, oc.U):.2e} p {_rel(pg, oc.p):.2e} phi {_rel(phig, oc.phi):.2e}")
+    assert _rel(Ug, oc.U) <= TOL_FP64 and _rel(pg, oc.p) <= TOL_FP64 and _rel(phig, oc.phi) <= TOL_FP64
+
+
 @pytest.mark.parametrize("shape,perm,rcm", [((11, 9, 7), 2, True), ((20, 20, 1), 1, False), ((8, 8, 8), None, False)])
 def test_dic_pcg_piso_parity(shape, perm, rcm):
     case = wl.cavity(shape, Re=400.0, dt=0.005, perm_seed=perm, use_rcm=rcm, tol=1e-9, p_precond=wl.PC_DIC)
