@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -267,8 +268,8 @@ struct Poller {
     fvm_status init()
     {
         if (ok) return FVM_OK;
-        if (hipHostMalloc((void **)&h, sizeof(KState) * kMaxBatch * kNumKs * kRing, hipHostMallocDefault) != hipSuccess)
-            return fvm_fail(FVM_EDEVICE, "poller: pinned host buffer");
+        const hipError_t e = hipHostMalloc((void **)&h, sizeof(KState) * kMaxBatch * kNumKs * kRing, hipHostMallocDefault);
+        if (e != hipSuccess) return fvm_fail(FVM_EDEVICE, std::string("poller: pinned host buffer: ") + hipGetErrorString(e));
         for (int k = 0; k < kRing; ++k)
             if (hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess)
                 return fvm_fail(FVM_EDEVICE, "poller: event");
@@ -303,11 +304,44 @@ struct fvm_case {
 namespace {
 
 // a group of resident cases advanced by shared launches
+// Captured chunks of Krylov iterations.  The descriptor table of a group is
+// a kernel argument that stays fixed while the group exists, so a chunk of
+// kGraphIters iterations of one solve kind is captured once per group and
+// then launched as one graph (one submission instead of 3-5 per iteration);
+// iterations past the last whole chunk are launched directly.  Every
+// captured node is a kernel launch.
+constexpr int kGraphIters = 8;
+constexpr int kGraphKinds = 8;
+struct GraphCache {
+    hipGraphExec_t ex[kGraphKinds] = {};
+    bool failed[kGraphKinds] = {};
+    GraphCache() = default;
+    GraphCache(const GraphCache &) = delete;
+    GraphCache &operator=(const GraphCache &) = delete;
+    ~GraphCache()
+    {
+        for (auto &e : ex)
+            if (e) (void)hipGraphExecDestroy(e);
+    }
+};
+
+// a non-blocking stream of the current device to capture on (capture is
+// not possible on the legacy default stream a caller may pass)
+hipStream_t capture_stream()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    static thread_local hipStream_t cs[64] = {};
+    if (!cs[dev] && hipStreamCreateWithFlags(&cs[dev], hipStreamNonBlocking) != hipSuccess) cs[dev] = nullptr;
+    return cs[dev];
+}
+
 struct Group {
     std::vector<fvm_case *> cs;
     BatchSet bs;
     Poller *poll;
     hipStream_t s;
+    std::shared_ptr<GraphCache> graphs = std::make_shared<GraphCache>();
     explicit Group(fvm_case *c, hipStream_t st) : poll(&c->poll), s(st)
     {
         cs.push_back(c);
@@ -518,10 +552,16 @@ inline const KState &st_of(Group &g, int slot, int i, int k) { return g.poll->sl
 
 // Enqueue iterations in chunks until the systems [first, first+count) of
 // every case are finished (done == 1; 2 means paused for a device-side
-// check); res[i*kNumKs + k] receives the final states.  launch_iter
-// enqueues one iteration; `predicted` sizes the first chunk.
+// check); res[i*kNumKs + k] receives the final states.  launch_iter(stream,
+// k) enqueues iteration k (counted from 0) on the stream; `predicted` sizes
+// the first chunk.  gkey (0 <= gkey < kGraphKinds) names the solve kind for
+// captured chunks (-1: never capture); the enqueued work does not depend on
+// whether a chunk was captured.  No capture while per-launch profiling
+// events are being recorded.
+bool prof_active() { return g_prof_on; }
+
 template <class F>
-fvm_status iterate_until_done(Group &g, int first, int count, int predicted, long limit, F launch_iter,
+fvm_status iterate_until_done(Group &g, int first, int count, int predicted, long limit, int gkey, F launch_iter,
                               std::vector<KState> &res)
 {
     int chunk = predicted > 0 ? std::max(2, predicted - predicted / 4) : 4;
@@ -536,10 +576,46 @@ fvm_status iterate_until_done(Group &g, int first, int count, int predicted, lon
     auto take = [&](int slot) {
         res.assign(g.poll->slot_ptr(slot), g.poll->slot_ptr(slot) + (size_t)g.n() * kNumKs);
     };
+    GraphCache &gc = *g.graphs;
+    const bool graphs_ok = gkey >= 0 && gkey < kGraphKinds && !prof_active();
+    // the captured chunk (built on first use; a failure turns capture off
+    // for this kind and the iterations are launched directly)
+    auto graph = [&]() -> hipGraphExec_t {
+        if (!graphs_ok || gc.failed[gkey]) return nullptr;
+        if (gc.ex[gkey]) return gc.ex[gkey];
+        hipStream_t cs = capture_stream();
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        bool ok = cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            for (int k = 0; k < kGraphIters; ++k) launch_iter(cs, k);
+            ok = hipStreamEndCapture(cs, &gr) == hipSuccess && gr;
+        }
+        if (ok) ok = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) == hipSuccess;
+        if (gr) (void)hipGraphDestroy(gr);
+        (void)hipGetLastError();
+        if (!ok) {
+            gc.failed[gkey] = true;
+            return nullptr;
+        }
+        gc.ex[gkey] = ex;
+        return ex;
+    };
     for (;;) {
-        const int n = (int)std::min<long>(chunk, std::max<long>(1, limit - issued));
-        for (int k = 0; k < n; ++k) launch_iter();
-        issued += n;
+        const long n = std::min<long>(chunk, std::max<long>(1, limit - issued));
+        long done_n = 0;
+        while (done_n < n) {
+            hipGraphExec_t ex = (issued % kGraphIters == 0 && n - done_n >= kGraphIters) ? graph() : nullptr;
+            if (ex) {
+                HIPCHK(hipGraphLaunch(ex, g.s));
+                issued += kGraphIters;
+                done_n += kGraphIters;
+            } else {
+                launch_iter(g.s, issued);
+                ++issued;
+                ++done_n;
+            }
+        }
         HIPCHK(hipGetLastError());
         int slot;
         fvm_status st = enqueue_states(g, slot);
@@ -614,10 +690,11 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
     if (!mixed) {
         if (dic) launch_dic_precond(bs, 1, s);
         const bool stab = kind == 0 && c0->o.u_solver == FVM_SOLVER_BICGSTAB;
-        st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 1, [&] {
-            if (stab) launch_bicgstab_iter(bs, s);
-            else if (kind == 0) launch_bicg_iter(bs, s);
-            else launch_pcg_iter(bs, dic, s);
+        const int gkey = stab ? 2 : kind == 0 ? 0 : (dic ? 3 : 1);
+        st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 1, gkey, [&](hipStream_t st_, long) {
+            if (stab) launch_bicgstab_iter(bs, st_);
+            else if (kind == 0) launch_bicg_iter(bs, st_);
+            else launch_pcg_iter(bs, dic, st_);
         }, res);
         if (st != FVM_OK) return st;
     } else if (kind == 1) {
@@ -628,12 +705,13 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
         // one).  Iterations enqueued while paused are no-ops, so the launch
         // limit is a multiple of max_iter; the device enforces max_iter.
         constexpr int kReplaceEvery = 4;
+        static_assert(kGraphIters % kReplaceEvery == 0, "captured chunks must repeat the replacement pattern");
         launch_rr_start(bs, s);
-        long k = 0;
-        st = iterate_until_done(g, first, count, predicted_iters(g, kind), (max_iter + 2) * kReplaceEvery, [&] {
-            launch_rr_iter(bs, s);
-            if (++k % kReplaceEvery == 0) launch_rr_replace(bs, s);
-        }, res);
+        st = iterate_until_done(g, first, count, predicted_iters(g, kind), (max_iter + 2) * kReplaceEvery, 4,
+                                [&](hipStream_t st_, long k) {
+                                    launch_rr_iter(bs, st_);
+                                    if ((k + 1) % kReplaceEvery == 0) launch_rr_replace(bs, st_);
+                                }, res);
         if (st != FVM_OK) return st;
     } else {
         // momentum: FP64 refinement around restarted FP32 BiCG solves
@@ -650,8 +728,8 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
             if (all) break;
             if (outer >= 1000) return fvm_fail(FVM_EDEVICE, "solve: refinement did not terminate");
             launch_mx_inner_init(bs, 0, s);
-            st = iterate_until_done(g, 4, 3, predicted_iters(g, 2), inner_max + 1,
-                                    [&] { launch_mx_inner_iter(bs, 0, s); }, res);
+            st = iterate_until_done(g, 4, 3, predicted_iters(g, 2), inner_max + 1, 5,
+                                    [&](hipStream_t st_, long) { launch_mx_inner_iter(bs, 0, st_); }, res);
             if (st != FVM_OK) return st;
             record_iters(g, res, 4, 3, 2);
             launch_mx_correct_resid(bs, 0, s);

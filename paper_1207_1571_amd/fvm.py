@@ -86,6 +86,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1207_1571_amd.build`")
+        # torch first: libfvm then binds to the HIP runtime torch has loaded,
+        # so both share one runtime (and one device context) in the process
+        import torch  # noqa: F401
         L = ct.CDLL(LIB_PATH)
         vp = ct.c_void_p
         L.fvm_mesh_create.argtypes = [ct.POINTER(FvmMeshDesc), ct.POINTER(vp)]

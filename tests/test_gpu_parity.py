@@ -138,6 +138,38 @@ def test_bicgstab_momentum_parity():
     _parity(duct, 8, simple=True, res_tol=0.0, what="BiCGStab SIMPLE duct")
 
 
+@pytest.mark.parametrize("variant", ["jacobi", "dic", "mixed", "bicgstab"])
+def test_captured_iteration_chunks_equal_direct_launches(variant):
+    """Krylov iterations launched through captured graphs (the default) and
+    launched one by one (per-launch profiling turns capture off) give the
+    same fields bit for bit, over several steps and many graph replays."""
+    from paper_1207_1571_amd import fvm
+    kw = dict(Re=300.0, dt=0.01, perm_seed=4, tol=1e-9)
+    if variant == "dic":
+        kw["p_precond"] = wl.PC_DIC
+    if variant == "mixed":
+        kw["precision"] = wl.MIXED
+    case = wl.cavity((14, 12, 10), **kw)
+    if variant == "bicgstab":
+        case = case.with_(u_solver=wl.SOLVER_BICGSTAB)
+    out = []
+    for profile in (False, True):
+        fvm.profile_enable(profile)
+        try:
+            _say(f"  {variant}: per-launch profiling {profile}")
+            c = fvm.Case(case)
+            st, info = c.piso(4)
+            out.append((c.get_state_numpy(), _counts(info)))
+            c.close()
+        finally:
+            fvm.profile_enable(False)
+    (a, ca), (b, cb) = out
+    _say(f"  {variant}: iterations {ca}")
+    assert ca == cb
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
 def test_solve_pressure_parity():
     import torch
     from paper_1207_1571_amd import fvm

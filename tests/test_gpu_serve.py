@@ -96,3 +96,25 @@ def test_budget_admission_on_device():
     spans = sorted((r.admitted_s, r.done_s) for r in res)
     for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
         assert a1 >= d0   # never two resident at once
+
+
+def test_batched_dic_cases_equal_their_solo_runs():
+    """Several PCG-DIC cases (FP64) advanced in shared launches: each case
+    elects its own XCD for its sweeps, and its fields equal its solo run bit
+    for bit."""
+    from paper_1207_1571_amd import fvm
+    specs = [wl.cavity(sh, Re=300.0, dt=0.01, perm_seed=seed, use_rcm=True, tol=1e-8, p_precond=wl.PC_DIC)
+             for sh, seed in (((9, 8, 7), 1), ((12, 6, 5), 2), ((7, 7, 7), 3))]
+    alone = []
+    for spec in specs:
+        c = fvm.Case(spec)
+        c.piso(3)
+        alone.append(c.get_state_numpy())
+        c.close()
+    cases = [fvm.Case(spec) for spec in specs]
+    st, infos = fvm.piso_batch(cases, 3)
+    assert st == 0
+    for c, a in zip(cases, alone):
+        for x, y in zip(c.get_state_numpy(), a):
+            assert np.array_equal(x, y)
+        c.close()
