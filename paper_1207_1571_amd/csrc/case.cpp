@@ -160,6 +160,14 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
     d.u_tol = o.u_ctl.tol; d.u_rel_tol = o.u_ctl.rel_tol; d.u_max_iter = o.u_ctl.max_iter;
     d.p_tol = o.p_ctl.tol; d.p_rel_tol = o.p_ctl.rel_tol; d.p_max_iter = o.p_ctl.max_iter;
     d.n_levels = (int32_t)m.lvl_start.size() - 1;
+    {
+        // a wave of the DIC sweeps starts polling once the position this far
+        // before its first one is done: two of the widest levels, at least
+        // 8192 positions (128 waves), in whole waves
+        int32_t wmax = 0;
+        for (int32_t l = 0; l < d.n_levels; ++l) wmax = std::max(wmax, m.lvl_start[l + 1] - m.lvl_start[l]);
+        d.dic_lag = ((std::max<int32_t>(8192, 2 * wmax) + 63) / 64) * 64;
+    }
     d.self = b.take<DevCase>(1);
     d.own = b.take<int32_t>(F); d.nei = b.take<int32_t>(Fi);
     d.own_start = b.take<int32_t>(N + 1); d.nbr_start = b.take<int32_t>(N + 1); d.losort = b.take<int32_t>(Fi);
@@ -193,11 +201,10 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
     if (dic) {
         d.z = b.take<double>(N); d.dstar = b.take<double>(N);
         d.dq = b.take<double>(N); d.yq = b.take<double>(N); d.zq = b.take<double>(N);
-        d.lvl_start = b.take<int32_t>(m.lvl_start.size()); d.lvl_cells = b.take<int32_t>(N);
+        d.lvl_cells = b.take<int32_t>(N);
         d.dW_lo = m.dW_lo; d.dW_hi = m.dW_hi;
         d.dl_pos = b.take<int32_t>((size_t)m.dW_lo * N); d.dl_face = b.take<int32_t>((size_t)m.dW_lo * N);
         d.du_pos = b.take<int32_t>((size_t)m.dW_hi * N); d.du_face = b.take<int32_t>((size_t)m.dW_hi * N);
-        d.lev_pos = b.take<int32_t>(N);
         d.dl_val = b.take<double>((size_t)m.dW_lo * N); d.du_val = b.take<double>((size_t)m.dW_hi * N);
     }
     if (mixed) {
@@ -437,11 +444,10 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     UPCHK(up(d.V, m->V, s));
     UPCHK(up(d.tmpC, m->C, s));
     UPCHK(up(d.tmpCf, m->Cf, s));
-    if (d.lvl_start) {
-        UPCHK(up(d.lvl_start, m->lvl_start, s)); UPCHK(up(d.lvl_cells, m->lvl_cells, s));
+    if (d.lvl_cells) {
+        UPCHK(up(d.lvl_cells, m->lvl_cells, s));
         UPCHK(up(d.dl_pos, m->dl_pos, s)); UPCHK(up(d.dl_face, m->dl_face, s));
         UPCHK(up(d.du_pos, m->du_pos, s)); UPCHK(up(d.du_face, m->du_face, s));
-        UPCHK(up(d.lev_pos, m->lev_pos, s));
     }
     UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s));
     UPCHK(up(d.sell_fe, m->sell_fe, s)); UPCHK(up(d.sell_col, m->sell_col, s));

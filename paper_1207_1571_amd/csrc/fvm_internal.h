@@ -43,9 +43,9 @@ struct fvm_mesh {
     // DIC dependencies in level order: for position q (cell lvl_cells[q]),
     // lower dependency k (ascending neighbour index) at dl_*[k * N + q],
     // upper ones at du_*[k * N + q]; *_pos = position of the neighbour,
-    // *_face = its face, -1 past the cell's count; lev_pos[q] = level of q
+    // *_face = its face, -1 past the cell's count
     int32_t dW_lo = 0, dW_hi = 0;
-    std::vector<int32_t> dl_pos, dl_face, du_pos, du_face, lev_pos;
+    std::vector<int32_t> dl_pos, dl_face, du_pos, du_face;
     // row-sliced copy of the off-diagonal structure (sliced ELL): slice s =
     // cells [256 s, 256 s + 256), sell_W slots per cell, entry (s, k, lane) at
     // (s * sell_W + k) * 256 + lane; a cell's entries in ascending column.
@@ -128,13 +128,14 @@ struct DevCase {
     int32_t u_stab;                              // momentum solver is BiCGStab
     double *z;                                   // [N] DIC preconditioned residual (cell order)
     double *dstar;                               // [N] DIC diagonal (cell order, for diagnostics)
-    int32_t *lvl_start, *lvl_cells;              // DIC level schedule
+    int32_t *lvl_cells;                          // DIC level schedule: cells in level order
     int32_t n_levels;
+    int32_t dic_lag;                             // DIC sweep gate distance (positions)
     // DIC dependencies in level order (see fvm_mesh), their coefficients
     // (refilled at the start of every solve) and the values published by the
     // sweeps, indexed by level position: D*, y (forward), z (backward)
     int32_t dW_lo, dW_hi;
-    int32_t *dl_pos, *dl_face, *du_pos, *du_face, *lev_pos;
+    int32_t *dl_pos, *dl_face, *du_pos, *du_face;
     double *dl_val, *du_val;
     double *dq, *yq, *zq;
     // sliced-ELL copy of the pressure matrix (structure as in fvm_mesh)

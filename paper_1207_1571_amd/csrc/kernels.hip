@@ -1453,12 +1453,14 @@ __device__ __forceinline__ unsigned int xcc_id() { return __builtin_amdgcn_s_get
 
 // Blocks claim tiles of 256 consecutive entries of the level order (reversed
 // for MODE 2); each wave of the block takes 64 of them.  Before its lanes
-// poll, a wave waits on a single word: the last cell (in processing order)
-// of the level before the level of its latest outside dependency.  The wave
-// thus starts polling about one level before its inputs complete: waves far
-// ahead of the front poll one address instead of up to 64 x D, which
-// keeps the XCD's L2 free for the hand-over traffic at the front, while the
-// front itself is not delayed by the gate.
+// poll, a wave waits on a single word: the value at the position dic_lag
+// places before its first one (dic_lag is at least twice the widest level,
+// and at least 8192).  Only the waves within that distance of the
+// completion front poll their dependencies; the ones further ahead poll one
+// address, which keeps the XCD's L2 free for the hand-over traffic at the
+// front.  Positions complete in roughly increasing order and the gate lies
+// before the wave's own positions, so the earliest unfinished position is
+// never gated: the sweep always progresses.
 constexpr int kChunk = 64;
 
 // DIC coefficients in level order, refilled at the start of every solve
@@ -1518,6 +1520,10 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     } else if (live) {
         while (nd < W && DP[nd * N + fq] >= 0) ++nd;
     }
+    // a wave whose lanes all depend only on positions inside the chunk (or on
+    // nothing) has no reason to wait; the test is a max over the wave's lanes
+    // (this form schedules better than a ballot).  Waves of the streaming
+    // path are not gated.
     int gate = -1;   // processing position of the latest dependency before this chunk
 #pragma unroll
     for (int t = 0; t < D; ++t) {
@@ -1528,18 +1534,12 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) gate = max(gate, __shfl_xor(gate, o, 64));
-    if (gate >= 0) {
-        // the gate: last position, in processing order, of the level one
-        // step before that of the latest outside dependency
-        const int gl = d.lev_pos[MODE == 2 ? n - 1 - gate : gate];
-        int gp = -1;
-        if (MODE == 2) { if (gl + 1 < d.n_levels) gp = d.lvl_start[gl + 1]; }
-        else if (gl >= 1) gp = d.lvl_start[gl] - 1;
-        if (gp >= 0) {
-            // every lane loads the same word: one request per wave
-            double v;
-            for (int sp = 0; sp < kSpinLimit && !dic_try(src, gp, v); ++sp) __builtin_amdgcn_s_sleep(1);
-        }
+    const int gq = chunk * kChunk - d.dic_lag;   // the gate, in processing order
+    if (gate >= 0 && gq >= 0) {
+        // every lane loads the same word: one request per wave
+        const int gp = MODE == 2 ? n - 1 - gq : gq;
+        double v;
+        for (int sp = 0; sp < kSpinLimit && !dic_try(src, gp, v); ++sp) __builtin_amdgcn_s_sleep(1);
     }
     double acc = 0.0;
     if (live && MODE != 2) acc = MODE == 0 ? d.pdiag[i] : d.r[i];

@@ -233,10 +233,8 @@ fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
         m->dW_hi = std::max(wh, 1);
         m->dl_pos.assign((size_t)m->dW_lo * N, -1); m->dl_face.assign((size_t)m->dW_lo * N, -1);
         m->du_pos.assign((size_t)m->dW_hi * N, -1); m->du_face.assign((size_t)m->dW_hi * N, -1);
-        m->lev_pos.resize(N);
         for (int32_t q = 0; q < N; ++q) {
             const int32_t i = m->lvl_cells[q];
-            m->lev_pos[q] = lev[i];
             int32_t k = 0;
             for (int32_t t = m->nbr_start[i]; t < m->nbr_start[i + 1]; ++t, ++k) {
                 const int32_t f = m->losort[t];

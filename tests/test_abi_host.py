@@ -165,8 +165,9 @@ def test_workspace_planner():
         assert 300 < per_cell < 1500, per_cell
         # FP32 copies: between 1 and 4 floats per cell-face slot added
         assert 40 < (mixed - fp64) / m.n_cells < 400
-        # DIC: z and D* in cell order, D*, y, z in level order (FP64), the level
-        # schedule and the dependencies in level order (positions, faces, values)
+        # DIC: z and D* in cell order, D*, y, z in level order (FP64), the cells
+        # in level order and the dependencies in level order (positions, faces,
+        # values)
         assert 100 <= (dic - fp64) / m.n_cells < 200
     # grows with the mesh; the marginal cost per added cell is in the same band
     (n1, a1, _, _), (n2, a2, _, _), (n3, a3, _, _) = sizes[8], sizes[16], sizes[24]
@@ -174,22 +175,17 @@ def test_workspace_planner():
     assert 300 < (a3 - a2) / (n3 - n2) < 1500
 
 
-def test_level_schedule_is_a_valid_dic_order():
-    """fvm_mesh_create computes level sets for the DIC sweeps; a cell's
-    level is larger than the levels of all its lower-numbered neighbours.
-    Checked indirectly: the planner reserves one level-start entry per level
-    plus one, which for an n^3 box in lexicographic order is 3(n-1)+1 levels,
-    besides per-cell arrays: z and D* in cell order, D*, y, z in level order
-    (FP64), the cells in level order and the level of each position (int32),
-    and for each of the 3 lower and 3 upper dependency slots a position and a
-    face (int32) and a coefficient (FP64)."""
-    n = 6
-    c = wl.cavity((n, n, n), Re=10.0, dt=0.01, p_precond=wl.PC_DIC)
-    m = _mesh(c)
-    base = fvm.workspace_bytes(m, _opts(c, p_ctl=wl.SolverCtl(1e-6)))
-    dic = fvm.workspace_bytes(m, fvm.opts_from_case(c))
-    levels = 3 * (n - 1) + 1
-    N = m.n_cells
-    expect = 5 * 8 * N + 4 * (levels + 1) + 2 * 4 * N + 6 * (4 + 4 + 8) * N
-    # each of the 14 arrays is aligned on 256 bytes
-    assert expect <= dic - base <= expect + 14 * 256
+def test_dic_workspace_is_per_cell():
+    """PCG-DIC adds per-cell arrays only: z and D* in cell order, D*, y, z in
+    level order (FP64), the cells in level order (int32), and for each of the
+    3 lower and 3 upper dependency slots of a hex cell a position and a face
+    (int32) and a coefficient (FP64)."""
+    for n in (6, 9):
+        c = wl.cavity((n, n, n), Re=10.0, dt=0.01, p_precond=wl.PC_DIC)
+        m = _mesh(c)
+        base = fvm.workspace_bytes(m, _opts(c, p_ctl=wl.SolverCtl(1e-6)))
+        dic = fvm.workspace_bytes(m, fvm.opts_from_case(c))
+        N = m.n_cells
+        expect = 5 * 8 * N + 4 * N + 6 * (4 + 4 + 8) * N
+        # each of the 12 arrays is aligned on 256 bytes
+        assert expect <= dic - base <= expect + 12 * 256

@@ -314,10 +314,13 @@ def test_dic_exact_on_chain_and_solve_pressure():
     assert _rel(pg.cpu().numpy(), po) <= TOL_FP64
 
 
-@pytest.mark.parametrize("shape,perm,rcm", [((40, 1, 1), None, False), ((9, 8, 7), 3, True), ((70, 60, 1), 4, False)])
+@pytest.mark.parametrize("shape,perm,rcm", [((40, 1, 1), None, False), ((9, 8, 7), 3, True), ((70, 60, 1), 4, False),
+                                            ((130, 120, 1), 5, False), ((30, 30, 30), 6, True)])
 def test_dic_apply_matches_oracle(shape, perm, rcm):
     """D* and z = M^-1 r of the GPU sweeps against the oracle's row-ordered
-    recurrences on the same assembled matrix."""
+    recurrences on the same assembled matrix.  The two larger meshes are
+    longer than the sweeps' gate distance (8192 positions), so their later
+    waves wait on the gate before polling."""
     import torch
     from paper_1207_1571_amd import fvm
     case = wl.cavity(shape, Re=100.0, dt=0.01, perm_seed=perm, use_rcm=rcm, tol=1e-9, p_precond=wl.PC_DIC)
@@ -366,14 +369,15 @@ def _long_range_mesh(n, reach):
                    lex_of_cell=np.arange(n))
 
 
-@pytest.mark.parametrize("reach,perm", [(6, None), (11, 9)])
-def test_dic_apply_many_dependencies(reach, perm):
+@pytest.mark.parametrize("reach,perm,n", [(6, None, 300), (11, 9, 300), (6, None, 20000), (11, 9, 20000)])
+def test_dic_apply_many_dependencies(reach, perm, n):
     """Cells with more dependencies than the 4 register slots (reach 6 in
     natural order: at most 6 per side, the 8-slot variant) or than 8 (reach
-    11, permuted: the streaming path)."""
+    11, permuted: the streaming path); the 20000-cell lines also pass the
+    sweeps' gate distance."""
     import torch
     from paper_1207_1571_amd import fvm
-    m = _long_range_mesh(300, reach)
+    m = _long_range_mesh(n, reach)
     if perm is not None:
         m = mg.random_permutation(m, perm)
     bcs = [wl.PatchBC(wl.FIXED, wl.FIXED)]
