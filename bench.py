@@ -17,8 +17,11 @@ in device memory before the timed region).
 Also reported on the same JSON line:
   roofline      the kernel class with the largest device time in a profiled
                 pass (HIP events around each launch, on the stream the kernel
-                runs on): algorithmic bytes per launch / mean launch time;
-  kernels       per-class mean time, launches and algorithmic GB/s;
+                runs on): algorithmic bytes per working launch / device time
+                per working launch (Krylov launches enqueued past a solve's
+                convergence return at once and do no work);
+  kernels       per-class device time, launches (all and working), mean time
+                per launch and per working launch, algorithmic GB/s;
   cpu_baseline  the FP64 oracle on the host on a bounded sample (the first
                 PISO step of the same case), in cell-updates/s.
 """
@@ -73,29 +76,49 @@ KERNEL_CLASSES = ["pcg_spmv", "pcg_update", "pcg_dir", "dic_setup", "dic_fwd", "
                   "pcg32_dir", "bicg32_spmv"]
 
 
+# classes whose launches past a solve's convergence return at once (the
+# host enqueues iterations ahead of the device's stop flag): their working
+# launches are counted from the solvers' iteration counts.  A pressure CG
+# solve of k iterations runs k direction/SpMV/update launches and k DIC
+# applications (one at the start, one after each update but the last).
+_P_WORK = ("pcg_spmv", "pcg_update", "pcg_dir", "dic_fwd", "dic_bwd", "pcg32_spmv", "pcg32_update", "pcg32_dir")
+_U_WORK = ("bicg_spmv",)
+
+
 def profile_classes(fvm, case, steps, N, Fi, dic):
-    """Per-class device time of `steps` PISO steps (HIP events per launch)."""
+    """Per-class device time of `steps` PISO steps (HIP events per launch).
+
+    mean_us is over every launch (as a kernel trace reports it); us_per_work
+    and alg_GBps are over the launches that did work."""
     import torch
     fvm.profile_enable(True)
-    case.piso(steps)
+    p_work = u_work = 0
+    for _ in range(steps):
+        st, info = case.piso(1)
+        p_work += sum(s["iters"] for s in info["p"])
+        u_work += max(s["iters"] for s in info["u"])
     torch.cuda.synchronize()
     out = {}
     for cls in KERNEL_CLASSES:
         ms, n = fvm.profile_read(cls)
         if n == 0:
             continue
+        work = min(n, p_work if cls in _P_WORK else u_work if cls in _U_WORK else n)
         mean_us = 1e3 * ms / n
+        work_us = 1e3 * ms / max(work, 1)
         b = algorithmic_bytes(cls, N, Fi, dic)
-        out[cls] = dict(total_ms=round(ms, 4), launches=n, mean_us=round(mean_us, 3),
-                        alg_GBps=round(b / (mean_us * 1e-6) / 1e9, 1) if b and mean_us > 0 else None)
+        out[cls] = dict(total_ms=round(ms, 4), launches=n, work_launches=work, mean_us=round(mean_us, 3),
+                        us_per_work=round(work_us, 3),
+                        alg_GBps=round(b / (work_us * 1e-6) / 1e9, 1) if b and work_us > 0 else None)
     fvm.profile_enable(False)
     return out
 
 
 def measured_traffic(kernel_class: str, workload: str):
-    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summaries under profiles/ (copy-calibrated), if they were taken on the
-    current kernel source; else None."""
+    """HBM bytes per working launch (median over dispatches) from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summaries under profiles/
+    (copy-calibrated), if they were taken on the current kernel source; else
+    None."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_1207_1571_amd", "csrc", "kernels.hip")
@@ -107,16 +130,16 @@ def measured_traffic(kernel_class: str, workload: str):
             rec = json.loads(line.split(":", 1)[1])
             if (rec.get("kernel_class") == kernel_class and rec.get("workload") == workload
                     and rec.get("kernels_hip_sha256") == sha):
-                return float(rec["bytes_per_launch"])
+                return float(rec["bytes_per_working_launch"])
     return None
 
 
 def vs_spmv(k, spmv_cls):
     """Assembly operators' device time per call relative to one SpMV (the
     analogue of the paper's Table 3 normalisation)."""
-    if spmv_cls not in k or not k[spmv_cls]["mean_us"]:
+    if spmv_cls not in k or not k[spmv_cls]["us_per_work"]:
         return None
-    sp = k[spmv_cls]["mean_us"]
+    sp = k[spmv_cls]["us_per_work"]
 
     def per_call(*names):
         if not all(n in k for n in names):
@@ -166,13 +189,13 @@ def cav200_section(fvm, wl, steps, log, profile_steps=2):
             k = profile_classes(fvm, pc, profile_steps, N, Fi, False)
             del pc
         pre = "pcg32" if prec == wl.MIXED else "pcg"
-        it_us = sum(k[c]["mean_us"] for c in (pre + "_dir", pre + "_spmv", pre + "_update") if c in k)
+        it_us = sum(k[c]["us_per_work"] for c in (pre + "_dir", pre + "_spmv", pre + "_update") if c in k)
         it_bytes = (112 * N + 16 * Fi) if prec == wl.FP64 else (64 * N + 12 * Fi)
         res[name] = dict(ms_per_step=round(1e3 * wall / steps, 2), cell_updates_per_s=round(N * steps / wall, 1),
                          p_iters_total=p_iters, ms_per_p_solve=round(1e3 * wall / (2 * steps), 2),
                          spmv_GBps=k.get(pre + "_spmv", {}).get("alg_GBps"),
-                         spmv_mean_us=k.get(pre + "_spmv", {}).get("mean_us"),
-                         cg_iter_us=round(it_us, 2), cg_iter_GBps=round(it_bytes / (it_us * 1e-6) / 1e9, 1) if it_us else None,
+                         spmv_us=k.get(pre + "_spmv", {}).get("us_per_work"),
+                         cg_iter_us=round(it_us, 2) if it_us else None, cg_iter_GBps=round(it_bytes / (it_us * 1e-6) / 1e9, 1) if it_us else None,
                          assembly_vs_spmv=vs_spmv(k, pre + "_spmv"), kernels=k)
         log(f"cav200 {name}: {res[name]['ms_per_step']} ms/step, p iters {p_iters}, SpMV {res[name]['spmv_GBps']} GB/s, "
             f"CG iteration {res[name]['cg_iter_GBps']} GB/s")
@@ -331,8 +354,8 @@ def main():
         tb = measured_traffic(dom, f"cav{args.n}")
         roofline = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(ach / HBM_PEAK_GBS, 4) if ach else None,
-                        traffic=tb,
-                        traffic_GBps=round(tb / (kernels[dom]["mean_us"] * 1e-6) / 1e9, 1) if tb else None,
+                        traffic=round(tb) if tb else None,
+                        traffic_GBps=round(tb / (kernels[dom]["us_per_work"] * 1e-6) / 1e9, 1) if tb else None,
                         algorithmic_bytes=algorithmic_bytes(dom, N, Fi, spec.p_ctl.precond == wl.PC_DIC))
         if dom.startswith("dic"):
             roofline["note"] = ("dependency-latency bound: the sweep is a chain of one step per level of the "

@@ -642,7 +642,9 @@ fvm_status iterate_until_done(Group &g, int first, int count, int predicted, lon
             return FVM_OK;
         }
         prev = slot;
-        chunk = predicted > 0 ? std::max(2, predicted / 8) : std::min(64, chunk * 2);
+        // later chunks stay short: the launches enqueued past the stop flag
+        // (up to two chunks) return at once but still cost a launch each
+        chunk = predicted > 0 ? std::min(64, std::max(2, predicted / 8)) : std::min(64, chunk * 2);
     }
 }
 
