@@ -217,7 +217,7 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
     {
         const size_t ns = (N + kBlock - 1) / kBlock, W = (size_t)m.sell_W;
         d.sell_W = m.sell_W;
-        d.sell_mode = b.take<int32_t>(ns); d.sell_off = b.take<int32_t>(ns * W);
+        d.sell_mode = b.take<int32_t>(ns); d.sell_off = b.take<int32_t>(ns * W); d.sell_mir = b.take<int32_t>(ns * W);
         d.sell_fe = b.take<int32_t>(ns * W * kBlock); d.sell_col = b.take<int32_t>(ns * W * kBlock);
         if (mixed) d.f_sell_val = b.take<float>(ns * W * kBlock);
         else d.sell_val = b.take<double>(ns * W * kBlock);
@@ -449,7 +449,7 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
         UPCHK(up(d.dl_pos, m->dl_pos, s)); UPCHK(up(d.dl_face, m->dl_face, s));
         UPCHK(up(d.du_pos, m->du_pos, s)); UPCHK(up(d.du_face, m->du_face, s));
     }
-    UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s));
+    UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s)); UPCHK(up(d.sell_mir, m->sell_mir, s));
     UPCHK(up(d.sell_fe, m->sell_fe, s)); UPCHK(up(d.sell_col, m->sell_col, s));
     UPCHK(hipMemsetAsync(d.ticket, 0, 64 * sizeof(unsigned int), s));
     UPCHK(hipMemsetAsync(d.gticket, 0, d.red_stride2 * sizeof(unsigned int), s));

@@ -55,8 +55,13 @@ struct fvm_mesh {
     // values is "regular" (sell_mode 0): slot k holds offset sell_off[s, k]
     // for every cell of the slice and no column is stored; otherwise
     // (sell_mode 1) columns are explicit in sell_col (padding: the cell).
+    // sell_mir[s, k] (regular slices, lower slots k): the slot k' that holds
+    // the same coefficients in the slices of the neighbours j = i + off_k
+    // (offset -off_k there), where the symmetric value a_ji = a_ij can be
+    // read instead of the slice's own copy; -1 where that does not hold for
+    // every cell of the slice (upper slots, explicit slices, borders).
     int32_t sell_W = 0;
-    std::vector<int32_t> sell_mode, sell_off, sell_fe, sell_col;
+    std::vector<int32_t> sell_mode, sell_off, sell_fe, sell_col, sell_mir;
 };
 
 // ---------------------------------------------------------------------------
@@ -140,7 +145,7 @@ struct DevCase {
     double *dq, *yq, *zq;
     // sliced-ELL copy of the pressure matrix (structure as in fvm_mesh)
     int32_t sell_W;
-    int32_t *sell_mode, *sell_off, *sell_fe, *sell_col;
+    int32_t *sell_mode, *sell_off, *sell_fe, *sell_col, *sell_mir;
     double *sell_val;                            // FP64 values (FP64 cases)
     float *f_sell_val;                           // FP32 values (mixed cases)
     // FP32 copies (mixed precision)

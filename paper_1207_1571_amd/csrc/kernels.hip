@@ -1230,25 +1230,37 @@ __global__ void __launch_bounds__(kBlock) k_sell_fill(Batch bt)
 template <class T>
 __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v, int sl, int i)
 {
+    // per-slice tables are read as uniform scalar loads, coefficients and
+    // gathers as global-space vector loads (no flat-load waits)
+    typedef const __attribute__((address_space(4))) int cint;
+    typedef const __attribute__((address_space(1))) T gT;
+    typedef const __attribute__((address_space(1))) int gint;
     constexpr bool kDiff = sizeof(T) == 4;
     const int W = d.sell_W;
     const size_t base = (size_t)sl * W * kBlock + threadIdx.x;
-    const T *__restrict__ val = v.sval + base;
-    const T *__restrict__ p = v.p;
+    gT *__restrict__ sv = (gT *)v.sval;
+    gT *__restrict__ val = sv + base;
+    gT *__restrict__ p = (gT *)v.p;
     const double pi = (double)p[i];
-    double qa = kDiff ? 0.0 : (double)v.diag[i] * pi, so = 0.0;
+    double qa = kDiff ? 0.0 : (double)((gT *)v.diag)[i] * pi, so = 0.0;
     if (d.sell_mode[sl] == 0) {
-        const int *__restrict__ off = d.sell_off + (size_t)sl * W;
+        cint *off = (cint *)(d.sell_off + (size_t)sl * W);
+        cint *mir = (cint *)(d.sell_mir + (size_t)sl * W);
         const int last = d.N - 1;
 #pragma unroll 6
         for (int k = 0; k < W; ++k) {
-            const T a = val[(size_t)k * kBlock];
             const int j = min(max(i + off[k], 0), last);
+            // a lower slot with a mirror reads a_ji from the neighbour's
+            // upper slot (a stream read moments ago, still in cache) instead
+            // of its own copy of the same value
+            const int mk = mir[k];
+            gT *src = mk < 0 ? val + (size_t)k * kBlock : sv + ((size_t)(j / kBlock) * W + mk) * kBlock + (j % kBlock);
+            const T a = *src;
             qa += (double)a * (double)p[j];
             if (kDiff) so += (double)a;
         }
     } else {
-        const int *__restrict__ col = d.sell_col + base;
+        gint *__restrict__ col = (gint *)(d.sell_col + base);
 #pragma unroll 6
         for (int k = 0; k < W; ++k) {
             const T a = val[(size_t)k * kBlock];
@@ -1256,7 +1268,7 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
             if (kDiff) so += (double)a;
         }
     }
-    const T q = kDiff ? (T)(qa + ((double)v.exc[i] - so) * pi) : (T)qa;
+    const T q = kDiff ? (T)(qa + ((double)((gT *)v.exc)[i] - so) * pi) : (T)qa;
     v.q[i] = q;
     return pi * (double)q;
 }

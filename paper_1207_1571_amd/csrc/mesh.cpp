@@ -77,6 +77,44 @@ void build_sell(fvm_mesh *m)
             }
         }
     }
+    // mirror slots of the regular slices (the matrix is symmetric in
+    // structure and value: entry (i, j) of slot k equals entry (j, i), which a
+    // regular neighbour slice holds in the slot whose offset is -off_k)
+    m->sell_mir.assign((size_t)ns * W, -1);
+    // a slot is real if some cell of the slice has an entry there
+    std::vector<char> used((size_t)ns * W, 0);
+    for (int32_t s = 0; s < ns; ++s)
+        for (int32_t k = 0; k < W; ++k)
+            for (int32_t l = 0; l < kBlock && !used[(size_t)s * W + k]; ++l)
+                used[(size_t)s * W + k] = m->sell_fe[((size_t)s * W + k) * kBlock + l] >= 0;
+    auto slot_of = [&](int32_t s, int32_t off) {
+        if (s < 0 || s >= ns || m->sell_mode[s] != 0) return -1;
+        for (int32_t k = 0; k < W; ++k)
+            if (used[(size_t)s * W + k] && m->sell_off[(size_t)s * W + k] == off) return k;
+        return -1;
+    };
+    for (int32_t s = 0; s < ns; ++s) {
+        if (m->sell_mode[s] != 0) continue;
+        const int32_t i0 = s * kBlock, i1 = std::min(N, i0 + kBlock);
+        for (int32_t k = 0; k < W; ++k) {
+            const int32_t off = m->sell_off[(size_t)s * W + k];
+            if (off >= 0 || !used[(size_t)s * W + k] || i0 + off < 0) continue;
+            // the neighbours j = i + off of the slice's cells span at most two slices
+            const int32_t sa = (i0 + off) / kBlock, sb = (i1 - 1 + off) / kBlock;
+            const int32_t ka = slot_of(sa, -off);
+            if (ka < 0 || (sb != sa && slot_of(sb, -off) != ka)) continue;
+            // every entry of slot k must be the mirror of the neighbour's entry
+            // (padding on both sides, or the same face)
+            bool ok = true;
+            for (int32_t i = i0; i < i1 && ok; ++i) {
+                const int32_t j = i + off;
+                const int32_t fe = m->sell_fe[((size_t)s * W + k) * kBlock + (i - i0)];
+                const int32_t fm = m->sell_fe[((size_t)(j / kBlock) * W + ka) * kBlock + (j % kBlock)];
+                ok = (fe < 0 && fm < 0) || (fe >= 0 && fm >= 0 && (fe >> 1) == (fm >> 1));
+            }
+            if (ok) m->sell_mir[(size_t)s * W + k] = ka;
+        }
+    }
 }
 
 fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
