@@ -117,7 +117,8 @@ typedef struct {
     int32_t inner_max_iter;
     fvm_solver_ctl p_ctl, u_ctl;
     int32_t u_solver;      /* FVM_SOLVER_* for the momentum equation */
-    int32_t reserved;      /* must be 0 */
+    int32_t hybrid_K;      /* > 0: also lay out the paper's hybrid matrix format with this many ELL slots per
+                              row, for fvm_case_operator's FVM_OP_HY_* operators (comparison layout); 0: none */
 } fvm_case_opts;
 
 typedef struct {
@@ -196,6 +197,58 @@ fvm_status solve_pressure(fvm_case *c, const double *d_gamma_f, const double *d_
  * the case's pressure work arrays, not its fields.  Synchronises. */
 fvm_status fvm_dic_apply(fvm_case *c, const double *d_gamma_f, const double *d_r, double *d_z, double *d_dstar,
                          void *stream);
+
+/* ---- Comparison layout: the paper's hybrid matrix format (Section 3.1) ----
+ * Row i of a mesh's matrix holds the diagonal and one entry per internal
+ * face of cell i, in ascending column order.  The first K entries form the
+ * ELL part B: values V, columns I, and J, the slot at which the transposed
+ * entry sits in B, which gives column access (A^T x) without a transposed
+ * copy.  Entries beyond K form the CRS part C.  Face data lives once per
+ * face, at the entry of its owner row; the other cell reaches it through I
+ * and J.  The solver itself uses the face-major layout; this one exists to
+ * compare the two on the same operators. */
+
+/* fvm_mesh_hybrid -- the index arrays of the hybrid layout with K slots per
+ * row, in the paper's row-major form (host arrays the caller allocates; any
+ * may be NULL): I, J, Q [n_cells * K], c_start [n_cells + 1], c_col and
+ * c_tr [n_crs].  Unused slots hold I = i, J = k (value 0).  J = -1 - c when
+ * the transposed entry lies at position c of C; c_tr = K * j + k' for a
+ * transpose at slot k' of row j in B, else -1 - c'.  Q packs I and J as
+ * K * I + J where J >= 0 (-1 elsewhere).  Call with NULL arrays to learn
+ * n_crs.  Errors: FVM_EINVAL for K < 1 or K * n_cells beyond int32. */
+fvm_status fvm_mesh_hybrid(const fvm_mesh *mesh, int32_t K, int32_t *n_crs, int32_t *I, int32_t *J, int32_t *Q,
+                           int32_t *c_start, int32_t *c_col, int32_t *c_tr);
+
+enum {
+    FVM_OP_GRAD = 0, FVM_OP_DIV = 1, FVM_OP_LAP = 2, FVM_OP_SPMV = 3,
+    FVM_OP_HY_GRAD = 4, FVM_OP_HY_DIV = 5, FVM_OP_HY_LAP = 6, FVM_OP_HY_SPMV = 7, FVM_OP_HY_STMVP = 8,
+    FVM_OP_HY_SETMAT = 9
+};
+
+/* fvm_case_operator -- one assembly or matrix operator (Table 3's set), in
+ * the face-major layout of the solver (FVM_OP_GRAD .. FVM_OP_SPMV) or in the
+ * hybrid layout (FVM_OP_HY_*; the case must have been created with
+ * opts.hybrid_K > 0), enqueued on `stream`.  Device arrays, caller order:
+ *   GRAD, HY_GRAD: d_in cell scalar [n_cells]; d_out its Gauss gradient
+ *     [3][n_cells] (component-major); boundary faces take the case's p
+ *     patches (FIXED value, ZERO_GRAD owner value, EMPTY skipped).
+ *   DIV, HY_DIV: d_in face flux [n_faces] along the caller's Sf; d_out the
+ *     net outward flux of each cell over its non-EMPTY faces [n_cells].
+ *   LAP, HY_LAP: d_in gamma [n_faces]; assembles the matrix solve_pressure
+ *     builds (face coefficients gamma |S|^2 / (S.d), FIXED-p boundary terms,
+ *     the reference pin) into the layout; d_out its diagonal [n_cells]
+ *     (LAP) or the layout's values [K * n_cells + n_crs], B slot-major (row
+ *     i, slot k at k * n_cells + i) then C (HY_LAP).
+ *   SPMV: d_in x [n_cells]; d_out A x with the matrix of the last LAP.
+ *   HY_SPMV, HY_STMVP: d_in x; d_out A x or A^T x with the layout's values.
+ *   HY_SETMAT: d_in [diag n_cells | upper n_int | lower n_int], upper / lower
+ *     per caller internal face = the coefficient in the row of the caller's
+ *     owner / neighbour; sets the layout's values.
+ * Inputs are first converted into the layout (not part of the operator's
+ * profile class).  The case's fields are not touched; its pressure work
+ * arrays are.  Errors: FVM_EINVAL for an unknown op, or an FVM_OP_HY_* op on
+ * a case without the layout. */
+fvm_status fvm_case_operator(fvm_case *c, int32_t op, const double *d_in, double *d_out, void *stream);
 
 /* piso_step_batch -- advance several resident cases by n_steps PISO steps,
  * their kernels batched into shared launches (continuous-batching serving).

@@ -222,6 +222,21 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
         if (mixed) d.f_sell_val = b.take<float>(ns * W * kBlock);
         else d.sell_val = b.take<double>(ns * W * kBlock);
     }
+    if (o.hybrid_K > 0) {
+        const size_t K = (size_t)o.hybrid_K;
+        size_t nC = 0;
+        for (int32_t i = 0; i < m.N; ++i) {
+            const size_t len = (size_t)(m.nbr_start[i + 1] - m.nbr_start[i]) + 1 + (m.own_start[i + 1] - m.own_start[i]);
+            nC += len > K ? len - K : 0;
+        }
+        const size_t E = K * N + nC;
+        d.hy_K = o.hybrid_K; d.hy_nC = (int32_t)nC;
+        d.hy_I = b.take<int32_t>(K * N); d.hy_J = b.take<int32_t>(K * N); d.hy_dpos = b.take<int32_t>(N);
+        d.hy_locO = b.take<int32_t>(Fi); d.hy_locN = b.take<int32_t>(Fi);
+        d.hy_cstart = b.take<int32_t>(N + 1); d.hy_ccol = b.take<int32_t>(nC); d.hy_ctrpos = b.take<int32_t>(nC);
+        d.hy_V = b.take<double>(E); d.hy_Sx = b.take<double>(E); d.hy_Sy = b.take<double>(E); d.hy_Sz = b.take<double>(E);
+        d.hy_w = b.take<double>(E); d.hy_dl = b.take<double>(E); d.hy_g = b.take<double>(E); d.hy_phi = b.take<double>(E);
+    }
     d.red_stride = (int32_t)(((N + kBlock - 1) / kBlock + 7) / 8 * 8);
     d.red_stride2 = (d.red_stride + kGroup - 1) / kGroup;
     d.partials = b.take<double>((size_t)kMaxRed * d.red_stride);
@@ -257,7 +272,9 @@ fvm_status check_opts(const fvm_mesh *m, const fvm_case_opts *o)
         return fvm_fail(FVM_EINVAL, "case: bad momentum solver");
     if (o->u_solver == FVM_SOLVER_BICGSTAB && o->precision != FVM_FP64)
         return fvm_fail(FVM_EINVAL, "case: the BiCGStab momentum solver is FP64 only");
-    if (o->reserved != 0) return fvm_fail(FVM_EINVAL, "case: reserved option field must be 0");
+    if (o->hybrid_K < 0 || o->hybrid_K > 64) return fvm_fail(FVM_EINVAL, "case: hybrid_K must be in [0, 64]");
+    if (o->hybrid_K > 0 && (int64_t)o->hybrid_K * m->N >= INT32_MAX)
+        return fvm_fail(FVM_EINVAL, "case: hybrid_K * n_cells exceeds int32");
     return FVM_OK;
 }
 
@@ -451,12 +468,25 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     }
     UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s)); UPCHK(up(d.sell_mir, m->sell_mir, s));
     UPCHK(up(d.sell_fe, m->sell_fe, s)); UPCHK(up(d.sell_col, m->sell_col, s));
+    HybridHost hy;
+    if (d.hy_K > 0) {
+        build_hybrid(*m, d.hy_K, hy);
+        if (hy.nC != d.hy_nC || (int64_t)d.hy_K * m->N + hy.nC >= INT32_MAX)
+            return fail(fvm_fail(FVM_EINVAL, "case: hybrid layout too large for int32 positions"));
+        UPCHK(up(d.hy_I, hy.dI, s)); UPCHK(up(d.hy_J, hy.dJ, s)); UPCHK(up(d.hy_dpos, hy.dpos, s));
+        UPCHK(up(d.hy_locO, hy.locO, s)); UPCHK(up(d.hy_locN, hy.locN, s));
+        UPCHK(up(d.hy_cstart, hy.c_start, s)); UPCHK(up(d.hy_ccol, hy.c_col, s)); UPCHK(up(d.hy_ctrpos, hy.c_trpos, s));
+        const size_t E = (size_t)d.hy_K * m->N + hy.nC;
+        for (double *a : {d.hy_V, d.hy_Sx, d.hy_Sy, d.hy_Sz, d.hy_w, d.hy_dl, d.hy_g, d.hy_phi})
+            UPCHK(hipMemsetAsync(a, 0, E * sizeof(double), s));
+    }
     UPCHK(hipMemsetAsync(d.ticket, 0, 64 * sizeof(unsigned int), s));
     UPCHK(hipMemsetAsync(d.gticket, 0, d.red_stride2 * sizeof(unsigned int), s));
     UPCHK(hipMemsetAsync(d.ks, 0, kNumKs * sizeof(KState), s));
     const Group g(c, s);
     launch_init_partials(g.bs, s);
     launch_geometry(g.bs, s);
+    if (d.hy_K > 0) launch_hybrid_geometry(g.bs, s);
     UPCHK(hipMemsetAsync(d.U, 0, 3 * (size_t)m->N * sizeof(double), s));
     UPCHK(hipMemsetAsync(d.p, 0, (size_t)m->N * sizeof(double), s));
     launch_flux_from_U(g.bs, s);
@@ -943,6 +973,21 @@ extern "C" fvm_status fvm_dic_apply(fvm_case *c, const double *gamma, const doub
     HIPCHK(hipMemcpyAsync(z, d.z, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
     if (dstar) HIPCHK(hipMemcpyAsync(dstar, d.dstar, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
+    return FVM_OK;
+}
+
+extern "C" fvm_status fvm_case_operator(fvm_case *c, int32_t op, const double *d_in, double *d_out, void *stream)
+{
+    if (!c) return fvm_fail(FVM_EINVAL, "operator: null case");
+    if (op < FVM_OP_GRAD || op > FVM_OP_HY_SETMAT) return fvm_fail(FVM_EINVAL, "operator: unknown op");
+    if (op >= FVM_OP_HY_GRAD && c->d.hy_K <= 0)
+        return fvm_fail(FVM_EINVAL, "operator: the case has no hybrid layout (create it with hybrid_K > 0)");
+    if (c->o.precision != FVM_FP64) return fvm_fail(FVM_EINVAL, "operator: FP64 cases only");
+    if (!d_in || (op != FVM_OP_HY_SETMAT && !d_out)) return fvm_fail(FVM_EINVAL, "operator: null array");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Group g(c, s);
+    launch_operator(g.bs, op, d_in, d_out, s);
+    HIPCHK(hipGetLastError());
     return FVM_OK;
 }
 

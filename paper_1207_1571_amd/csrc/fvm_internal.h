@@ -8,12 +8,35 @@
 
 #include "fvm.h"
 
+struct fvm_mesh;
+struct HybridHost;
+// builds h from the canonical mesh (see HybridHost); K >= 1
+void build_hybrid(const fvm_mesh &m, int32_t K, HybridHost &h);
+
 struct ihipStream_t;
 typedef struct ihipStream_t *hipStream_t;
 
 // ---------------------------------------------------------------------------
 // Host-side canonical mesh (built by fvm_mesh_create, uploaded per case)
 // ---------------------------------------------------------------------------
+// The paper's hybrid matrix layout (Section 3.1), built on the host from the
+// canonical faces: row i holds its entries in ascending column order (the
+// faces seen from the neighbour side, the diagonal, the owned faces); the
+// first K go to the ELL part B, the rest to the CRS part C.
+//   paper form (row-major, exported for checks): I[i*K+k] column, J[i*K+k]
+//   slot of the transposed entry in B, or -1 - c for position c in C; an
+//   unused slot holds I = i, J = k.  C: c_start[N+1], c_col, c_tr (K*j+k'
+//   for a transpose in B, -1 - c' in C).
+//   device form: B slot-major at k*N + i, C after it at K*N + c; dI, dJ as
+//   I, J; dpos[i] = position of the diagonal, locO[f] / locN[f] = positions
+//   of the owner-side / neighbour-side entries of canonical internal face f;
+//   c_trpos = device position of each C entry's transpose.
+struct HybridHost {
+    int32_t K = 0, nC = 0;
+    std::vector<int32_t> I, J, c_start, c_col, c_tr;
+    std::vector<int32_t> dI, dJ, dpos, locO, locN, c_trpos;
+};
+
 struct fvm_mesh {
     int32_t N = 0, F = 0, Fi = 0, Fb = 0, npatch = 0;
     // internal faces in canonical order: own[c] < nei[c], sorted by (own, nei);
@@ -152,6 +175,12 @@ struct DevCase {
     float *f_diag, *f_up, *f_lo, *f_pdiag, *f_poff;
     float *f_pexc;   // pressure row sums diag_i + sum_f off_f (FP64 sum, rounded)
     float *f_x, *f_b, *f_r, *f_rt, *f_p, *f_pt, *f_q, *f_qt;   // [3][N]
+    // the paper's hybrid layout (comparison operators; see HybridHost): B
+    // slot-major at k*N + i, C after it at hy_K*N + c; face data (S, w, dl),
+    // gamma and flux once per face at the owner-side entry
+    int32_t hy_K, hy_nC;
+    int32_t *hy_I, *hy_J, *hy_dpos, *hy_locO, *hy_locN, *hy_cstart, *hy_ccol, *hy_ctrpos;
+    double *hy_V, *hy_Sx, *hy_Sy, *hy_Sz, *hy_w, *hy_dl, *hy_g, *hy_phi;
     // reductions
     double *partials;                            // [kMaxRed][red_stride]   level-1 slots
     double *partials2;                           // [kMaxRed][red_stride2]  level-2 slots
@@ -245,6 +274,8 @@ void launch_mx_inner_init(const BatchSet &bs, int kind, hipStream_t s);
 void launch_mx_inner_iter(const BatchSet &bs, int kind, hipStream_t s);
 void launch_mx_correct_resid(const BatchSet &bs, int kind, hipStream_t s);
 // mixed-precision pressure CG: FP32 recurrence with FP64 residual replacement
+void launch_operator(const BatchSet &bs, int op, const double *in, double *out, hipStream_t s);
+void launch_hybrid_geometry(const BatchSet &bs, hipStream_t s);
 void launch_rr_start(const BatchSet &bs, hipStream_t s);
 void launch_rr_iter(const BatchSet &bs, hipStream_t s);
 void launch_rr_replace(const BatchSet &bs, hipStream_t s);

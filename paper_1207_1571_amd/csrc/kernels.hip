@@ -1964,6 +1964,235 @@ __global__ void __launch_bounds__(kBlock) k_mx_resid(Batch bt)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Operators one at a time (the assembly set of the paper's Table 3 plus the
+// matrix products), in the solver's face-major layout and in the paper's
+// hybrid layout (Section 3.1), for comparing the two
+// ---------------------------------------------------------------------------
+
+// caller face order -> canonical order; oriented values change sign where
+// the caller's orientation is reversed
+__global__ void k_faces_in(Batch bt, const double *__restrict__ uv, double *__restrict__ out, int oriented)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    out[f] = f < d.Fi ? (oriented ? (double)d.face_sign[f] : 1.0) * uv[d.face_user[f]] : uv[f];
+}
+
+// face-major Gauss gradient: the solver's gather
+__global__ void k_op_grad(Batch bt, const double *__restrict__ x, double *__restrict__ g)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    double g0, g1, g2;
+    gauss_sum(d, i, x, d.patch_pk, d.patch_pv, 1, g0, g1, g2);
+    const double V = d.V[i];
+    const long N = d.N;
+    g[i] = g0 / V; g[N + i] = g1 / V; g[2 * N + i] = g2 / V;
+}
+
+// face-major divergence of a canonical face flux (phiH): owned faces out,
+// neighbour-side faces in, non-EMPTY boundary faces out
+__global__ void k_op_div(Batch bt, double *__restrict__ out)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const double *__restrict__ ph = d.phiH;
+    double sum = 0.0;
+    for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) sum += ph[f];
+    for (int k = d.nbr_start[i]; k < d.nbr_start[i + 1]; ++k) sum -= ph[d.losort[k]];
+    for (int k = d.bnd_start[i]; k < d.bnd_start[i + 1]; ++k) {
+        const int b = d.bnd_list[k];
+        if (d.patch_pk[d.bpatch[b]] != FVM_BC_EMPTY) sum += ph[d.Fi + b];
+    }
+    out[i] = sum;
+}
+
+// face-major A x on the sliced-ELL copy (one block per slice), no dot
+__global__ void __launch_bounds__(kBlock) k_op_spmv(Batch bt, const double *__restrict__ x, double *__restrict__ y)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (K.raw * kBlock >= d.N) return;
+    const CGArr<double> v{d.pdiag, d.poff, nullptr, d.sell_val, nullptr, nullptr, const_cast<double *>(x), y, nullptr,
+                          nullptr};
+    if (i < d.N) (void)spmv_cell<double>(d, v, K.raw, i);
+}
+
+// hybrid layout: device position of the entry whose transpose code is Jc in
+// row j's slot (a slot of B, or -1 - c for position c of C)
+__device__ __forceinline__ long hy_tpos(const DevCase &d, int j, int Jc)
+{
+    return Jc >= 0 ? (long)Jc * d.N + j : (long)d.hy_K * d.N + (-1 - Jc);
+}
+
+// face data of canonical internal faces into their owner-side entries
+__global__ void k_hy_geom(Batch bt)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.Fi) return;
+    const long p = d.hy_locO[f];
+    d.hy_Sx[p] = d.Sx[f]; d.hy_Sy[p] = d.Sy[f]; d.hy_Sz[p] = d.Sz[f];
+    d.hy_w[p] = d.w[f]; d.hy_dl[p] = d.dl[f];
+}
+
+// caller face values -> owner-side entries of the layout
+__global__ void k_hy_faces_in(Batch bt, const double *__restrict__ uv, double *__restrict__ dst, int oriented)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.Fi) return;
+    dst[d.hy_locO[f]] = (oriented ? (double)d.face_sign[f] : 1.0) * uv[d.face_user[f]];
+}
+
+// matrix values from [diag N | upper Fi | lower Fi] in caller order
+__global__ void k_hy_setmat(Batch bt, const double *__restrict__ in)
+{
+    CASE_OF(bt);
+    const int t = K.raw * kBlock + threadIdx.x;
+    if (t < d.N) d.hy_V[d.hy_dpos[t]] = in[t];
+    if (t < d.Fi) {
+        const int u = d.face_user[t];
+        const double up = in[d.N + u], lo = in[(long)d.N + d.Fi + u];
+        const bool same = d.face_sign[t] > 0;
+        d.hy_V[d.hy_locO[t]] = same ? up : lo;
+        d.hy_V[d.hy_locN[t]] = same ? lo : up;
+    }
+}
+
+// Row i of the hybrid layout, entries in ascending column order (B, then
+// C); for each off-diagonal entry the face data sits at the entry itself
+// when i owns the face (j > i) and at the transposed entry otherwise.
+// Gauss gradient of x
+__global__ void k_hy_grad(Batch bt, const double *__restrict__ x, double *__restrict__ g)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const long N = d.N, KN = (long)d.hy_K * N;
+    const double xi = x[i];
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    auto face = [&](long own_pos, long tr_pos, int j) {
+        const bool owner = j > i;
+        const long p = owner ? own_pos : tr_pos;
+        const double w = d.hy_w[p];
+        const double pf = owner ? w * xi + (1.0 - w) * x[j] : w * x[j] + (1.0 - w) * xi;
+        const double sg = owner ? 1.0 : -1.0;
+        g0 += sg * d.hy_Sx[p] * pf; g1 += sg * d.hy_Sy[p] * pf; g2 += sg * d.hy_Sz[p] * pf;
+    };
+    for (int k = 0; k < d.hy_K; ++k) {
+        const long e = (long)k * N + i;
+        const int j = d.hy_I[e];
+        if (j != i) face(e, j > i ? e : hy_tpos(d, j, d.hy_J[e]), j);
+    }
+    for (int c = d.hy_cstart[i]; c < d.hy_cstart[i + 1]; ++c) {
+        const int j = d.hy_ccol[c];
+        if (j != i) face(KN + c, d.hy_ctrpos[c], j);
+    }
+    for (int k = d.bnd_start[i]; k < d.bnd_start[i + 1]; ++k) {
+        const int b = d.bnd_list[k], f = d.Fi + b, pt = d.bpatch[b], kind = d.patch_pk[pt];
+        if (kind == FVM_BC_EMPTY) continue;
+        const double pf = kind == FVM_BC_FIXED ? d.patch_pv[pt] : xi;
+        g0 += d.Sx[f] * pf; g1 += d.Sy[f] * pf; g2 += d.Sz[f] * pf;
+    }
+    const double V = d.V[i];
+    g[i] = g0 / V; g[N + i] = g1 / V; g[2 * N + i] = g2 / V;
+}
+
+// divergence of the flux held in the layout (hy_phi) plus the canonical
+// boundary fluxes (phiH)
+__global__ void k_hy_div(Batch bt, double *__restrict__ out)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const long N = d.N, KN = (long)d.hy_K * N;
+    double sum = 0.0;
+    for (int k = 0; k < d.hy_K; ++k) {
+        const long e = (long)k * N + i;
+        const int j = d.hy_I[e];
+        if (j > i) sum += d.hy_phi[e];
+        else if (j < i) sum -= d.hy_phi[hy_tpos(d, j, d.hy_J[e])];
+    }
+    for (int c = d.hy_cstart[i]; c < d.hy_cstart[i + 1]; ++c) {
+        const int j = d.hy_ccol[c];
+        if (j > i) sum += d.hy_phi[KN + c];
+        else if (j < i) sum -= d.hy_phi[d.hy_ctrpos[c]];
+    }
+    for (int k = d.bnd_start[i]; k < d.bnd_start[i + 1]; ++k) {
+        const int b = d.bnd_list[k];
+        if (d.patch_pk[d.bpatch[b]] != FVM_BC_EMPTY) sum += d.phiH[d.Fi + b];
+    }
+    out[i] = sum;
+}
+
+// pressure Laplacian into the layout's values: off-diagonal -gamma dl, the
+// diagonal their negated sum plus the FIXED-p boundary terms and the pin
+__global__ void k_hy_lap(Batch bt)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const long N = d.N, KN = (long)d.hy_K * N, dp = d.hy_dpos[i];
+    double dg = 0.0;
+    for (int k = 0; k < d.hy_K; ++k) {
+        const long e = (long)k * N + i;
+        const int j = d.hy_I[e];
+        if (j == i) {
+            if (e != dp) d.hy_V[e] = 0.0;   // unused slot
+            continue;
+        }
+        const long p = j > i ? e : hy_tpos(d, j, d.hy_J[e]);
+        const double a = d.hy_g[p] * d.hy_dl[p];
+        d.hy_V[e] = -a;
+        dg += a;
+    }
+    for (int c = d.hy_cstart[i]; c < d.hy_cstart[i + 1]; ++c) {
+        const int j = d.hy_ccol[c];
+        if (j == i) continue;
+        const long p = j > i ? KN + c : d.hy_ctrpos[c];
+        const double a = d.hy_g[p] * d.hy_dl[p];
+        d.hy_V[KN + c] = -a;
+        dg += a;
+    }
+    for (int k = d.bnd_start[i]; k < d.bnd_start[i + 1]; ++k) {
+        const int b = d.bnd_list[k], f = d.Fi + b;
+        if (d.patch_pk[d.bpatch[b]] == FVM_BC_FIXED) dg += d.gam[f] * d.dl[f];
+    }
+    if (i == d.pin_cell && !d.has_fixed_p) dg = 2.0 * dg;
+    d.hy_V[dp] = dg;
+}
+
+// y = A x (row access: V, I) or A^T x (column access: the value of the
+// transposed entry, found through J)
+__global__ void k_hy_spmv(Batch bt, const double *__restrict__ x, double *__restrict__ y, int transpose)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    const long N = d.N, KN = (long)d.hy_K * N;
+    double acc = 0.0;
+    if (!transpose) {
+        for (int k = 0; k < d.hy_K; ++k) {
+            const long e = (long)k * N + i;
+            acc += d.hy_V[e] * x[d.hy_I[e]];
+        }
+        for (int c = d.hy_cstart[i]; c < d.hy_cstart[i + 1]; ++c) acc += d.hy_V[KN + c] * x[d.hy_ccol[c]];
+    } else {
+        for (int k = 0; k < d.hy_K; ++k) {
+            const long e = (long)k * N + i;
+            const int j = d.hy_I[e];
+            acc += d.hy_V[hy_tpos(d, j, d.hy_J[e])] * x[j];
+        }
+        for (int c = d.hy_cstart[i]; c < d.hy_cstart[i + 1]; ++c) acc += d.hy_V[d.hy_ctrpos[c]] * x[d.hy_ccol[c]];
+    }
+    y[i] = acc;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2219,3 +2448,75 @@ void launch_rr_replace(const BatchSet &bs, hipStream_t s)
     Prof p("pcg_replace", s);
     run(k_rr_replace, bs, SZ_CELL4, s);
 }
+
+// one operator of fvm_case_operator (op validated by the caller); the input
+// conversion runs outside the operator's profile class
+void launch_operator(const BatchSet &bs, int op, const double *in, double *out, hipStream_t s)
+{
+    const DevCase &h = *bs.host[0];
+    switch (op) {
+    case FVM_OP_GRAD: {
+        Prof p("op_grad", s);
+        run(k_op_grad, bs, SZ_CELL, s, in, out);
+        break;
+    }
+    case FVM_OP_DIV: {
+        run(k_faces_in, bs, SZ_FACE, s, in, h.phiH, 1);
+        Prof p("op_div", s);
+        run(k_op_div, bs, SZ_CELL, s, out);
+        break;
+    }
+    case FVM_OP_LAP: {
+        run(k_faces_in, bs, SZ_FACE, s, in, h.gam, 0);
+        {
+            Prof p("op_lap", s);
+            run(k_p_face_gamma, bs, SZ_FACE, s, (const double *)h.gam);
+            run(k_p_cell, bs, SZ_CELL, s, 0);
+        }
+        run(k_sell_fill, bs, SZ_CELL, s);
+        (void)hipMemcpyAsync(out, h.pdiag, sizeof(double) * (size_t)h.N, hipMemcpyDeviceToDevice, s);
+        break;
+    }
+    case FVM_OP_SPMV: {
+        Prof p("op_spmv", s);
+        run(k_op_spmv, bs, SZ_CELL, s, in, out);
+        break;
+    }
+    case FVM_OP_HY_GRAD: {
+        Prof p("hy_grad", s);
+        run(k_hy_grad, bs, SZ_CELL, s, in, out);
+        break;
+    }
+    case FVM_OP_HY_DIV: {
+        run(k_faces_in, bs, SZ_FACE, s, in, h.phiH, 1);
+        run(k_hy_faces_in, bs, SZ_FACEI, s, in, h.hy_phi, 1);
+        Prof p("hy_div", s);
+        run(k_hy_div, bs, SZ_CELL, s, out);
+        break;
+    }
+    case FVM_OP_HY_LAP: {
+        run(k_faces_in, bs, SZ_FACE, s, in, h.gam, 0);
+        run(k_hy_faces_in, bs, SZ_FACEI, s, in, h.hy_g, 0);
+        {
+            Prof p("hy_lap", s);
+            run(k_hy_lap, bs, SZ_CELL, s);
+        }
+        (void)hipMemcpyAsync(out, h.hy_V, sizeof(double) * ((size_t)h.hy_K * h.N + h.hy_nC), hipMemcpyDeviceToDevice,
+                             s);
+        break;
+    }
+    case FVM_OP_HY_SPMV:
+    case FVM_OP_HY_STMVP: {
+        Prof p(op == FVM_OP_HY_SPMV ? "hy_spmv" : "hy_stmvp", s);
+        run(k_hy_spmv, bs, SZ_CELL, s, in, out, op == FVM_OP_HY_STMVP ? 1 : 0);
+        break;
+    }
+    case FVM_OP_HY_SETMAT:
+        run(k_hy_setmat, bs, SZ_MAXNF, s, in);
+        break;
+    default:
+        break;
+    }
+}
+
+void launch_hybrid_geometry(const BatchSet &bs, hipStream_t s) { run(k_hy_geom, bs, SZ_FACEI, s); }

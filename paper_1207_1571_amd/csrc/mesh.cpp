@@ -117,6 +117,87 @@ void build_sell(fvm_mesh *m)
     }
 }
 
+}  // namespace
+
+// Hybrid layout (Section 3.1).  Row i in ascending column order is: the
+// owners of the faces whose neighbour is i (losort order: ascending owner),
+// the diagonal, the neighbours of the faces i owns (ascending neighbour).
+// So the slot of every entry follows from face positions alone: face f =
+// (o, n), o < n, sits at slot nlow(o) + 1 + (f - own_start[o]) of row o and
+// at slot (t - nbr_start[n]) of row n, where losort[t] = f.
+void build_hybrid(const fvm_mesh &m, int32_t K, HybridHost &h)
+{
+    const int32_t N = m.N, Fi = m.Fi;
+    h.K = K;
+    std::vector<int32_t> nlow(N), len(N);
+    for (int32_t i = 0; i < N; ++i) {
+        nlow[i] = m.nbr_start[i + 1] - m.nbr_start[i];
+        len[i] = nlow[i] + 1 + (m.own_start[i + 1] - m.own_start[i]);
+    }
+    h.c_start.assign((size_t)N + 1, 0);
+    for (int32_t i = 0; i < N; ++i) h.c_start[i + 1] = h.c_start[i] + std::max(0, len[i] - K);
+    h.nC = h.c_start[N];
+    std::vector<int32_t> lpos(Fi);
+    for (int32_t t = 0; t < Fi; ++t) lpos[m.losort[t]] = t;
+    // an entry (row, slot): its paper-form transpose code and device position
+    auto code = [&](int32_t row, int32_t slot) { return slot < K ? slot : -1 - (h.c_start[row] + slot - K); };
+    auto devpos = [&](int32_t row, int32_t slot) {
+        return slot < K ? (int32_t)((int64_t)slot * N + row) : (int32_t)((int64_t)K * N + h.c_start[row] + slot - K);
+    };
+    h.I.assign((size_t)N * K, 0);
+    h.J.assign((size_t)N * K, 0);
+    for (int32_t i = 0; i < N; ++i)
+        for (int32_t k = 0; k < K; ++k) {   // unused slots; real entries are overwritten below
+            h.I[(size_t)i * K + k] = i;
+            h.J[(size_t)i * K + k] = k;
+        }
+    h.c_col.assign(h.nC, 0);
+    h.c_tr.assign(h.nC, 0);
+    h.dpos.assign(N, 0);
+    h.locO.assign(Fi, 0);
+    h.locN.assign(Fi, 0);
+    // place one entry: row r, slot sl, column col, transpose at (tr_row, tr_slot)
+    auto place = [&](int32_t r, int32_t sl, int32_t col, int32_t tr_row, int32_t tr_slot) {
+        if (sl < K) {
+            h.I[(size_t)r * K + sl] = col;
+            h.J[(size_t)r * K + sl] = code(tr_row, tr_slot);
+        } else {
+            const int32_t c = h.c_start[r] + sl - K;
+            h.c_col[c] = col;
+            h.c_tr[c] = tr_slot < K ? K * tr_row + tr_slot : code(tr_row, tr_slot);
+        }
+    };
+    for (int32_t i = 0; i < N; ++i) {
+        place(i, nlow[i], i, i, nlow[i]);
+        h.dpos[i] = devpos(i, nlow[i]);
+    }
+    for (int32_t o = 0; o < N; ++o)
+        for (int32_t f = m.own_start[o]; f < m.own_start[o + 1]; ++f) {
+            const int32_t n = m.nei[f];
+            const int32_t so = nlow[o] + 1 + (f - m.own_start[o]);
+            const int32_t sn = lpos[f] - m.nbr_start[n];
+            place(o, so, n, n, sn);
+            place(n, sn, o, o, so);
+            h.locO[f] = devpos(o, so);
+            h.locN[f] = devpos(n, sn);
+        }
+    // device forms
+    h.dI.assign((size_t)N * K, 0);
+    h.dJ.assign((size_t)N * K, 0);
+    for (int32_t i = 0; i < N; ++i)
+        for (int32_t k = 0; k < K; ++k) {
+            h.dI[(size_t)k * N + i] = h.I[(size_t)i * K + k];
+            h.dJ[(size_t)k * N + i] = h.J[(size_t)i * K + k];
+        }
+    h.c_trpos.assign(h.nC, 0);
+    for (int32_t c = 0; c < h.nC; ++c) {
+        const int32_t t = h.c_tr[c];
+        h.c_trpos[c] = t >= 0 ? (int32_t)((int64_t)(t % K) * N + t / K) : (int32_t)((int64_t)K * N + (-1 - t));
+    }
+}
+
+namespace {
+
 fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
 {
     if (!d || d->n_cells < 1 || d->n_internal_faces < 0 || d->n_faces < d->n_internal_faces || d->n_patches < 0)
@@ -313,6 +394,30 @@ extern "C" fvm_status fvm_mesh_create(const fvm_mesh_desc *desc, fvm_mesh **out)
 }
 
 extern "C" void fvm_mesh_destroy(fvm_mesh *mesh) { delete mesh; }
+
+extern "C" fvm_status fvm_mesh_hybrid(const fvm_mesh *m, int32_t K, int32_t *n_crs, int32_t *I, int32_t *J,
+                                      int32_t *Q, int32_t *c_start, int32_t *c_col, int32_t *c_tr)
+{
+    if (!m) return fvm_fail(FVM_EINVAL, "hybrid: null mesh");
+    if (K < 1) return fvm_fail(FVM_EINVAL, "hybrid: K must be >= 1");
+    if ((int64_t)K * m->N >= INT32_MAX) return fvm_fail(FVM_EINVAL, "hybrid: K * n_cells exceeds int32");
+    try {
+        HybridHost h;
+        build_hybrid(*m, K, h);
+        if (n_crs) *n_crs = h.nC;
+        const size_t NK = (size_t)m->N * K;
+        if (I) std::copy(h.I.begin(), h.I.end(), I);
+        if (J) std::copy(h.J.begin(), h.J.end(), J);
+        if (Q)
+            for (size_t e = 0; e < NK; ++e) Q[e] = h.J[e] >= 0 ? K * h.I[e] + h.J[e] : -1;
+        if (c_start) std::copy(h.c_start.begin(), h.c_start.end(), c_start);
+        if (c_col) std::copy(h.c_col.begin(), h.c_col.end(), c_col);
+        if (c_tr) std::copy(h.c_tr.begin(), h.c_tr.end(), c_tr);
+    } catch (const std::bad_alloc &) {
+        return fvm_fail(FVM_ENOMEM, "hybrid: out of host memory");
+    }
+    return FVM_OK;
+}
 
 extern "C" fvm_status fvm_mesh_info(const fvm_mesh *m, int32_t *n_cells, int32_t *n_faces, int32_t *n_internal,
                                     int32_t *non_orthogonal)

@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libfvm.so")
 FVM_OK, FVM_WARN_MAXITER, FVM_EINVAL, FVM_ENOMEM, FVM_ENUMERIC, FVM_EDEVICE = 0, 1, -1, -2, -3, -4
 BC_FIXED, BC_ZERO_GRAD, BC_EMPTY = 0, 1, 2
 PC_JACOBI, PC_DIC = 0, 1
+# fvm_case_operator: face-major layout, then the paper's hybrid layout
+OP_GRAD, OP_DIV, OP_LAP, OP_SPMV = 0, 1, 2, 3
+OP_HY_GRAD, OP_HY_DIV, OP_HY_LAP, OP_HY_SPMV, OP_HY_STMVP, OP_HY_SETMAT = 4, 5, 6, 7, 8, 9
 FP64, MIXED = 0, 1
 
 i32p = ct.POINTER(ct.c_int32)
@@ -46,7 +49,7 @@ class FvmCaseOpts(ct.Structure):
                 ("p_ref_value", ct.c_double), ("inner_rel_tol", ct.c_double), ("n_corr", ct.c_int32),
                 ("n_non_orth_corr", ct.c_int32), ("convection", ct.c_int32), ("precision", ct.c_int32),
                 ("p_ref_cell", ct.c_int32), ("inner_max_iter", ct.c_int32), ("p_ctl", FvmSolverCtl),
-                ("u_ctl", FvmSolverCtl), ("u_solver", ct.c_int32), ("reserved", ct.c_int32)]
+                ("u_ctl", FvmSolverCtl), ("u_solver", ct.c_int32), ("hybrid_K", ct.c_int32)]
 
 
 class FvmSolveInfo(ct.Structure):
@@ -77,7 +80,7 @@ _lib = None
 EXPORTS = ("fvm_mesh_create", "fvm_mesh_destroy", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
            "fvm_case_destroy", "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
            "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read",
-           "fvm_last_error")
+           "fvm_last_error", "fvm_mesh_hybrid", "fvm_case_operator")
 
 
 def lib():
@@ -110,9 +113,12 @@ def lib():
         L.fvm_profile_enable.argtypes = [ct.c_int32]
         L.fvm_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
         L.fvm_last_error.restype = ct.c_char_p
+        L.fvm_mesh_hybrid.argtypes = [vp, ct.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, i32p]
+        L.fvm_case_operator.argtypes = [vp, ct.c_int32, vp, vp, vp]
         for name in ("fvm_mesh_create", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
                      "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
-                     "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read"):
+                     "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable",
+                     "fvm_profile_read", "fvm_mesh_hybrid", "fvm_case_operator"):
             getattr(L, name).restype = ct.c_int32
         _lib = L
     return _lib
@@ -174,7 +180,7 @@ def opts_from_case(case) -> FvmCaseOpts:
                        case.inner_max_iter,
                        FvmSolverCtl(case.p_ctl.tol, case.p_ctl.rel_tol, case.p_ctl.max_iter, case.p_ctl.precond),
                        FvmSolverCtl(case.u_ctl.tol, case.u_ctl.rel_tol, case.u_ctl.max_iter, case.u_ctl.precond),
-                       getattr(case, "u_solver", 0), 0)
+                       getattr(case, "u_solver", 0), getattr(case, "hybrid_K", 0))
 
 
 def workspace_bytes(mesh: Mesh, opts: FvmCaseOpts) -> int:
@@ -256,6 +262,27 @@ class Case:
         st = _check(lib().solve_pressure(self.handle, _dptr(gamma), _dptr(rhs), _dptr(p), ct.byref(ctl),
                                          ct.c_void_p(_stream_ptr(self.stream)), ct.byref(info)))
         return st, info.as_dict()
+
+
+def mesh_hybrid(mesh: Mesh, K: int):
+    """fvm_mesh_hybrid: the paper-form index arrays of the hybrid layout."""
+    import numpy as np
+    nC = ct.c_int32()
+    _check(lib().fvm_mesh_hybrid(mesh.handle, K, ct.byref(nC), None, None, None, None, None, None))
+    N = mesh.n_cells
+    out = dict(I=np.empty((N, K), np.int32), J=np.empty((N, K), np.int32), Q=np.empty((N, K), np.int32),
+               c_start=np.empty(N + 1, np.int32), c_col=np.empty(max(nC.value, 1), np.int32),
+               c_tr=np.empty(max(nC.value, 1), np.int32))
+    p = {k: v.ctypes.data_as(i32p) for k, v in out.items()}
+    _check(lib().fvm_mesh_hybrid(mesh.handle, K, None, p["I"], p["J"], p["Q"], p["c_start"], p["c_col"], p["c_tr"]))
+    out["c_col"] = out["c_col"][:nC.value]
+    out["c_tr"] = out["c_tr"][:nC.value]
+    return out
+
+
+def operator(case: Case, op: int, x, out=None):
+    """fvm_case_operator on the case's stream (device tensors)."""
+    _check(lib().fvm_case_operator(case.handle, op, _dptr(x), _dptr(out), ct.c_void_p(_stream_ptr(case.stream))))
 
 
 def dic_apply(case: Case, gamma, r, z, dstar=None):

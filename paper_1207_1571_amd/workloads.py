@@ -63,6 +63,7 @@ class CaseSpec:
     inner_rel_tol: float = 1e-3
     inner_max_iter: int = 2000
     u_solver: int = SOLVER_BICG
+    hybrid_K: int = 0            # > 0: the case also holds the paper's hybrid layout (comparison operators)
     p_ctl: SolverCtl = field(default_factory=lambda: SolverCtl(1e-6))
     u_ctl: SolverCtl = field(default_factory=lambda: SolverCtl(1e-6))
     mode: str = "piso"            # "piso" | "simple"
