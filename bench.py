@@ -237,6 +237,65 @@ def tp_section(fvm, wl, steps, log):
     return res
 
 
+# the paper's Table 3 (C2070, its hybrid layout): SMVP time and the
+# divergence, gradient and Laplacian times normalised by it
+PAPER_TABLE3 = {"cav100": dict(smvp_us=1103, div=2.9, grad=10.7, lap=2.4),
+                "tp1M": dict(smvp_us=775, div=2.8, grad=10.4, lap=2.3)}
+
+
+def layout_section(fvm, wl, log, reps=20):
+    """The assembly operators one at a time in the solver's face-major layout
+    and in the paper's hybrid layout (ELL + J + CRS, K = 7), normalised by
+    each layout's own SMVP as in the paper's Table 3 (device time per launch,
+    HIP events; the conversion of the inputs into each layout is excluded)."""
+    import numpy as np
+    import torch
+    out = {}
+    specs = (("cav100", "cav100 (random + RCM numbering)", wl.cav100(n=100, n_steps=1)),
+             ("cav100_lex", "100^3 cavity, lexicographic", wl.cavity((100, 100, 100), Re=400.0, dt=0.002)),
+             ("tp1M", "tp1M 3200x300 pipe, lexicographic", wl.tp1m(n_steps=1)))
+    for key, desc, spec in specs:
+        spec = spec.with_(hybrid_K=7)
+        t = time.perf_counter()
+        c = fvm.Case(spec)
+        N, F = spec.mesh.V.shape[0], spec.mesh.owner.shape[0]
+        log(f"layouts {key}: case with both layouts in {time.perf_counter() - t:.1f}s")
+        rng = np.random.default_rng(9)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()
+        x, flux, gamma = dev(rng.normal(size=N)), dev(rng.normal(size=F)), dev(rng.uniform(0.5, 2.0, F))
+        y, g3 = torch.empty(N, dtype=torch.float64, device="cuda"), torch.empty(3 * N, dtype=torch.float64, device="cuda")
+        V = torch.empty(7 * N + 2 * F, dtype=torch.float64, device="cuda")
+        ops = [(fvm.OP_LAP, gamma, y), (fvm.OP_GRAD, x, g3), (fvm.OP_DIV, flux, y), (fvm.OP_SPMV, x, y),
+               (fvm.OP_HY_LAP, gamma, V), (fvm.OP_HY_GRAD, x, g3), (fvm.OP_HY_DIV, flux, y), (fvm.OP_HY_SPMV, x, y),
+               (fvm.OP_HY_STMVP, x, y)]
+        for op, a, o in ops:
+            fvm.operator(c, op, a, o)
+        torch.cuda.synchronize()
+        fvm.profile_enable(True)
+        for _ in range(reps):
+            for op, a, o in ops:
+                fvm.operator(c, op, a, o)
+        torch.cuda.synchronize()
+        us = {}
+        for cls in ("op_spmv", "op_grad", "op_div", "op_lap", "hy_spmv", "hy_stmvp", "hy_grad", "hy_div", "hy_lap"):
+            ms, n = fvm.profile_read(cls)
+            us[cls] = round(1e3 * ms / max(n, 1), 2)
+        fvm.profile_enable(False)
+        res = dict(workload=desc, cells=N)
+        for lay, pre in (("face_major", "op"), ("hybrid", "hy")):
+            sm = us[pre + "_spmv"]
+            res[lay] = dict(smvp_us=sm, div=round(us[pre + "_div"] / sm, 2), grad=round(us[pre + "_grad"] / sm, 2),
+                            lap=round(us[pre + "_lap"] / sm, 2))
+        res["hybrid"]["stmvp"] = round(us["hy_stmvp"] / us["hy_spmv"], 2)
+        res["us"] = us
+        base = "tp1M" if key == "tp1M" else "cav100"
+        res["paper_table3"] = PAPER_TABLE3[base]
+        log(f"layouts {key}: face-major {res['face_major']}, hybrid {res['hybrid']}")
+        out[key] = res
+        del c
+    return out
+
+
 def serve_section(fvm, wl, n_requests, n_steps, log):
     """Serving stream (cavity/duct cases, cube side log-uniform 16..96,
     Re U(10, 1000), Poisson arrivals at 40 req/s), reduced to `n_requests`
@@ -280,6 +339,8 @@ def main():
                     help="steps of the per-kernel-class timing pass of the 200^3 section (0: skip)")
     ap.add_argument("--tp-steps", type=int, default=10, help="PISO steps of the tp1M transient pipe section (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving section (0: skip)")
+    ap.add_argument("--no-layouts", dest="layouts", action="store_false",
+                    help="skip the face-major vs hybrid layout operator comparison")
     ap.add_argument("--serve-steps", type=int, default=20, help="PISO steps per serving request")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for memory counters)")
@@ -347,6 +408,7 @@ def main():
               if args.cav200_steps > 0 else None)
     serving = serve_section(fvm, wl, args.serve_requests, args.serve_steps, log) if args.serve_requests > 0 else None
     tp = tp_section(fvm, wl, args.tp_steps, log) if args.tp_steps > 0 else None
+    layouts = layout_section(fvm, wl, log) if args.layouts else None
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"]) if kernels else None
     roofline = None
     if dom:
@@ -393,6 +455,7 @@ def main():
         "cav200": cav200,
         "serving": serving,
         "tp1m": tp,
+        "layouts": layouts,
         "p_iters_last_step": p_iters_last,
         "roofline": roofline,
         "assembly_vs_spmv": vs_spmv(kernels, "pcg_spmv") if kernels else None,
