@@ -1557,6 +1557,7 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     if (live && MODE != 2) acc = MODE == 0 ? d.pdiag[i] : d.r[i];
     const double dsi = (MODE != 0 && live) ? d.dq[fq] : 1.0;
     const double yi = (MODE == 2 && live) ? d.yq[fq] : 0.0;
+    const double ri = (MODE == 2 && live) ? d.r[i] : 0.0;   // for r.z, loaded before the wait
     unsigned int missing = fast ? (nd >= 32 ? 0xffffffffu : ((1u << nd) - 1u)) : 0u;
     int k = 0;                // streaming path cursor
     double part = 0.0;
@@ -1612,7 +1613,7 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
                     dic_put(d.zq, fq, zi);
                     d.z[i] = zi;
                     clear_word(d.yq, fq);
-                    part = d.r[i] * zi;
+                    part = ri * zi;
                 }
                 fin = true;
             } else if (++spins > kSpinLimit) {
