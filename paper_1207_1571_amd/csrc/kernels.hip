@@ -1553,6 +1553,9 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
         double v;
         for (int sp = 0; sp < kSpinLimit && !dic_try(src, gp, v); ++sp) __builtin_amdgcn_s_sleep(1);
     }
+    // past the gate the wave is near the completion front: it takes issue
+    // priority over the waves still waiting at their gates
+    __builtin_amdgcn_s_setprio(2);
     double acc = 0.0;
     if (live && MODE != 2) acc = MODE == 0 ? d.pdiag[i] : d.r[i];
     const double dsi = (MODE != 0 && live) ? d.dq[fq] : 1.0;
@@ -1630,6 +1633,7 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
         if (__all(fin)) break;
         __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_s_setprio(0);
     return part;
 }
 
