@@ -1548,10 +1548,13 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     for (int o = 32; o > 0; o >>= 1) gate = max(gate, __shfl_xor(gate, o, 64));
     const int gq = chunk * kChunk - d.dic_lag;   // the gate, in processing order
     if (gate >= 0 && gq >= 0) {
-        // every lane loads the same word: one request per wave
+        // every lane loads the same word: one request per wave; the wait
+        // is long (the gate lies about two levels behind the wave's first
+        // position), so the wave sleeps ~2000 cycles between polls and
+        // leaves the issue slots and the L2 to the waves at the front
         const int gp = MODE == 2 ? n - 1 - gq : gq;
         double v;
-        for (int sp = 0; sp < kSpinLimit && !dic_try(src, gp, v); ++sp) __builtin_amdgcn_s_sleep(1);
+        for (int sp = 0; sp < kSpinLimit && !dic_try(src, gp, v); ++sp) __builtin_amdgcn_s_sleep(32);
     }
     // past the gate the wave is near the completion front: it takes issue
     // priority over the waves still waiting at their gates
