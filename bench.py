@@ -243,6 +243,30 @@ PAPER_TABLE3 = {"cav100": dict(smvp_us=1103, div=2.9, grad=10.7, lap=2.4),
                 "tp1M": dict(smvp_us=775, div=2.8, grad=10.4, lap=2.3)}
 
 
+def precond_section(fvm, wl, mesh, steps, log):
+    """The benchmark case with the pressure preconditioner switched to
+    Jacobi: the same PISO steps from rest, time per step and CG iterations
+    (the benchmark configuration itself uses DIC)."""
+    import torch
+    spec = wl.cav100(n=100, n_steps=steps)
+    spec = spec.with_(p_ctl=wl.SolverCtl(spec.p_ctl.tol, spec.p_ctl.rel_tol, spec.p_ctl.max_iter, wl.PC_JACOBI))
+    c = fvm.Case(spec, mesh=mesh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(steps):
+        st, info = c.piso(1)
+        its += sum(s["iters"] for s in info["p"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res = dict(workload=f"cav100, {steps} PISO steps from rest, pressure CG with Jacobi instead of DIC",
+               ms_per_step=round(1e3 * wall / steps, 2), p_iters_per_step=round(its / steps, 1),
+               cell_updates_per_s=round(mesh.n_cells * steps / wall, 1))
+    log(f"precond: Jacobi {res['ms_per_step']} ms/step, {res['p_iters_per_step']} CG iterations per step")
+    del c
+    return res
+
+
 def layout_section(fvm, wl, log, reps=20):
     """The assembly operators one at a time in the solver's face-major layout
     and in the paper's hybrid layout (ELL + J + CRS, K = 7), normalised by
@@ -339,6 +363,8 @@ def main():
                     help="steps of the per-kernel-class timing pass of the 200^3 section (0: skip)")
     ap.add_argument("--tp-steps", type=int, default=10, help="PISO steps of the tp1M transient pipe section (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=32, help="requests of the serving section (0: skip)")
+    ap.add_argument("--no-precond-compare", dest="precond_compare", action="store_false",
+                    help="skip the run of the benchmark case with Jacobi in place of DIC")
     ap.add_argument("--no-layouts", dest="layouts", action="store_false",
                     help="skip the face-major vs hybrid layout operator comparison")
     ap.add_argument("--serve-steps", type=int, default=20, help="PISO steps per serving request")
@@ -403,6 +429,7 @@ def main():
         kernels = profile_classes(fvm, pc, args.profile_steps, N, Fi, spec.p_ctl.precond == wl.PC_DIC)
         del pc
         log("kernel classes: " + json.dumps(kernels))
+    jacobi = precond_section(fvm, wl, mesh, args.steps, log) if args.precond_compare else None
     del mesh
     cav200 = (cav200_section(fvm, wl, args.cav200_steps, log, args.cav200_profile_steps)
               if args.cav200_steps > 0 else None)
@@ -456,6 +483,7 @@ def main():
         "serving": serving,
         "tp1m": tp,
         "layouts": layouts,
+        "jacobi_instead_of_dic": jacobi,
         "p_iters_last_step": p_iters_last,
         "roofline": roofline,
         "assembly_vs_spmv": vs_spmv(kernels, "pcg_spmv") if kernels else None,
