@@ -53,9 +53,15 @@ enum {
  * FIXED: the patch value; ZERO_GRAD: the owner-cell value; EMPTY: the face
  * takes part in no sum (front/back of 2-D slabs). */
 enum { FVM_BC_FIXED = 0, FVM_BC_ZERO_GRAD = 1, FVM_BC_EMPTY = 2 };
-/* Pressure preconditioner: Jacobi (the paper's choice, Section 3) or
- * diagonal incomplete Cholesky. */
-enum { FVM_PC_JACOBI = 0, FVM_PC_DIC = 1 };
+/* Pressure preconditioner: Jacobi (the paper's choice, Section 3),
+ * diagonal incomplete Cholesky, or one V-cycle of an aggregation algebraic
+ * multigrid (the stronger preconditioner the paper leaves to future work,
+ * Section 5: one-ring aggregation of the cell graph, piecewise-constant
+ * prolongation, Galerkin coarse operators rebuilt at every solve, damped
+ * Jacobi smoothing with weight 2/3 before and after the coarse correction,
+ * an exact solve on the coarsest level; FP64 cases only, one case per
+ * piso_step_batch call). */
+enum { FVM_PC_JACOBI = 0, FVM_PC_DIC = 1, FVM_PC_AMG = 2 };
 /* FVM_FP64: everything in double precision.  FVM_MIXED: the inner Krylov
  * iterations run in FP32 inside an FP64 residual-refinement loop. */
 enum { FVM_FP64 = 0, FVM_MIXED = 1 };
@@ -218,6 +224,15 @@ fvm_status fvm_dic_apply(fvm_case *c, const double *d_gamma_f, const double *d_r
  * n_crs.  Errors: FVM_EINVAL for K < 1 or K * n_cells beyond int32. */
 fvm_status fvm_mesh_hybrid(const fvm_mesh *mesh, int32_t K, int32_t *n_crs, int32_t *I, int32_t *J, int32_t *Q,
                            int32_t *c_start, int32_t *c_col, int32_t *c_tr);
+
+/* fvm_mesh_amg -- the aggregation AMG hierarchy the FVM_PC_AMG
+ * preconditioner builds for this mesh (host arrays the caller allocates;
+ * any may be NULL): the number of levels, and for `level` its cell and face
+ * counts, its faces (own < nei, sorted) and, except on the last level, the
+ * aggregate of each cell on the next level.  Level 0 is the mesh, its faces
+ * in canonical order.  Errors: FVM_EINVAL for a level out of range. */
+fvm_status fvm_mesh_amg(const fvm_mesh *mesh, int32_t level, int32_t *n_levels, int32_t *n_cells, int32_t *n_faces,
+                        int32_t *own, int32_t *nei, int32_t *agg);
 
 enum {
     FVM_OP_GRAD = 0, FVM_OP_DIV = 1, FVM_OP_LAP = 2, FVM_OP_SPMV = 3,

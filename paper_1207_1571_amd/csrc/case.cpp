@@ -147,7 +147,7 @@ struct Bump {
     }
 };
 
-void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
+void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d, std::vector<AmgLevel> *lv = nullptr)
 {
     const size_t N = m.N, F = m.F, Fi = m.Fi, Fb = m.Fb, np = m.npatch;
     const bool no = m.nonorth, dic = o.p_ctl.precond == FVM_PC_DIC, mixed = o.precision == FVM_MIXED;
@@ -222,6 +222,44 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d)
         if (mixed) d.f_sell_val = b.take<float>(ns * W * kBlock);
         else d.sell_val = b.take<double>(ns * W * kBlock);
     }
+    if (o.p_ctl.precond == FVM_PC_AMG) {
+        const AmgHost &A = mesh_amg(m);
+        const int nl = (int)A.L.size();
+        d.amg_nl = nl;
+        d.amg_nc = A.L[nl - 1].n;
+        d.amg = b.take<AmgLevel>(nl);
+        d.amg_cinv = b.take<double>((size_t)d.amg_nc * d.amg_nc);
+        if (!d.z) d.z = b.take<double>(N);
+        std::vector<AmgLevel> tmp;
+        std::vector<AmgLevel> &v = lv ? *lv : tmp;
+        v.assign(nl, AmgLevel{});
+        for (int l = 0; l < nl; ++l) {
+            const AmgLevelHost &L = A.L[l];
+            const size_t n = L.n, nf = L.nf;
+            d.amg_n[l] = L.n;
+            d.amg_nf[l] = L.nf;
+            AmgLevel &e = v[l];
+            e.n = L.n;
+            e.nf = L.nf;
+            e.x = b.take<double>(n);
+            e.r = b.take<double>(n);
+            if (l > 0) {
+                e.diag = b.take<double>(n); e.offd = b.take<double>(nf); e.b = b.take<double>(n);
+                e.out = e.r;
+                e.own = b.take<int32_t>(nf); e.nei = b.take<int32_t>(nf);
+                e.own_start = b.take<int32_t>(n + 1); e.nbr_start = b.take<int32_t>(n + 1);
+                e.losort = b.take<int32_t>(nf);
+                e.mstart = b.take<int32_t>(L.mstart.size()); e.members = b.take<int32_t>(L.members.size());
+                e.istart = b.take<int32_t>(L.istart.size()); e.inner = b.take<int32_t>(L.inner.size());
+                e.cstart = b.take<int32_t>(L.cstart.size()); e.cfaces = b.take<int32_t>(L.cfaces.size());
+            } else {
+                e.diag = d.pdiag; e.offd = d.poff; e.b = d.r; e.out = d.z;
+                e.own = d.own; e.nei = d.nei; e.own_start = d.own_start; e.nbr_start = d.nbr_start;
+                e.losort = d.losort;
+            }
+            if (l < nl - 1) e.agg = b.take<int32_t>(n);
+        }
+    }
     if (o.hybrid_K > 0) {
         const size_t K = (size_t)o.hybrid_K;
         size_t nC = 0;
@@ -260,8 +298,10 @@ fvm_status check_opts(const fvm_mesh *m, const fvm_case_opts *o)
         return fvm_fail(FVM_EINVAL, "case: mixed precision runs Jacobi inner solves (DIC is FP64 only)");
     if (o->precision == FVM_MIXED && (!(o->inner_rel_tol > 0.0) || !(o->inner_rel_tol < 1.0) || o->inner_max_iter < 1))
         return fvm_fail(FVM_EINVAL, "case: mixed precision needs 0 < inner_rel_tol < 1 and inner_max_iter >= 1");
-    if (o->p_ctl.precond != FVM_PC_JACOBI && o->p_ctl.precond != FVM_PC_DIC)
+    if (o->p_ctl.precond != FVM_PC_JACOBI && o->p_ctl.precond != FVM_PC_DIC && o->p_ctl.precond != FVM_PC_AMG)
         return fvm_fail(FVM_EINVAL, "case: bad preconditioner");
+    if (o->precision == FVM_MIXED && o->p_ctl.precond == FVM_PC_AMG)
+        return fvm_fail(FVM_EINVAL, "case: the AMG preconditioner is FP64 only");
     if (o->u_ctl.precond != FVM_PC_JACOBI) return fvm_fail(FVM_EINVAL, "case: momentum solver takes Jacobi only");
     if (o->p_ctl.max_iter < 1 || o->u_ctl.max_iter < 1) return fvm_fail(FVM_EINVAL, "case: max_iter must be >= 1");
     if (!(o->p_ctl.tol >= 0.0) || !(o->u_ctl.tol >= 0.0) || !(o->p_ctl.rel_tol >= 0.0) || !(o->u_ctl.rel_tol >= 0.0))
@@ -431,7 +471,8 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     c->nonorth = m->nonorth; c->has_fixed_p = m->has_fixed_p;
     c->patches = m->patches;
     Bump b{reinterpret_cast<char *>(ws)};
-    plan(*m, *o, b, c->d);
+    std::vector<AmgLevel> amg_lv;
+    plan(*m, *o, b, c->d, &amg_lv);
     auto fail = [&](fvm_status code) {
         c->poll.release();
         delete c;
@@ -468,6 +509,26 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     }
     UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s)); UPCHK(up(d.sell_mir, m->sell_mir, s));
     UPCHK(up(d.sell_fe, m->sell_fe, s)); UPCHK(up(d.sell_col, m->sell_col, s));
+    if (d.amg_nl > 0) {
+        const AmgHost &A = mesh_amg(*m);
+        if (d.amg_nc > kAmgDenseMax)
+            return fail(fvm_fail(FVM_EINVAL, "case: AMG coarsening stalled above the dense coarsest size"));
+        auto w = [](const int32_t *p) { return const_cast<int32_t *>(p); };
+        for (int l = 0; l < d.amg_nl; ++l) {
+            const AmgLevelHost &L = A.L[l];
+            const AmgLevel &e = amg_lv[l];
+            if (l > 0) {
+                UPCHK(up(w(e.own), L.own, s)); UPCHK(up(w(e.nei), L.nei, s));
+                UPCHK(up(w(e.own_start), L.own_start, s)); UPCHK(up(w(e.nbr_start), L.nbr_start, s));
+                UPCHK(up(w(e.losort), L.losort, s));
+                UPCHK(up(w(e.mstart), L.mstart, s)); UPCHK(up(w(e.members), L.members, s));
+                UPCHK(up(w(e.istart), L.istart, s)); UPCHK(up(w(e.inner), L.inner, s));
+                UPCHK(up(w(e.cstart), L.cstart, s)); UPCHK(up(w(e.cfaces), L.cfaces, s));
+            }
+            if (l < d.amg_nl - 1) UPCHK(up(w(e.agg), L.agg, s));
+        }
+        UPCHK(hipMemcpyAsync(d.amg, amg_lv.data(), sizeof(AmgLevel) * amg_lv.size(), hipMemcpyHostToDevice, s));
+    }
     HybridHost hy;
     if (d.hy_K > 0) {
         build_hybrid(*m, d.hy_K, hy);
@@ -717,22 +778,25 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
     const int first = kind == 0 ? 0 : 3, count = kind == 0 ? 3 : 1;
     const int precond = ctl_src == 2 ? ctl->precond : c0->o.p_ctl.precond;
     const int dic = kind == 1 && precond == FVM_PC_DIC;
+    const int amg = kind == 1 && precond == FVM_PC_AMG;
+    const int pc = dic ? 1 : amg ? 2 : 0;     // external preconditioner (z and rho from it)
     const bool mixed = c0->o.precision == FVM_MIXED;
     long max_iter = 0;
     for (auto *c : g.cs)
         max_iter = std::max<long>(max_iter, ctl_src == 2 ? ctl->max_iter : kind == 0 ? c->o.u_ctl.max_iter : c->o.p_ctl.max_iter);
     launch_set_ctl(bs, first, count, ctl_src, ctl ? ctl->tol : 0.0, ctl ? ctl->rel_tol : 0.0, ctl ? ctl->max_iter : 0, s);
     if (kind == 0) launch_bicg_init(bs, c0->o.u_solver == FVM_SOLVER_BICGSTAB, s);
-    else launch_pcg_init(bs, dic, s);
+    else launch_pcg_init(bs, pc, s);
     fvm_status st;
     if (!mixed) {
         if (dic) launch_dic_precond(bs, 1, s);
+        else if (amg) launch_amg_precond(bs, 1, s);
         const bool stab = kind == 0 && c0->o.u_solver == FVM_SOLVER_BICGSTAB;
-        const int gkey = stab ? 2 : kind == 0 ? 0 : (dic ? 3 : 1);
+        const int gkey = stab ? 2 : kind == 0 ? 0 : (dic ? 3 : amg ? 6 : 1);
         st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 1, gkey, [&](hipStream_t st_, long) {
             if (stab) launch_bicgstab_iter(bs, st_);
             else if (kind == 0) launch_bicg_iter(bs, st_);
-            else launch_pcg_iter(bs, dic, st_);
+            else launch_pcg_iter(bs, pc, st_);
         }, res);
         if (st != FVM_OK) return st;
     } else if (kind == 1) {
@@ -932,10 +996,12 @@ extern "C" fvm_status solve_pressure(fvm_case *c, const double *gamma, const dou
                                      const fvm_solver_ctl *ctl, void *stream, fvm_solve_info *out)
 {
     if (!c || !gamma || !rhs || !p || !ctl) return fvm_fail(FVM_EINVAL, "solve_pressure: null argument");
-    if (ctl->precond != FVM_PC_JACOBI && ctl->precond != FVM_PC_DIC)
+    if (ctl->precond != FVM_PC_JACOBI && ctl->precond != FVM_PC_DIC && ctl->precond != FVM_PC_AMG)
         return fvm_fail(FVM_EINVAL, "solve_pressure: bad preconditioner");
     if (ctl->precond == FVM_PC_DIC && !c->d.dstar)
         return fvm_fail(FVM_EINVAL, "solve_pressure: DIC needs a case created with the DIC preconditioner");
+    if (ctl->precond == FVM_PC_AMG && c->d.amg_nl < 1)
+        return fvm_fail(FVM_EINVAL, "solve_pressure: AMG needs a case created with the AMG preconditioner");
     if (ctl->max_iter < 1) return fvm_fail(FVM_EINVAL, "solve_pressure: max_iter must be >= 1");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Group g(c, s);
@@ -1005,6 +1071,8 @@ extern "C" fvm_status piso_step_batch(fvm_case *const *cases, int32_t n, int32_t
             c->o.n_non_orth_corr != a->o.n_non_orth_corr || c->o.p_ctl.precond != a->o.p_ctl.precond ||
             c->o.u_solver != a->o.u_solver)
             return fvm_fail(FVM_EINVAL, "batch: cases must share precision, correctors, preconditioner and momentum solver");
+        if (n > 1 && c->o.p_ctl.precond == FVM_PC_AMG)
+            return fvm_fail(FVM_EINVAL, "batch: AMG cases run one per call");
         for (int j = 0; j < i; ++j)
             if (cases[j] == c) return fvm_fail(FVM_EINVAL, "batch: a case appears twice");
     }

@@ -3,6 +3,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -12,6 +13,11 @@ struct fvm_mesh;
 struct HybridHost;
 // builds h from the canonical mesh (see HybridHost); K >= 1
 void build_hybrid(const fvm_mesh &m, int32_t K, HybridHost &h);
+struct AmgHost;
+// the AMG hierarchy of the mesh's cell graph, built once and cached
+const AmgHost &mesh_amg(const fvm_mesh &m);
+constexpr int kAmgCoarseMax = 128;    // coarsen while a level has more cells
+constexpr int kAmgDenseMax = 512;     // largest coarsest level (dense inverse)
 
 struct ihipStream_t;
 typedef struct ihipStream_t *hipStream_t;
@@ -35,6 +41,23 @@ struct HybridHost {
     int32_t K = 0, nC = 0;
     std::vector<int32_t> I, J, c_start, c_col, c_tr;
     std::vector<int32_t> dI, dJ, dpos, locO, locN, c_trpos;
+};
+
+// Aggregation AMG hierarchy of the cell graph (pressure preconditioner).
+// Level 0 is the mesh; level l + 1 aggregates level l: agg[l] maps its
+// cells to the next level's.  Coarse faces are the distinct aggregate
+// pairs joined by a fine face, canonical (lower, upper) and sorted.  The
+// gather lists of a coarse level name, per coarse cell, its member cells
+// (restriction, diagonal) and the fine faces inside it; per coarse face,
+// the fine faces joining its two aggregates; all in ascending fine order.
+struct AmgLevelHost {
+    int32_t n = 0, nf = 0;
+    std::vector<int32_t> own, nei, own_start, nbr_start, losort;   // levels >= 1
+    std::vector<int32_t> agg;                                      // [n], all but the last level
+    std::vector<int32_t> mstart, members, istart, inner, cstart, cfaces;   // levels >= 1
+};
+struct AmgHost {
+    std::vector<AmgLevelHost> L;
 };
 
 struct fvm_mesh {
@@ -85,6 +108,7 @@ struct fvm_mesh {
     // every cell of the slice (upper slots, explicit slices, borders).
     int32_t sell_W = 0;
     std::vector<int32_t> sell_mode, sell_off, sell_fe, sell_col, sell_mir;
+    mutable std::shared_ptr<AmgHost> amg;   // AMG hierarchy, built on first use
 };
 
 // ---------------------------------------------------------------------------
@@ -121,6 +145,15 @@ constexpr int kNumKs = 8;            // Krylov states per case
 // ---------------------------------------------------------------------------
 // Device view of one case: every pointer lies inside the caller's workspace.
 // ---------------------------------------------------------------------------
+// one level of the AMG hierarchy on the device (level 0 points at the
+// case's own topology and pressure matrix; b = the CG residual, out = z)
+struct AmgLevel {
+    int32_t n, nf;
+    const int32_t *own, *nei, *own_start, *nbr_start, *losort, *agg;
+    const int32_t *mstart, *members, *istart, *inner, *cstart, *cfaces;
+    double *diag, *offd, *x, *b, *r, *out;
+};
+
 struct DevCase {
     int32_t N, F, Fi, Fb, npatch;
     int32_t nonorth, has_fixed_p, pin_cell;
@@ -181,6 +214,12 @@ struct DevCase {
     int32_t hy_K, hy_nC;
     int32_t *hy_I, *hy_J, *hy_dpos, *hy_locO, *hy_locN, *hy_cstart, *hy_ccol, *hy_ctrpos;
     double *hy_V, *hy_Sx, *hy_Sy, *hy_Sz, *hy_w, *hy_dl, *hy_g, *hy_phi;
+    // AMG preconditioner: amg_nl levels (device descriptors), the inverse
+    // of the coarsest matrix (amg_nc x amg_nc, row-major)
+    int32_t amg_nl, amg_nc;
+    int32_t amg_n[20], amg_nf[20];               // level sizes (read by the host launcher)
+    AmgLevel *amg;
+    double *amg_cinv;
     // reductions
     double *partials;                            // [kMaxRed][red_stride]   level-1 slots
     double *partials2;                           // [kMaxRed][red_stride2]  level-2 slots
@@ -275,6 +314,10 @@ void launch_mx_inner_iter(const BatchSet &bs, int kind, hipStream_t s);
 void launch_mx_correct_resid(const BatchSet &bs, int kind, hipStream_t s);
 // mixed-precision pressure CG: FP32 recurrence with FP64 residual replacement
 void launch_operator(const BatchSet &bs, int op, const double *in, double *out, hipStream_t s);
+// AMG preconditioner of the pressure CG (single-case groups): with_setup
+// rebuilds the coarse operators and the coarsest inverse; then z = V(r) and
+// r.z -> rho, beta
+void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s);
 void launch_hybrid_geometry(const BatchSet &bs, hipStream_t s);
 void launch_rr_start(const BatchSet &bs, hipStream_t s);
 void launch_rr_iter(const BatchSet &bs, hipStream_t s);

@@ -1363,6 +1363,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_sumx(Batch bt)
 }
 
 // FP64 start: r = b - A x; normalisation; Jacobi: first rho = r.(r/diag)
+// dic: 0 Jacobi, 1 DIC, 2 AMG (the last two compute z and rho themselves)
 __global__ void __launch_bounds__(kBlock) k_pcg_init(Batch bt, int dic)
 {
     CASE_OF(bt);
@@ -1378,7 +1379,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(Batch bt, int dic)
         v[0] += fabs(ax - xb * a1) + fabs(b - xb * a1);
         v[1] += fabs(r);
         if (!dic) v[2] += r * (r / d.pdiag[i]);
-        else {
+        else if (dic == 1) {
             clear_word(d.dq, i);
             clear_word(d.yq, i);
             clear_word(d.zq, i);
@@ -2201,6 +2202,162 @@ __global__ void k_hy_spmv(Batch bt, const double *__restrict__ x, double *__rest
     y[i] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// Aggregation AMG preconditioner (pressure CG): one V-cycle per application.
+// Level l restricts to level l + 1 by summing over each aggregate, and
+// prolongs by copying an aggregate's value to its cells.  On the way down a
+// level smooths once from zero (x = w D^-1 b) and forms its residual; on the
+// way up it adds the coarse correction and smooths once more.  Both fused
+// kernels evaluate the neighbours' x on the fly from the same expression
+// that stores it, so one launch does what would otherwise take two.  The
+// coarsest level applies a dense inverse built at the start of each solve.
+// These kernels run on single-case groups, with explicit grids.
+// ---------------------------------------------------------------------------
+constexpr double kAmgOmega = 2.0 / 3.0;
+
+__global__ void __launch_bounds__(kBlock) k_amg_galerkin(const DevCase *dc, int l)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &C = d.amg[l], &F = d.amg[l - 1];
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < C.n) {
+        double a = 0.0;
+        for (int k = C.mstart[t]; k < C.mstart[t + 1]; ++k) a += F.diag[C.members[k]];
+        for (int k = C.istart[t]; k < C.istart[t + 1]; ++k) a += 2.0 * F.offd[C.inner[k]];
+        C.diag[t] = a;
+    }
+    if (t < C.nf) {
+        double a = 0.0;
+        for (int k = C.cstart[t]; k < C.cstart[t + 1]; ++k) a += F.offd[C.cfaces[k]];
+        C.offd[t] = a;
+    }
+}
+
+// inverse of the coarsest matrix by Gauss-Jordan elimination in place (the
+// matrix is symmetric positive definite: no pivoting), one block
+__global__ void __launch_bounds__(kBlock) k_amg_cinv(const DevCase *dc)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &C = d.amg[d.amg_nl - 1];
+    const int n = C.n, t = threadIdx.x;
+    double *A = d.amg_cinv;
+    __shared__ double fcol[kAmgDenseMax];
+    for (long e = t; e < (long)n * n; e += kBlock) A[e] = 0.0;
+    __syncthreads();
+    for (int i = t; i < n; i += kBlock) A[(long)i * n + i] = C.diag[i];
+    for (int f = t; f < C.nf; f += kBlock) {
+        A[(long)C.own[f] * n + C.nei[f]] = C.offd[f];
+        A[(long)C.nei[f] * n + C.own[f]] = C.offd[f];
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double piv = A[(long)k * n + k];
+        __syncthreads();
+        for (int j = t; j < n; j += kBlock) A[(long)k * n + j] = j == k ? 1.0 / piv : A[(long)k * n + j] / piv;
+        for (int i = t; i < n; i += kBlock) fcol[i] = i == k ? 0.0 : A[(long)i * n + k];
+        __syncthreads();
+        for (long e = t; e < (long)n * n; e += kBlock) {
+            const int i = (int)(e / n), j = (int)(e % n);
+            if (i == k) continue;
+            A[e] = j == k ? -fcol[i] * A[(long)k * n + k] : A[e] - fcol[i] * A[(long)k * n + j];
+        }
+        __syncthreads();
+    }
+}
+
+// x = w b / diag and r = b - A x (neighbours' x from their b and diag)
+__global__ void __launch_bounds__(kBlock) k_amg_down(const DevCase *dc, int l)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &L = d.amg[l];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= L.n) return;
+    const double bi = L.b[i], xi = kAmgOmega * bi / L.diag[i];
+    L.x[i] = xi;
+    double ax = L.diag[i] * xi;
+    for (int f = L.own_start[i]; f < L.own_start[i + 1]; ++f) {
+        const int j = L.nei[f];
+        ax += L.offd[f] * (kAmgOmega * L.b[j] / L.diag[j]);
+    }
+    for (int k = L.nbr_start[i]; k < L.nbr_start[i + 1]; ++k) {
+        const int f = L.losort[k], j = L.own[f];
+        ax += L.offd[f] * (kAmgOmega * L.b[j] / L.diag[j]);
+    }
+    L.r[i] = bi - ax;
+}
+
+// coarse right-hand side: sum of the fine residuals over each aggregate
+__global__ void __launch_bounds__(kBlock) k_amg_restrict(const DevCase *dc, int l)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &C = d.amg[l], &F = d.amg[l - 1];
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= C.n) return;
+    double a = 0.0;
+    for (int k = C.mstart[t]; k < C.mstart[t + 1]; ++k) a += F.r[C.members[k]];
+    C.b[t] = a;
+}
+
+// coarsest level: out = A^-1 b
+__global__ void __launch_bounds__(kBlock) k_amg_coarse(const DevCase *dc)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &C = d.amg[d.amg_nl - 1];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= C.n) return;
+    const double *row = d.amg_cinv + (long)i * C.n;
+    double a = 0.0;
+    for (int j = 0; j < C.n; ++j) a += row[j] * C.b[j];
+    C.out[i] = a;
+}
+
+// x' = x + P xc, out = x' + w (b - A x') / diag (neighbours' x' on the fly)
+__global__ void __launch_bounds__(kBlock) k_amg_up(const DevCase *dc, int l)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &L = d.amg[l];
+    const double *__restrict__ xc = d.amg[l + 1].out;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= L.n) return;
+    const double xi = L.x[i] + xc[L.agg[i]];
+    double ax = L.diag[i] * xi;
+    for (int f = L.own_start[i]; f < L.own_start[i + 1]; ++f) {
+        const int j = L.nei[f];
+        ax += L.offd[f] * (L.x[j] + xc[L.agg[j]]);
+    }
+    for (int k = L.nbr_start[i]; k < L.nbr_start[i + 1]; ++k) {
+        const int f = L.losort[k], j = L.own[f];
+        ax += L.offd[f] * (L.x[j] + xc[L.agg[j]]);
+    }
+    L.out[i] = xi + kAmgOmega * (L.b[i] - ax) / L.diag[i];
+}
+
+// rho = r.z after the preconditioner; beta from the previous rho
+__global__ void __launch_bounds__(kBlock) k_amg_rz(Batch bt)
+{
+    CASE_OF(bt);
+    if (d.ks[3].done) return;
+    const Range rg = block_range(d.N, K);
+    double v[1] = {0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) v[0] += d.r[i] * d.z[i];
+    __shared__ double tot[1];
+    if (reduce_last<1>(v, d, K, tot) && threadIdx.x == 0) {
+        KState &s = d.ks[3];
+        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else if (s.iters == 0) s.rho = tot[0];
+        else {
+            s.beta = tot[0] / s.rho;
+            s.rho = tot[0];
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2395,21 +2552,22 @@ void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s)
 
 void launch_dic_reset(const BatchSet &bs, hipStream_t s) { run(k_dic_reset, bs, SZ_CELL, s); }
 
-void launch_pcg_iter(const BatchSet &bs, int dic, hipStream_t s)
+void launch_pcg_iter(const BatchSet &bs, int pc, hipStream_t s)
 {
     {
         Prof p("pcg_dir", s);
-        run(k_cg_dir<double, 4>, bs, SZ_CELL4, s, dic);
+        run(k_cg_dir<double, 4>, bs, SZ_CELL4, s, pc != 0 ? 1 : 0);
     }
     {
         Prof p("pcg_spmv", s);
-        run(k_cg_spmv<double, 1>, bs, SZ_CELL, s, dic);
+        run(k_cg_spmv<double, 1>, bs, SZ_CELL, s, pc != 0 ? 1 : 0);
     }
     {
         Prof p("pcg_update", s);
-        run(k_cg_update<2>, bs, SZ_CELL2, s, dic);
+        run(k_cg_update<2>, bs, SZ_CELL2, s, pc != 0 ? 1 : 0);
     }
-    if (dic) launch_dic_precond(bs, 0, s);
+    if (pc == 1) launch_dic_precond(bs, 0, s);
+    else if (pc == 2) launch_amg_precond(bs, 0, s);
 }
 
 void launch_mx_cvt(const BatchSet &bs, int kind, hipStream_t s) { run(k_mx_cvt, bs, SZ_MAXNF, s, kind); }
@@ -2528,3 +2686,25 @@ void launch_operator(const BatchSet &bs, int op, const double *in, double *out, 
 }
 
 void launch_hybrid_geometry(const BatchSet &bs, hipStream_t s) { run(k_hy_geom, bs, SZ_FACEI, s); }
+
+void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
+{
+    const DevCase &h = *bs.host[0];
+    const DevCase *dev = h.self;
+    const int nl = h.amg_nl;
+    auto grid = [](int n) { return dim3((unsigned)((n + kBlock - 1) / kBlock > 0 ? (n + kBlock - 1) / kBlock : 1)); };
+    if (with_setup) {
+        Prof p("amg_setup", s);
+        for (int l = 1; l < nl; ++l)
+            hipLaunchKernelGGL(k_amg_galerkin, grid(std::max(h.amg_n[l], h.amg_nf[l])), dim3(kBlock), 0, s, dev, l);
+        hipLaunchKernelGGL(k_amg_cinv, dim3(1), dim3(kBlock), 0, s, dev);
+    }
+    Prof p("amg_vcycle", s);
+    for (int l = 0; l < nl - 1; ++l) {
+        hipLaunchKernelGGL(k_amg_down, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
+        hipLaunchKernelGGL(k_amg_restrict, grid(h.amg_n[l + 1]), dim3(kBlock), 0, s, dev, l + 1);
+    }
+    hipLaunchKernelGGL(k_amg_coarse, grid(h.amg_n[nl - 1]), dim3(kBlock), 0, s, dev);
+    for (int l = nl - 2; l >= 0; --l) hipLaunchKernelGGL(k_amg_up, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
+    run(k_amg_rz, bs, SZ_CELL, s);
+}

@@ -196,6 +196,134 @@ void build_hybrid(const fvm_mesh &m, int32_t K, HybridHost &h)
     }
 }
 
+// AMG hierarchy.  Aggregation of a level in cell index order: a cell none
+// of whose neighbours is aggregated yet starts an aggregate with all of them;
+// every cell left over joins the aggregate of its lowest-index neighbour
+// aggregated that way (a cell without neighbours is its own aggregate).
+// Levels are added while a level has more than kAmgCoarseMax cells and the
+// aggregation shrinks it by at least 10%.
+namespace {
+
+// neighbour-side faces of cell i in losort order, then owned faces: the
+// neighbours in ascending order
+template <class Fn>
+void for_neighbours(const std::vector<int32_t> &own, const std::vector<int32_t> &nei,
+                    const std::vector<int32_t> &own_start, const std::vector<int32_t> &nbr_start,
+                    const std::vector<int32_t> &losort, int32_t i, Fn fn)
+{
+    for (int32_t k = nbr_start[i]; k < nbr_start[i + 1]; ++k) fn(own[losort[k]]);
+    for (int32_t f = own_start[i]; f < own_start[i + 1]; ++f) fn(nei[f]);
+}
+
+void face_ranges(int32_t n, const std::vector<int32_t> &own, const std::vector<int32_t> &nei,
+                 std::vector<int32_t> &own_start, std::vector<int32_t> &nbr_start, std::vector<int32_t> &losort)
+{
+    const int32_t nf = (int32_t)nei.size();
+    own_start.assign((size_t)n + 1, 0);
+    nbr_start.assign((size_t)n + 1, 0);
+    for (int32_t f = 0; f < nf; ++f) { own_start[own[f] + 1]++; nbr_start[nei[f] + 1]++; }
+    for (int32_t i = 0; i < n; ++i) { own_start[i + 1] += own_start[i]; nbr_start[i + 1] += nbr_start[i]; }
+    losort.assign(nf, 0);
+    std::vector<int32_t> fill(nbr_start.begin(), nbr_start.end() - 1);
+    for (int32_t f = 0; f < nf; ++f) losort[fill[nei[f]]++] = f;   // faces ascending: owners ascending per cell
+}
+
+}  // namespace
+
+const AmgHost &mesh_amg(const fvm_mesh &m)
+{
+    if (m.amg) return *m.amg;
+    auto h = std::make_shared<AmgHost>();
+    h->L.emplace_back();
+    {
+        AmgLevelHost &L0 = h->L[0];
+        L0.n = m.N;
+        L0.nf = m.Fi;
+    }
+    // level 0 topology is the mesh's
+    const std::vector<int32_t> own0(m.own.begin(), m.own.begin() + m.Fi);
+    const std::vector<int32_t> *own = &own0, *nei = &m.nei, *os = &m.own_start, *ns = &m.nbr_start, *lo = &m.losort;
+    while (h->L.back().n > kAmgCoarseMax && h->L.size() < 20) {
+        const int32_t l = (int32_t)h->L.size() - 1;
+        const int32_t n = h->L[l].n;
+        std::vector<int32_t> agg(n, -1);
+        std::vector<char> first(n, 0);
+        int32_t na = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            if (agg[i] != -1) continue;
+            bool free_all = true;
+            for_neighbours(*own, *nei, *os, *ns, *lo, i, [&](int32_t j) { free_all = free_all && agg[j] == -1; });
+            if (!free_all) continue;
+            agg[i] = na;
+            first[i] = 1;
+            for_neighbours(*own, *nei, *os, *ns, *lo, i, [&](int32_t j) { agg[j] = na; first[j] = 1; });
+            ++na;
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            if (agg[i] != -1) continue;
+            int32_t to = -1;
+            for_neighbours(*own, *nei, *os, *ns, *lo, i, [&](int32_t j) { if (to < 0 && first[j]) to = agg[j]; });
+            agg[i] = to >= 0 ? to : na++;
+        }
+        if (na > 0.9 * n) break;
+        // coarse faces: distinct aggregate pairs, sorted
+        const int32_t nf = (int32_t)nei->size();
+        std::vector<int64_t> key;
+        key.reserve(nf);
+        for (int32_t f = 0; f < nf; ++f) {
+            const int32_t A = agg[(*own)[f]], B = agg[(*nei)[f]];
+            if (A != B) key.push_back((int64_t)std::min(A, B) * na + std::max(A, B));
+        }
+        std::sort(key.begin(), key.end());
+        key.erase(std::unique(key.begin(), key.end()), key.end());
+        AmgLevelHost C;
+        C.n = na;
+        C.nf = (int32_t)key.size();
+        C.own.resize(C.nf);
+        C.nei.resize(C.nf);
+        for (int32_t F = 0; F < C.nf; ++F) { C.own[F] = (int32_t)(key[F] / na); C.nei[F] = (int32_t)(key[F] % na); }
+        face_ranges(C.n, C.own, C.nei, C.own_start, C.nbr_start, C.losort);
+        // gather lists (ascending fine index)
+        C.mstart.assign((size_t)na + 1, 0);
+        for (int32_t i = 0; i < n; ++i) C.mstart[agg[i] + 1]++;
+        for (int32_t a = 0; a < na; ++a) C.mstart[a + 1] += C.mstart[a];
+        C.members.resize(n);
+        {
+            std::vector<int32_t> fill(C.mstart.begin(), C.mstart.end() - 1);
+            for (int32_t i = 0; i < n; ++i) C.members[fill[agg[i]]++] = i;
+        }
+        C.istart.assign((size_t)na + 1, 0);
+        C.cstart.assign((size_t)C.nf + 1, 0);
+        std::vector<int32_t> cf(nf, -1);
+        for (int32_t f = 0; f < nf; ++f) {
+            const int32_t A = agg[(*own)[f]], B = agg[(*nei)[f]];
+            if (A == B) C.istart[A + 1]++;
+            else {
+                const int64_t k = (int64_t)std::min(A, B) * na + std::max(A, B);
+                cf[f] = (int32_t)(std::lower_bound(key.begin(), key.end(), k) - key.begin());
+                C.cstart[cf[f] + 1]++;
+            }
+        }
+        for (int32_t a = 0; a < na; ++a) C.istart[a + 1] += C.istart[a];
+        for (int32_t F = 0; F < C.nf; ++F) C.cstart[F + 1] += C.cstart[F];
+        C.inner.resize(C.istart[na]);
+        C.cfaces.resize(C.cstart[C.nf]);
+        {
+            std::vector<int32_t> fi(C.istart.begin(), C.istart.end() - 1), fc(C.cstart.begin(), C.cstart.end() - 1);
+            for (int32_t f = 0; f < nf; ++f) {
+                if (cf[f] < 0) C.inner[fi[agg[(*own)[f]]]++] = f;
+                else C.cfaces[fc[cf[f]]++] = f;
+            }
+        }
+        h->L[l].agg = std::move(agg);
+        h->L.push_back(std::move(C));
+        const AmgLevelHost &N = h->L.back();
+        own = &N.own; nei = &N.nei; os = &N.own_start; ns = &N.nbr_start; lo = &N.losort;
+    }
+    m.amg = h;
+    return *h;
+}
+
 namespace {
 
 fvm_status build(const fvm_mesh_desc *d, fvm_mesh *m)
@@ -394,6 +522,32 @@ extern "C" fvm_status fvm_mesh_create(const fvm_mesh_desc *desc, fvm_mesh **out)
 }
 
 extern "C" void fvm_mesh_destroy(fvm_mesh *mesh) { delete mesh; }
+
+extern "C" fvm_status fvm_mesh_amg(const fvm_mesh *m, int32_t level, int32_t *n_levels, int32_t *n_cells,
+                                   int32_t *n_faces, int32_t *own, int32_t *nei, int32_t *agg)
+{
+    if (!m) return fvm_fail(FVM_EINVAL, "amg: null mesh");
+    try {
+        const AmgHost &h = mesh_amg(*m);
+        const int32_t nl = (int32_t)h.L.size();
+        if (n_levels) *n_levels = nl;
+        if (level < 0 || level >= nl) return fvm_fail(FVM_EINVAL, "amg: level out of range");
+        const AmgLevelHost &L = h.L[level];
+        if (n_cells) *n_cells = L.n;
+        if (n_faces) *n_faces = L.nf;
+        if (level == 0) {
+            if (own) std::copy(m->own.begin(), m->own.begin() + m->Fi, own);
+            if (nei) std::copy(m->nei.begin(), m->nei.end(), nei);
+        } else {
+            if (own) std::copy(L.own.begin(), L.own.end(), own);
+            if (nei) std::copy(L.nei.begin(), L.nei.end(), nei);
+        }
+        if (agg && level < nl - 1) std::copy(L.agg.begin(), L.agg.end(), agg);
+    } catch (const std::bad_alloc &) {
+        return fvm_fail(FVM_ENOMEM, "amg: out of host memory");
+    }
+    return FVM_OK;
+}
 
 extern "C" fvm_status fvm_mesh_hybrid(const fvm_mesh *m, int32_t K, int32_t *n_crs, int32_t *I, int32_t *J,
                                       int32_t *Q, int32_t *c_start, int32_t *c_col, int32_t *c_tr)

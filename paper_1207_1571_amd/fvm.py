@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfvm.so")
 
 FVM_OK, FVM_WARN_MAXITER, FVM_EINVAL, FVM_ENOMEM, FVM_ENUMERIC, FVM_EDEVICE = 0, 1, -1, -2, -3, -4
 BC_FIXED, BC_ZERO_GRAD, BC_EMPTY = 0, 1, 2
-PC_JACOBI, PC_DIC = 0, 1
+PC_JACOBI, PC_DIC, PC_AMG = 0, 1, 2
 # fvm_case_operator: face-major layout, then the paper's hybrid layout
 OP_GRAD, OP_DIV, OP_LAP, OP_SPMV = 0, 1, 2, 3
 OP_HY_GRAD, OP_HY_DIV, OP_HY_LAP, OP_HY_SPMV, OP_HY_STMVP, OP_HY_SETMAT = 4, 5, 6, 7, 8, 9
@@ -80,7 +80,7 @@ _lib = None
 EXPORTS = ("fvm_mesh_create", "fvm_mesh_destroy", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
            "fvm_case_destroy", "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
            "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read",
-           "fvm_last_error", "fvm_mesh_hybrid", "fvm_case_operator")
+           "fvm_last_error", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg")
 
 
 def lib():
@@ -115,10 +115,11 @@ def lib():
         L.fvm_last_error.restype = ct.c_char_p
         L.fvm_mesh_hybrid.argtypes = [vp, ct.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, i32p]
         L.fvm_case_operator.argtypes = [vp, ct.c_int32, vp, vp, vp]
+        L.fvm_mesh_amg.argtypes = [vp, ct.c_int32, i32p, i32p, i32p, i32p, i32p, i32p]
         for name in ("fvm_mesh_create", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
                      "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
                      "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable",
-                     "fvm_profile_read", "fvm_mesh_hybrid", "fvm_case_operator"):
+                     "fvm_profile_read", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg"):
             getattr(L, name).restype = ct.c_int32
         _lib = L
     return _lib
@@ -262,6 +263,24 @@ class Case:
         st = _check(lib().solve_pressure(self.handle, _dptr(gamma), _dptr(rhs), _dptr(p), ct.byref(ctl),
                                          ct.c_void_p(_stream_ptr(self.stream)), ct.byref(info)))
         return st, info.as_dict()
+
+
+def mesh_amg(mesh: Mesh):
+    """fvm_mesh_amg: the AMG hierarchy, one dict per level (n, own, nei, agg)."""
+    import numpy as np
+    nl = ct.c_int32()
+    _check(lib().fvm_mesh_amg(mesh.handle, 0, ct.byref(nl), None, None, None, None, None))
+    out = []
+    for l in range(nl.value):
+        n, nf = ct.c_int32(), ct.c_int32()
+        _check(lib().fvm_mesh_amg(mesh.handle, l, None, ct.byref(n), ct.byref(nf), None, None, None))
+        own, nei = np.empty(max(nf.value, 1), np.int32), np.empty(max(nf.value, 1), np.int32)
+        agg = np.empty(max(n.value, 1), np.int32)
+        last = l == nl.value - 1
+        _check(lib().fvm_mesh_amg(mesh.handle, l, None, None, None, own.ctypes.data_as(i32p), nei.ctypes.data_as(i32p),
+                                  None if last else agg.ctypes.data_as(i32p)))
+        out.append(dict(n=n.value, own=own[:nf.value], nei=nei[:nf.value], agg=None if last else agg[:n.value]))
+    return out
 
 
 def mesh_hybrid(mesh: Mesh, K: int):

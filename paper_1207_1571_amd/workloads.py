@@ -21,7 +21,7 @@ import numpy as np
 from . import meshgen as mg
 
 FIXED, ZERO_GRAD, EMPTY = 0, 1, 2
-PC_JACOBI, PC_DIC = 0, 1
+PC_JACOBI, PC_DIC, PC_AMG = 0, 1, 2
 FP64, MIXED = 0, 1
 CONV_LINEAR, CONV_UPWIND = 0, 1
 SOLVER_BICG, SOLVER_BICGSTAB = 0, 1   # momentum solver

@@ -120,3 +120,24 @@ def test_pcg_solution_and_fewer_iterations_than_jacobi():
     assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
     xj, ij = orc.pcg(own, nei, diag, offd, b, np.zeros(m.n_cells), 1e-11)
     assert info["iters"] < 0.5 * ij["iters"], (info["iters"], ij["iters"])
+
+
+@pytest.mark.parametrize("shape,perm", [((9, 8, 7), None), ((10, 9, 1), 3), ((14, 13, 12), 5), ((30, 30, 30), None)])
+def test_library_hierarchy_equals_oracle(shape, perm):
+    """fvm_mesh_amg: the library's levels (sizes, coarse faces, aggregation)
+    equal the oracle's exactly."""
+    import os
+    from paper_1207_1571_amd import fvm
+    if not os.path.exists(fvm.LIB_PATH):
+        pytest.skip("libfvm.so not built")
+    case = wl.cavity(shape, Re=10.0, dt=0.01, perm_seed=perm)
+    m = case.mesh
+    lm = fvm.Mesh(m, case.bcs)
+    lib_levels = fvm.mesh_amg(lm)
+    ora = amg.build_hierarchy(m.n_cells, m.owner[:m.n_internal], m.neighbour, coarse_max=128)
+    assert [L["n"] for L in lib_levels] == [L["n"] for L in ora]
+    for l, (a, b) in enumerate(zip(lib_levels, ora)):
+        if l > 0:
+            assert np.array_equal(a["own"], b["own"]) and np.array_equal(a["nei"], b["nei"])
+        if b["agg"] is not None:
+            assert np.array_equal(a["agg"], b["agg"]), l
