@@ -2338,6 +2338,46 @@ __global__ void __launch_bounds__(kBlock) k_amg_up(const DevCase *dc, int l)
     L.out[i] = xi + kAmgOmega * (L.b[i] - ax) / L.diag[i];
 }
 
+// rho/beta update from r.z (the value every block has summed)
+__device__ __forceinline__ void amg_rho(KState &s, double rz)
+{
+    if (!(rz > 0.0) || !isfinite(rz)) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+    else if (s.iters == 0) s.rho = rz;
+    else {
+        s.beta = rz / s.rho;
+        s.rho = rz;
+    }
+}
+
+// the finest level's way up fused with r.z (z = its output, r = its b)
+__global__ void __launch_bounds__(kBlock) k_amg_up0(Batch bt)
+{
+    CASE_OF(bt);
+    if (d.ks[3].done) return;
+    const AmgLevel &L = d.amg[0];
+    const double *__restrict__ xc = d.amg[1].out;
+    const Range rg = block_range(d.N, K);
+    double v[1] = {0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const double xi = L.x[i] + xc[L.agg[i]];
+        double ax = L.diag[i] * xi;
+        for (int f = L.own_start[i]; f < L.own_start[i + 1]; ++f) {
+            const int j = L.nei[f];
+            ax += L.offd[f] * (L.x[j] + xc[L.agg[j]]);
+        }
+        for (int k = L.nbr_start[i]; k < L.nbr_start[i + 1]; ++k) {
+            const int f = L.losort[k], j = L.own[f];
+            ax += L.offd[f] * (L.x[j] + xc[L.agg[j]]);
+        }
+        const double bi = L.b[i];
+        const double z = xi + kAmgOmega * (bi - ax) / L.diag[i];
+        L.out[i] = z;
+        v[0] += bi * z;
+    }
+    __shared__ double tot[1];
+    if (reduce_last<1>(v, d, K, tot) && threadIdx.x == 0) amg_rho(d.ks[3], tot[0]);
+}
+
 // rho = r.z after the preconditioner; beta from the previous rho
 __global__ void __launch_bounds__(kBlock) k_amg_rz(Batch bt)
 {
@@ -2347,15 +2387,7 @@ __global__ void __launch_bounds__(kBlock) k_amg_rz(Batch bt)
     double v[1] = {0.0};
     for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) v[0] += d.r[i] * d.z[i];
     __shared__ double tot[1];
-    if (reduce_last<1>(v, d, K, tot) && threadIdx.x == 0) {
-        KState &s = d.ks[3];
-        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
-        else if (s.iters == 0) s.rho = tot[0];
-        else {
-            s.beta = tot[0] / s.rho;
-            s.rho = tot[0];
-        }
-    }
+    if (reduce_last<1>(v, d, K, tot) && threadIdx.x == 0) amg_rho(d.ks[3], tot[0]);
 }
 
 }  // namespace
@@ -2705,6 +2737,7 @@ void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
         hipLaunchKernelGGL(k_amg_restrict, grid(h.amg_n[l + 1]), dim3(kBlock), 0, s, dev, l + 1);
     }
     hipLaunchKernelGGL(k_amg_coarse, grid(h.amg_n[nl - 1]), dim3(kBlock), 0, s, dev);
-    for (int l = nl - 2; l >= 0; --l) hipLaunchKernelGGL(k_amg_up, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
-    run(k_amg_rz, bs, SZ_CELL, s);
+    for (int l = nl - 2; l >= 1; --l) hipLaunchKernelGGL(k_amg_up, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
+    if (nl > 1) run(k_amg_up0, bs, SZ_CELL, s);
+    else run(k_amg_rz, bs, SZ_CELL, s);
 }
