@@ -2338,6 +2338,80 @@ __global__ void __launch_bounds__(kBlock) k_amg_up(const DevCase *dc, int l)
     L.out[i] = xi + kAmgOmega * (L.b[i] - ax) / L.diag[i];
 }
 
+// Small coarse levels: a thread per row would walk its faces one dependent
+// load after another with few waves to hide the latency.  There a wave
+// takes a row, its lanes split the row's faces (or the aggregate's members)
+// and a fixed shuffle tree sums them.  Larger levels keep a thread per row
+// (a wave per row would leave most lanes idle).
+constexpr int kAmgWaveRows = 32768;   // levels with at most this many rows
+constexpr int kRowsPerBlock = kBlock / 64;
+
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_amg_down_w(const DevCase *dc, int l)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &L = d.amg[l];
+    const int i = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= L.n) return;   // the whole wave
+    const int o0 = L.own_start[i], no = L.own_start[i + 1] - o0;
+    const int n0 = L.nbr_start[i], nn = L.nbr_start[i + 1] - n0;
+    double acc = 0.0;
+    for (int t = lane; t < no + nn; t += 64) {
+        const int f = t < no ? o0 + t : L.losort[n0 + t - no];
+        const int j = t < no ? L.nei[f] : L.own[f];
+        acc += L.offd[f] * (kAmgOmega * L.b[j] / L.diag[j]);
+    }
+    acc = wave_sum64(acc);
+    if (lane == 0) {
+        const double bi = L.b[i], xi = kAmgOmega * bi / L.diag[i];
+        L.x[i] = xi;
+        L.r[i] = bi - (L.diag[i] * xi + acc);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_amg_restrict_w(const DevCase *dc, int l)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &C = d.amg[l], &F = d.amg[l - 1];
+    const int t = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (t >= C.n) return;
+    double a = 0.0;
+    for (int k = C.mstart[t] + lane; k < C.mstart[t + 1]; k += 64) a += F.r[C.members[k]];
+    a = wave_sum64(a);
+    if (lane == 0) C.b[t] = a;
+}
+
+__global__ void __launch_bounds__(kBlock) k_amg_up_w(const DevCase *dc, int l)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    const AmgLevel &L = d.amg[l];
+    const double *__restrict__ xc = d.amg[l + 1].out;
+    const int i = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= L.n) return;
+    const int o0 = L.own_start[i], no = L.own_start[i + 1] - o0;
+    const int n0 = L.nbr_start[i], nn = L.nbr_start[i + 1] - n0;
+    double acc = 0.0;
+    for (int t = lane; t < no + nn; t += 64) {
+        const int f = t < no ? o0 + t : L.losort[n0 + t - no];
+        const int j = t < no ? L.nei[f] : L.own[f];
+        acc += L.offd[f] * (L.x[j] + xc[L.agg[j]]);
+    }
+    acc = wave_sum64(acc);
+    if (lane == 0) {
+        const double xi = L.x[i] + xc[L.agg[i]];
+        L.out[i] = xi + kAmgOmega * (L.b[i] - (L.diag[i] * xi + acc)) / L.diag[i];
+    }
+}
+
 // rho/beta update from r.z (the value every block has summed)
 __device__ __forceinline__ void amg_rho(KState &s, double rz)
 {
@@ -2349,7 +2423,8 @@ __device__ __forceinline__ void amg_rho(KState &s, double rz)
     }
 }
 
-// the finest level's way up fused with r.z (z = its output, r = its b)
+// the finest level's way up, x' = x + P xc, z = x' + w (b - A x') / diag
+// (neighbours' x' on the fly), fused with r.z (r = its b)
 __global__ void __launch_bounds__(kBlock) k_amg_up0(Batch bt)
 {
     CASE_OF(bt);
@@ -2732,12 +2807,21 @@ void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
         hipLaunchKernelGGL(k_amg_cinv, dim3(1), dim3(kBlock), 0, s, dev);
     }
     Prof p("amg_vcycle", s);
+    // a wave per row on the coarse levels (level 0 keeps a thread per row)
+    auto wgrid = [](int n) { return dim3((unsigned)std::max(1, (n + kRowsPerBlock - 1) / kRowsPerBlock)); };
     for (int l = 0; l < nl - 1; ++l) {
-        hipLaunchKernelGGL(k_amg_down, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
-        hipLaunchKernelGGL(k_amg_restrict, grid(h.amg_n[l + 1]), dim3(kBlock), 0, s, dev, l + 1);
+        if (l == 0 || h.amg_n[l] > kAmgWaveRows)
+            hipLaunchKernelGGL(k_amg_down, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
+        else hipLaunchKernelGGL(k_amg_down_w, wgrid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
+        if (h.amg_n[l + 1] > kAmgWaveRows)
+            hipLaunchKernelGGL(k_amg_restrict, grid(h.amg_n[l + 1]), dim3(kBlock), 0, s, dev, l + 1);
+        else hipLaunchKernelGGL(k_amg_restrict_w, wgrid(h.amg_n[l + 1]), dim3(kBlock), 0, s, dev, l + 1);
     }
     hipLaunchKernelGGL(k_amg_coarse, grid(h.amg_n[nl - 1]), dim3(kBlock), 0, s, dev);
-    for (int l = nl - 2; l >= 1; --l) hipLaunchKernelGGL(k_amg_up, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
+    for (int l = nl - 2; l >= 1; --l) {
+        if (h.amg_n[l] > kAmgWaveRows) hipLaunchKernelGGL(k_amg_up, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
+        else hipLaunchKernelGGL(k_amg_up_w, wgrid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
+    }
     if (nl > 1) run(k_amg_up0, bs, SZ_CELL, s);
     else run(k_amg_rz, bs, SZ_CELL, s);
 }
