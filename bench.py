@@ -168,8 +168,10 @@ def cav200_section(fvm, wl, steps, log, profile_steps=2):
     log(f"cav200 mesh: {N} cells in {time.perf_counter() - t:.1f}s")
     res = {}
     fields = {}
-    for name, prec in (("fp64", wl.FP64), ("mixed", wl.MIXED)):
+    for name, prec in (("fp64", wl.FP64), ("mixed", wl.MIXED), ("amg_fp64", wl.FP64)):
         sp = spec.with_(precision=prec)
+        if name == "amg_fp64":
+            sp = sp.with_(p_ctl=wl.SolverCtl(sp.p_ctl.tol, sp.p_ctl.rel_tol, sp.p_ctl.max_iter, wl.PC_AMG))
         c = fvm.Case(sp, mesh=mesh)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -201,8 +203,11 @@ def cav200_section(fvm, wl, steps, log, profile_steps=2):
             f"CG iteration {res[name]['cg_iter_GBps']} GB/s")
     rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
     res["mixed_vs_fp64_relL2"] = dict(U=rel(fields["mixed"][0], fields["fp64"][0]), p=rel(fields["mixed"][1], fields["fp64"][1]))
+    res["amg_vs_fp64_relL2"] = dict(U=rel(fields["amg_fp64"][0], fields["fp64"][0]),
+                                    p=rel(fields["amg_fp64"][1], fields["fp64"][1]))
     res["workload"] = (f"cav200: 3-D lid-driven cavity 200^3 hex cells, lexicographic, Re=1000, PISO dt=0.001, "
-                       f"{steps} steps, PCG-Jacobi / PBiCG-Jacobi tol 1e-6; mixed = FP32 inner (eta 1e-3) + FP64 refinement")
+                       f"{steps} steps, PCG-Jacobi / PBiCG-Jacobi tol 1e-6; mixed = FP32 inner (eta 1e-3) + FP64 "
+                       f"refinement; amg_fp64 = FP64 with the AMG V-cycle preconditioning the pressure CG")
     return res
 
 
