@@ -2207,10 +2207,12 @@ __global__ void k_hy_spmv(Batch bt, const double *__restrict__ x, double *__rest
 // Level l restricts to level l + 1 by summing over each aggregate, and
 // prolongs by copying an aggregate's value to its cells.  On the way down a
 // level smooths once from zero (x = w D^-1 b) and forms its residual; on the
-// way up it adds the coarse correction and smooths once more.  Both fused
-// kernels evaluate the neighbours' x on the fly from the same expression
-// that stores it, so one launch does what would otherwise take two.  The
-// coarsest level applies a dense inverse built at the start of each solve.
+// way up it adds the coarse correction and smooths once more.  On the
+// coarse levels both steps are single fused kernels that evaluate the
+// neighbours' x on the fly from the same expression that stores it; the
+// finest level writes x first and then runs the solver's sliced-ELL SpMV
+// row code (coalesced, mirrored lower slots).  The coarsest level applies a
+// dense inverse built at the start of each solve.
 // These kernels run on single-case groups, with explicit grids.
 // ---------------------------------------------------------------------------
 constexpr double kAmgOmega = 2.0 / 3.0;
@@ -2423,35 +2425,47 @@ __device__ __forceinline__ void amg_rho(KState &s, double rz)
     }
 }
 
-// the finest level's way up, x' = x + P xc, z = x' + w (b - A x') / diag
-// (neighbours' x' on the fly), fused with r.z (r = its b)
-__global__ void __launch_bounds__(kBlock) k_amg_up0(Batch bt)
+// The finest level through the sliced-ELL copy of the pressure matrix (the
+// solver's SpMV row code: coalesced slot streams, mirrored lower slots):
+// the smoothed or corrected x is written out first, then one pass forms
+// the residual or the second smoothing step.
+__global__ void __launch_bounds__(kBlock) k_amg_x0(Batch bt, int up)
 {
     CASE_OF(bt);
     if (d.ks[3].done) return;
     const AmgLevel &L = d.amg[0];
     const double *__restrict__ xc = d.amg[1].out;
     const Range rg = block_range(d.N, K);
-    double v[1] = {0.0};
-    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
-        const double xi = L.x[i] + xc[L.agg[i]];
-        double ax = L.diag[i] * xi;
-        for (int f = L.own_start[i]; f < L.own_start[i + 1]; ++f) {
-            const int j = L.nei[f];
-            ax += L.offd[f] * (L.x[j] + xc[L.agg[j]]);
-        }
-        for (int k = L.nbr_start[i]; k < L.nbr_start[i + 1]; ++k) {
-            const int f = L.losort[k], j = L.own[f];
-            ax += L.offd[f] * (L.x[j] + xc[L.agg[j]]);
-        }
-        const double bi = L.b[i];
-        const double z = xi + kAmgOmega * (bi - ax) / L.diag[i];
-        L.out[i] = z;
-        v[0] += bi * z;
-    }
-    __shared__ double tot[1];
-    if (reduce_last<1>(v, d, K, tot) && threadIdx.x == 0) amg_rho(d.ks[3], tot[0]);
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock)
+        L.x[i] = up ? L.x[i] + xc[L.agg[i]] : kAmgOmega * L.b[i] / L.diag[i];
 }
+
+// down: r = b - A x; up: z = x + w (b - A x) / diag, with r.z
+__global__ void __launch_bounds__(kBlock) k_amg_sell(Batch bt, int up)
+{
+    CASE_OF(bt);
+    if (d.ks[3].done) return;
+    const AmgLevel &L = d.amg[0];
+    const CGArr<double> v{d.pdiag, d.poff, nullptr, d.sell_val, nullptr, nullptr, L.x, L.r, nullptr, nullptr};
+    const Range rg = block_range(d.N, K);
+    double acc[1] = {0.0};
+    for (int base = rg.beg; base < rg.end; base += kBlock) {
+        const int i = base + threadIdx.x;
+        if (i >= rg.end) continue;
+        (void)spmv_cell<double>(d, v, base / kBlock, i);   // L.r[i] = (A x)_i
+        const double bi = L.b[i];
+        if (!up) L.r[i] = bi - L.r[i];
+        else {
+            const double z = L.x[i] + kAmgOmega * (bi - L.r[i]) / L.diag[i];
+            L.out[i] = z;
+            acc[0] += bi * z;
+        }
+    }
+    if (!up) return;
+    __shared__ double tot[1];
+    if (reduce_last<1>(acc, d, K, tot) && threadIdx.x == 0) amg_rho(d.ks[3], tot[0]);
+}
+
 
 // rho = r.z after the preconditioner; beta from the previous rho
 __global__ void __launch_bounds__(kBlock) k_amg_rz(Batch bt)
@@ -2810,7 +2824,10 @@ void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
     // a wave per row on the coarse levels (level 0 keeps a thread per row)
     auto wgrid = [](int n) { return dim3((unsigned)std::max(1, (n + kRowsPerBlock - 1) / kRowsPerBlock)); };
     for (int l = 0; l < nl - 1; ++l) {
-        if (l == 0 || h.amg_n[l] > kAmgWaveRows)
+        if (l == 0) {
+            run(k_amg_x0, bs, SZ_CELL, s, 0);
+            run(k_amg_sell, bs, SZ_CELL, s, 0);
+        } else if (h.amg_n[l] > kAmgWaveRows)
             hipLaunchKernelGGL(k_amg_down, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
         else hipLaunchKernelGGL(k_amg_down_w, wgrid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
         if (h.amg_n[l + 1] > kAmgWaveRows)
@@ -2822,6 +2839,8 @@ void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
         if (h.amg_n[l] > kAmgWaveRows) hipLaunchKernelGGL(k_amg_up, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
         else hipLaunchKernelGGL(k_amg_up_w, wgrid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
     }
-    if (nl > 1) run(k_amg_up0, bs, SZ_CELL, s);
-    else run(k_amg_rz, bs, SZ_CELL, s);
+    if (nl > 1) {
+        run(k_amg_x0, bs, SZ_CELL, s, 1);
+        run(k_amg_sell, bs, SZ_CELL, s, 1);
+    } else run(k_amg_rz, bs, SZ_CELL, s);
 }
