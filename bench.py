@@ -23,7 +23,16 @@ Also reported on the same JSON line:
   kernels       per-class device time, launches (all and working), mean time
                 per launch and per working launch, algorithmic GB/s;
   cpu_baseline  the FP64 oracle on the host on a bounded sample (the first
-                PISO step of the same case), in cell-updates/s.
+                PISO step of the same case), in cell-updates/s;
+  other_preconditioners  the same case with Jacobi and with the AMG V-cycle
+                in place of DIC (time per step, CG iterations per step);
+  cav200        the 200^3 cavity (Jacobi) in FP64, in mixed precision and in
+                FP64 with AMG: time per step, iterations, per-kernel GB/s;
+  serving       continuous batching of a reduced request stream: p50/p99;
+  tp1m          the transient pipe with its time-dependent inlet;
+  layouts       the assembly operators one at a time in the solver's layout
+                and in the paper's hybrid ELL + J + CRS layout, normalised by
+                each layout's SMVP as in the paper's Table 3.
 """
 from __future__ import annotations
 
