@@ -81,7 +81,23 @@ class GpuBackend:
             return self.fvm.Case(spec, device=self.device, stream=self.stream, mesh=mesh)
 
     def advance(self, cases: Sequence, n_steps: int) -> List[dict]:
-        st, infos = self.fvm.piso_batch(list(cases), n_steps, stream=self.stream, raise_on_case_failure=False)
+        """piso_step_batch over sub-batches of cases that may share launches
+        (same precision, correctors, pressure preconditioner and momentum
+        solver; AMG cases one at a time)."""
+        fvm = self.fvm
+        subs: Dict[tuple, List[int]] = {}
+        for k, c in enumerate(cases):
+            o = c.opts
+            key = (o.precision, o.n_corr, o.n_non_orth_corr, o.p_ctl.precond, o.u_solver)
+            if o.p_ctl.precond == fvm.PC_AMG:
+                key = key + (k,)
+            subs.setdefault(key, []).append(k)
+        infos: List[dict] = [None] * len(cases)
+        for idx in subs.values():
+            st, part = fvm.piso_batch([cases[k] for k in idx], n_steps, stream=self.stream,
+                                      raise_on_case_failure=False)
+            for k, info in zip(idx, part):
+                infos[k] = info
         return infos
 
     def finish(self, case):

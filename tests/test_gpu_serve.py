@@ -118,3 +118,32 @@ def test_batched_dic_cases_equal_their_solo_runs():
         for x, y in zip(c.get_state_numpy(), a):
             assert np.array_equal(x, y)
         c.close()
+
+
+def test_mixed_options_stream():
+    """Requests with different precisions and pressure preconditioners
+    (Jacobi, DIC, AMG) in one stream: the backend advances compatible cases
+    together and AMG cases alone; every case equals its solo run."""
+    from paper_1207_1571_amd import fvm
+    from paper_1207_1571_amd.serve import GpuBackend, Request, Server
+    specs = [wl.cavity((9, 8, 7), Re=300.0, dt=0.01, tol=1e-8),
+             wl.cavity((8, 8, 8), Re=200.0, dt=0.01, tol=1e-8, precision=wl.MIXED),
+             wl.cavity((10, 9, 8), Re=300.0, dt=0.01, tol=1e-8, p_precond=wl.PC_AMG),
+             wl.cavity((7, 7, 7), Re=100.0, dt=0.01, tol=1e-8, p_precond=wl.PC_DIC),
+             wl.cavity((11, 9, 7), Re=300.0, dt=0.01, tol=1e-8, p_precond=wl.PC_AMG),
+             wl.cavity((9, 9, 9), Re=300.0, dt=0.01, tol=1e-8)]
+    alone = []
+    for spec in specs:
+        c = fvm.Case(spec)
+        st, _ = c.piso(4)
+        assert st == 0
+        alone.append(c.get_state_numpy())
+        c.close()
+    be = GpuBackend(keep_fields=True)
+    budget = sum(be.footprint(s) for s in specs)
+    res = Server(be, budget, slots=6, group=6, chunk=2).run([Request(k, 0.0, s, 4) for k, s in enumerate(specs)])
+    assert sorted(r.rid for r in res) == list(range(len(specs)))
+    for r in res:
+        assert r.status == 0, r
+        for a, b in zip(r.fields, alone[r.rid]):
+            assert np.array_equal(a, b), r.rid
