@@ -392,7 +392,7 @@ def main():
                     help="run a plain 256 MiB device copy first (reference for memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
