@@ -229,6 +229,7 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d, std::v
         d.amg_nc = A.L[nl - 1].n;
         d.amg = b.take<AmgLevel>(nl);
         d.amg_cinv = b.take<double>((size_t)d.amg_nc * d.amg_nc);
+        d.amg_img = b.take<double>(kAmgTailLds / 8);
         if (!d.z) d.z = b.take<double>(N);
         std::vector<AmgLevel> tmp;
         std::vector<AmgLevel> &v = lv ? *lv : tmp;
@@ -258,6 +259,8 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d, std::v
                 e.losort = d.losort;
             }
             if (l < nl - 1) e.agg = b.take<int32_t>(n);
+            d.amg_b[l] = e.b;
+            d.amg_out[l] = e.out;
         }
     }
     if (o.hybrid_K > 0) {

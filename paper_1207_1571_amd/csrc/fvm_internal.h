@@ -18,6 +18,7 @@ struct AmgHost;
 const AmgHost &mesh_amg(const fvm_mesh &m);
 constexpr int kAmgCoarseMax = 128;    // coarsen while a level has more cells
 constexpr int kAmgDenseMax = 512;     // largest coarsest level (dense inverse)
+constexpr int kAmgTailLds = 64 * 1024;   // LDS bytes of the fused smallest-levels launch
 
 struct ihipStream_t;
 typedef struct ihipStream_t *hipStream_t;
@@ -220,6 +221,8 @@ struct DevCase {
     int32_t amg_n[20], amg_nf[20];               // level sizes (read by the host launcher)
     AmgLevel *amg;
     double *amg_cinv;
+    double *amg_img;                             // [kAmgTailLds / 8] LDS image of the smallest levels
+    double *amg_b[20], *amg_out[20];             // each level's right-hand side and result (host copies)
     // reductions
     double *partials;                            // [kMaxRed][red_stride]   level-1 slots
     double *partials2;                           // [kMaxRed][red_stride2]  level-2 slots

@@ -2414,6 +2414,256 @@ __global__ void __launch_bounds__(kBlock) k_amg_up_w(const DevCase *dc, int l)
     }
 }
 
+// The smallest levels and the coarse solve in one launch.  Below a few
+// hundred rows each of the kernels above costs a launch and a couple of
+// dependent global-memory round trips whatever its size, so the levels
+// l0 .. nl - 1 whose structure fits in LDS run in one block.  Once per
+// solve (after the Galerkin products) k_amg_tail_pack writes their
+// structure and matrix values into an HBM image laid out exactly as the
+// LDS; each cycle then stages that image and level l0's right-hand side
+// with one round of independent 16-byte loads, smooths, restricts, solves
+// and prolongs in LDS, and writes only the corrected x of level l0.  The
+// arithmetic is that of k_amg_down, k_amg_restrict, k_amg_coarse and
+// k_amg_up (the coarse product split over a wave's lanes).
+constexpr int kAmgTailThreads = 1024;
+constexpr int kAmgTailWords = kAmgTailLds / 16 / kAmgTailThreads;   // 16-byte loads per thread
+
+// LDS carving: consecutive arrays, each rounded up to 16 bytes.  The host
+// walks the same sequence with a null base to size the launch.
+struct LdsBump {
+    char *base;   // null when only sizing
+    long off;
+    template <class T> __host__ __device__ T *take(long n)
+    {
+        T *r = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += (n * (long)sizeof(T) + 15) / 16 * 16;
+        return r;
+    }
+};
+
+struct AmgTailLevel {
+    double *diag, *offd, *b, *x, *r;   // r holds out on the way up
+    int32_t *os, *ns, *nei, *own, *losort, *agg, *cmstart, *cmembers;
+};
+
+// level l of the tail (l < nl - 1 has the full structure; the coarsest level
+// only b and out)
+__host__ __device__ inline AmgTailLevel amg_tail_carve(LdsBump &bp, const int32_t *n, const int32_t *nf, int l, int nl)
+{
+    AmgTailLevel t{};
+    const long m = n[l];
+    t.b = bp.take<double>(m);
+    t.r = bp.take<double>(m);
+    if (l < nl - 1) {
+        const long f = nf[l];
+        t.diag = bp.take<double>(m);
+        t.x = bp.take<double>(m);
+        t.offd = bp.take<double>(f);
+        t.os = bp.take<int32_t>(m + 1);
+        t.ns = bp.take<int32_t>(m + 1);
+        t.nei = bp.take<int32_t>(f);
+        t.own = bp.take<int32_t>(f);
+        t.losort = bp.take<int32_t>(f);
+        t.agg = bp.take<int32_t>(m);
+        t.cmstart = bp.take<int32_t>(n[l + 1] + 1);
+        t.cmembers = bp.take<int32_t>(m);
+    }
+    return t;
+}
+
+// LDS bytes of the tail from level l0, or -1 when it does not fit
+__host__ inline long amg_tail_bytes(const int32_t *n, const int32_t *nf, int l0, int nl)
+{
+    LdsBump bp{nullptr, 0};
+    for (int l = l0; l < nl; ++l) amg_tail_carve(bp, n, nf, l, nl);
+    return bp.off <= kAmgTailLds ? bp.off : -1;
+}
+
+// the LDS arrays of tail level l for an image at base (carved again where
+// needed: a handful of scalar operations, and no per-lane pointer table)
+__device__ inline AmgTailLevel amg_tail_level(const DevCase &d, char *base, int l0, int l)
+{
+    LdsBump bp{base, 0};
+    for (int k = l0; k < l; ++k) amg_tail_carve(bp, d.amg_n, d.amg_nf, k, d.amg_nl);
+    return amg_tail_carve(bp, d.amg_n, d.amg_nf, l, d.amg_nl);
+}
+
+template <class T>
+__device__ __forceinline__ void tail_copy(T *dst, const T *__restrict__ src, long n)
+{
+    for (long k = threadIdx.x; k < n; k += kAmgTailThreads) dst[k] = src[k];
+}
+
+// once per solve: the HBM image of the tail levels (b and r stay unset)
+__global__ void __launch_bounds__(kAmgTailThreads) k_amg_tail_pack(const DevCase *dc, int l0)
+{
+    const DevCase &d = *dc;
+    if (d.ks[3].done) return;
+    char *img = reinterpret_cast<char *>(d.amg_img);
+    for (int l = l0; l < d.amg_nl - 1; ++l) {
+        const AmgTailLevel t = amg_tail_level(d, img, l0, l);
+        const AmgLevel &L = d.amg[l], &C = d.amg[l + 1];
+        const int m = L.n, f = L.nf;
+        tail_copy(t.diag, L.diag, m);
+        tail_copy(t.offd, L.offd, f);
+        tail_copy(t.os, L.own_start, m + 1);
+        tail_copy(t.ns, L.nbr_start, m + 1);
+        tail_copy(t.nei, L.nei, f);
+        tail_copy(t.own, L.own, f);
+        tail_copy(t.losort, L.losort, f);
+        tail_copy(t.agg, L.agg, m);
+        tail_copy(t.cmstart, C.mstart, C.n + 1);
+        tail_copy(t.cmembers, C.members, m);
+    }
+}
+
+// bytes: the image size (amg_tail_bytes), at most kAmgTailLds; src: the
+// image; gb, gout: level l0's b and out; cinv: the coarse inverse; n0, mc:
+// the sizes of level l0 and of the coarsest level.  The buffers come as
+// arguments so that their loads leave before the stop flag is read.
+__global__ void __launch_bounds__(kAmgTailThreads)
+k_amg_tail(const DevCase *dc, int l0, int bytes, const int4 *__restrict__ src, const double *__restrict__ gb,
+           double *__restrict__ gout, const double *__restrict__ cinv, int n0, int mc)
+{
+    const DevCase &d = *dc;
+    extern __shared__ __align__(16) char amg_lds[];
+    const int tid = threadIdx.x;
+    const bool stop = d.ks[3].done;
+    const bool cpre = mc <= 2 * (kAmgTailThreads / 64);
+    double cv0 = 0.0, cv1 = 0.0;
+    {
+        // level l0's b opens the image; the rest comes from the packed copy.
+        // Every load is issued before the first LDS store.
+        const int w0 = (n0 * 8 + 15) / 16, w1 = bytes / 16;
+        int4 v[kAmgTailWords];
+        double bv[2];
+        if (cpre) {
+            // the coarse inverse's entries this lane multiplies (rows tid / 64
+            // and tid / 64 + 16 of at most 32, one column each)
+            const int i0 = tid >> 6, j = tid & 63;
+            if (j < mc && i0 < mc) cv0 = cinv[(long)i0 * mc + j];
+            if (j < mc && i0 + kAmgTailThreads / 64 < mc) cv1 = cinv[(long)(i0 + kAmgTailThreads / 64) * mc + j];
+        }
+#pragma unroll
+        for (int k = 0; k < kAmgTailWords; ++k) {
+            const int w = w0 + tid + k * kAmgTailThreads;
+            if (w < w1) v[k] = src[w];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = tid + k * kAmgTailThreads;
+            if (i < n0) bv[k] = gb[i];
+        }
+        int4 *dst = reinterpret_cast<int4 *>(amg_lds);
+        double *lb = reinterpret_cast<double *>(amg_lds);
+#pragma unroll
+        for (int k = 0; k < kAmgTailWords; ++k) {
+            const int w = w0 + tid + k * kAmgTailThreads;
+            if (w < w1) dst[w] = v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = tid + k * kAmgTailThreads;
+            if (i < n0) lb[i] = bv[k];
+        }
+        for (int i = tid + 2 * kAmgTailThreads; i < n0; i += kAmgTailThreads) lb[i] = gb[i];
+    }
+    if (stop) return;   // the whole block
+    const int nl = d.amg_nl;
+    auto level = [&](int l) { return amg_tail_level(d, amg_lds, l0, l); };
+    __syncthreads();
+
+    // Rows of a level go to groups of G lanes (G a power of two, the largest
+    // with G * rows <= the block, at most 64); a group's lanes split the
+    // row's faces and a shuffle tree sums them.  x is stored in a pass of
+    // its own so the face loops read it instead of recomputing it.
+    auto group = [](int m) {
+        int g = 1;
+        while (g < 64 && 2 * g * m <= kAmgTailThreads) g *= 2;
+        return g;
+    };
+    auto gsum = [](double v, int g) {
+        for (int o = g >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        return v;
+    };
+    // A x without the diagonal: faces of row i, split over the group
+    auto offdiag = [](const AmgTailLevel &t, const double *x, int i, int sub, int g) {
+        const int o0 = t.os[i], no = t.os[i + 1] - o0;
+        const int n0 = t.ns[i], nn = t.ns[i + 1] - n0;
+        double a = 0.0;
+        for (int k = sub; k < no + nn; k += g) {
+            const int f = k < no ? o0 + k : t.losort[n0 + k - no];
+            const int j = k < no ? t.nei[f] : t.own[f];
+            a += t.offd[f] * x[j];
+        }
+        return a;
+    };
+
+    // down: x = w b / diag, r = b - A x, restrict
+    for (int l = l0; l < nl - 1; ++l) {
+        const AmgTailLevel t = level(l);
+        const int m = d.amg_n[l], g = group(m), sub = tid & (g - 1);
+        for (int i = tid; i < m; i += kAmgTailThreads) t.x[i] = kAmgOmega * t.b[i] / t.diag[i];
+        __syncthreads();
+        for (int base = 0; base < m; base += kAmgTailThreads / g) {
+            const int i = base + tid / g;
+            const double a = gsum(i < m ? offdiag(t, t.x, i, sub, g) : 0.0, g);
+            if (i < m && sub == 0) t.r[i] = t.b[i] - (t.diag[i] * t.x[i] + a);
+        }
+        __syncthreads();
+        const int mn = d.amg_n[l + 1], gc = group(mn), subc = tid & (gc - 1);
+        double *cb = level(l + 1).b;
+        for (int base = 0; base < mn; base += kAmgTailThreads / gc) {
+            const int c = base + tid / gc;
+            double a = 0.0;
+            if (c < mn)
+                for (int k = t.cmstart[c] + subc; k < t.cmstart[c + 1]; k += gc) a += t.r[t.cmembers[k]];
+            a = gsum(a, gc);
+            if (c < mn && subc == 0) cb[c] = a;
+        }
+        __syncthreads();
+    }
+
+    // coarsest: out = A^-1 b, a wave per row, lanes split the row
+    {
+        const AmgTailLevel t = level(nl - 1);
+        const int lane = tid & 63;
+        for (int i = tid >> 6, k = 0; i < mc; i += kAmgTailThreads / 64, ++k) {
+            double a = 0.0;
+            if (cpre) {
+                if (lane < mc) a = (k == 0 ? cv0 : cv1) * t.b[lane];
+            } else {
+                const double *row = d.amg_cinv + (long)i * mc;
+                for (int j = lane; j < mc; j += 64) a += row[j] * t.b[j];
+            }
+            a = wave_sum64(a);
+            if (lane == 0) t.r[i] = a;
+        }
+        __syncthreads();
+    }
+
+    // up: x' = x + P xc, out = x' + w (b - A x') / diag; level l0 writes its
+    // result to HBM
+    for (int l = nl - 2; l >= l0; --l) {
+        const AmgTailLevel t = level(l);
+        const double *xc = level(l + 1).r;
+        const int m = d.amg_n[l], g = group(m), sub = tid & (g - 1);
+        for (int i = tid; i < m; i += kAmgTailThreads) t.x[i] += xc[t.agg[i]];
+        __syncthreads();
+        for (int base = 0; base < m; base += kAmgTailThreads / g) {
+            const int i = base + tid / g;
+            const double a = gsum(i < m ? offdiag(t, t.x, i, sub, g) : 0.0, g);
+            if (i < m && sub == 0) {
+                const double xi = t.x[i];
+                const double o = xi + kAmgOmega * (t.b[i] - (t.diag[i] * xi + a)) / t.diag[i];
+                if (l == l0) gout[i] = o;
+                else t.r[i] = o;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // rho/beta update from r.z (the value every block has summed)
 __device__ __forceinline__ void amg_rho(KState &s, double rz)
 {
@@ -2814,16 +3064,25 @@ void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
     const DevCase *dev = h.self;
     const int nl = h.amg_nl;
     auto grid = [](int n) { return dim3((unsigned)((n + kBlock - 1) / kBlock > 0 ? (n + kBlock - 1) / kBlock : 1)); };
+    // the levels from l0 on (l0 >= 1, below the coarsest) run in one launch
+    // when their structure fits in LDS; otherwise l0 = nl - 1
+    int l0 = nl - 1;
+    long tail_lds = -1;
+    for (int l = 1; l <= nl - 2; ++l)
+        if ((tail_lds = amg_tail_bytes(h.amg_n, h.amg_nf, l, nl)) >= 0) { l0 = l; break; }
     if (with_setup) {
         Prof p("amg_setup", s);
         for (int l = 1; l < nl; ++l)
             hipLaunchKernelGGL(k_amg_galerkin, grid(std::max(h.amg_n[l], h.amg_nf[l])), dim3(kBlock), 0, s, dev, l);
         hipLaunchKernelGGL(k_amg_cinv, dim3(1), dim3(kBlock), 0, s, dev);
+        if (l0 < nl - 1) hipLaunchKernelGGL(k_amg_tail_pack, dim3(1), dim3(kAmgTailThreads), 0, s, dev, l0);
     }
     Prof p("amg_vcycle", s);
     // a wave per row on the coarse levels (level 0 keeps a thread per row)
     auto wgrid = [](int n) { return dim3((unsigned)std::max(1, (n + kRowsPerBlock - 1) / kRowsPerBlock)); };
-    for (int l = 0; l < nl - 1; ++l) {
+    // the levels from l0 on (l0 >= 1, below the coarsest) run in one launch
+    // when their structure fits in LDS; otherwise l0 = nl - 1
+    for (int l = 0; l < l0; ++l) {
         if (l == 0) {
             run(k_amg_x0, bs, SZ_CELL, s, 0);
             run(k_amg_sell, bs, SZ_CELL, s, 0);
@@ -2834,8 +3093,12 @@ void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
             hipLaunchKernelGGL(k_amg_restrict, grid(h.amg_n[l + 1]), dim3(kBlock), 0, s, dev, l + 1);
         else hipLaunchKernelGGL(k_amg_restrict_w, wgrid(h.amg_n[l + 1]), dim3(kBlock), 0, s, dev, l + 1);
     }
-    hipLaunchKernelGGL(k_amg_coarse, grid(h.amg_n[nl - 1]), dim3(kBlock), 0, s, dev);
-    for (int l = nl - 2; l >= 1; --l) {
+    if (l0 < nl - 1)
+        hipLaunchKernelGGL(k_amg_tail, dim3(1), dim3(kAmgTailThreads), (unsigned)tail_lds, s, dev, l0, (int)tail_lds,
+                           reinterpret_cast<const int4 *>(h.amg_img), h.amg_b[l0], h.amg_out[l0], h.amg_cinv,
+                           h.amg_n[l0], h.amg_n[nl - 1]);
+    else hipLaunchKernelGGL(k_amg_coarse, grid(h.amg_n[nl - 1]), dim3(kBlock), 0, s, dev);
+    for (int l = std::min(l0, nl - 1) - 1; l >= 1; --l) {
         if (h.amg_n[l] > kAmgWaveRows) hipLaunchKernelGGL(k_amg_up, grid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
         else hipLaunchKernelGGL(k_amg_up_w, wgrid(h.amg_n[l]), dim3(kBlock), 0, s, dev, l);
     }

@@ -23,8 +23,11 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+# The meshes give one and two levels (no fused smallest-levels launch),
+# three levels with that launch from level 1, and (32^3) four levels with
+# wave-per-row kernels on level 1 and the fused launch from level 2.
 @pytest.mark.parametrize("shape,perm", [((4, 4, 3), None), ((8, 7, 6), 3), ((15, 13, 9), 6), ((40, 35, 1), 2),
-                                        ((24, 22, 20), None)])
+                                        ((24, 22, 20), None), ((32, 32, 32), 5)])
 def test_solve_pressure_amg_matches_oracle(shape, perm):
     import torch
     from paper_1207_1571_amd import fvm
