@@ -487,3 +487,157 @@ def test_breakdown_and_maxiter_statuses():
     b = np.ones(m.n_cells); b[3] = np.nan
     _, info = orc.pcg(own, nei, d, o, b, np.zeros(m.n_cells), 1e-8)
     assert info["status"] == -3
+
+
+# --------------------------------------------------------------------- O4 convection
+
+def _per_face_patches(m):
+    """The same mesh with every boundary face in a patch of its own, so that
+    each can carry its own boundary value."""
+    import dataclasses
+    Fi, F = m.n_internal, m.n_faces
+    return dataclasses.replace(m, patch_names=[f"b{f}" for f in range(Fi, F)],
+                               patch_start=np.arange(Fi, F, dtype=np.int32),
+                               patch_size=np.ones(F - Fi, np.int32))
+
+
+def _convection_residual(m, bcs, u0, convection, phi_cell):
+    """(A phi - b)_P for component 0 of the convection-only momentum system
+    (nu = 0, steady) built from the uniform flux F_f = S_f . u0."""
+    Fi = m.n_internal
+    F = m.Sf @ u0
+    diag, up, lo, src = orc.momentum_system(m, bcs, 0.0, 0.0, convection, F)
+    own, nei = m.owner[:Fi].copy(), m.neighbour.copy()
+    Ap = orc.amul(own, nei, diag, up, lo, phi_cell)
+    scale = np.abs(diag * phi_cell).max() + np.abs(src[:, 0]).max()
+    return Ap - src[:, 0], scale
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_O4_central_convection_of_linear_field_is_exact(seed):
+    """Linear (central) convection, no diffusion, uniform velocity u0:
+    Gauss's theorem gives sum_f s F_f phi_f = V (u0 . a) for phi = a.x + c,
+    and linear interpolation reproduces a linear field at the face centre of
+    an orthogonal (graded, renumbered) box.  Every boundary face is FIXED at
+    the field's value there, except a random half that is ZERO_GRAD, whose
+    faces carry the owner value: they add F_b (phi_P - phi(C_b)) to the
+    identity.  A sign flip of the flux, w swapped with 1 - w on a graded
+    mesh, or a dropped boundary term -F_b U_b breaks it."""
+    rng = np.random.default_rng(40 + seed)
+    m = _per_face_patches(_graded_mesh(seed, shape=(6, 5, 4)))
+    Fi, F = m.n_internal, m.n_faces
+    a = rng.normal(size=3); c0 = rng.normal(); u0 = rng.normal(size=3)
+    phi_cell = m.C @ a + c0
+    phi_b = m.Cf[Fi:] @ a + c0
+    zg = rng.random(F - Fi) < 0.5
+    bcs = [wl.PatchBC(ZERO_GRAD if zg[b] else FIXED, ZERO_GRAD, (float(phi_b[b]), 0.0, 0.0)) for b in range(F - Fi)]
+    res, scale = _convection_residual(m, bcs, u0, 0, phi_cell)
+    expect = m.V * (u0 @ a)
+    Fb = m.Sf[Fi:] @ u0
+    zg_term = np.where(zg, Fb * (phi_cell[m.owner[Fi:]] - phi_b), 0.0)
+    np.add.at(expect, m.owner[Fi:], zg_term)
+    assert np.abs(res - expect).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("u0", [(0.7, -1.3, 0.4), (-0.2, 0.9, -1.1)])
+def test_O4_upwind_convection_of_linear_field_on_uniform_box(u0):
+    """Upwind convection on a uniform box: each interior cell takes, per
+    axis, F (phi_P - phi_upstream) = h^2 u (a h), so sum_f s F_f phi_up =
+    V (u0 . a) whatever the flow direction.  Cells touching the boundary
+    see the FIXED face value half a cell away and are left out."""
+    u0 = np.array(u0)
+    m = _per_face_patches(mg.random_permutation(mg.box_mesh(6, 5, 4, lengths=(1.2, 1.0, 0.8)), 6))
+    Fi, F = m.n_internal, m.n_faces
+    a = np.array([0.8, -0.5, 1.9]); c0 = 0.3
+    phi_cell = m.C @ a + c0
+    phi_b = m.Cf[Fi:] @ a + c0
+    bcs = [wl.PatchBC(FIXED, ZERO_GRAD, (float(phi_b[b]), 0.0, 0.0)) for b in range(F - Fi)]
+    res, scale = _convection_residual(m, bcs, u0, 1, phi_cell)
+    interior = np.ones(m.n_cells, bool)
+    interior[m.owner[Fi:]] = False
+    assert interior.sum() == 4 * 3 * 2
+    expect = m.V * (u0 @ a)
+    assert np.abs(res - expect)[interior].max() <= 1e-13 * scale
+    # and the boundary cells do differ (the upwind face value is not exact there)
+    assert np.abs(res - expect)[~interior].max() > 1e-6 * scale
+
+
+def test_O4_convection_matrix_entries_hand_worked():
+    """Two cells of a 2x1x1 box (unit cells, so w = 1/2), flux F = S.u0 with
+    u0 = (2, 0, 0) and nu = 0.5: the internal face has |S| = 1 and delta = 1,
+    F = 2, so a_PN = F (1 - w) - nu delta = 0.5, a_NP = -F w - nu delta =
+    -1.5; with every boundary face a no-slip wall (FIXED 0, F_b = 0 apart
+    from the x-faces: F_b = -2 in at x = 0 and +2 out at x = 2, each with
+    delta_b = 2 on a unit cell) the diagonals are a_PP = F w + nu delta +
+    nu (4 side faces x 2 + x-face 2) = 1 + 0.5 + 5 = 6.5 and a_NN =
+    -F (1 - w) + nu delta + 5 = -1 + 0.5 + 5 = 4.5; a lid value
+    U_b = (3, 0, 0) on the x = 0 face adds (nu delta_b - F_b) U_b =
+    (1 + 2) 3 = 9 to b_P."""
+    m = _per_face_patches(mg.box_mesh(2, 1, 1, lengths=(2.0, 1.0, 1.0)))
+    Fi, F = m.n_internal, m.n_faces
+    assert Fi == 1
+    bcs = []
+    for b in range(F - Fi):
+        f = Fi + b
+        on_x0 = m.Cf[f, 0] == 0.0
+        bcs.append(wl.PatchBC(FIXED, ZERO_GRAD, (3.0 if on_x0 else 0.0, 0.0, 0.0)))
+    phi = m.Sf @ np.array([2.0, 0.0, 0.0])
+    diag, up, lo, src = orc.momentum_system(m, bcs, 0.5, 0.0, 0, phi)
+    P = int(m.owner[0]); Q = int(m.neighbour[0])
+    assert abs(m.C[P, 0] - 0.5) < 1e-15 and abs(m.C[Q, 0] - 1.5) < 1e-15
+    assert up[0] == pytest.approx(0.5, abs=1e-14)
+    assert lo[0] == pytest.approx(-1.5, abs=1e-14)
+    assert diag[P] == pytest.approx(6.5, abs=1e-14)
+    assert diag[Q] == pytest.approx(4.5, abs=1e-14)
+    assert src[P, 0] == pytest.approx(9.0, abs=1e-14) and src[Q, 0] == 0.0
+    assert np.all(src[:, 1:] == 0.0)
+
+
+# --------------------------------------------------------------------- O12 normaliser
+
+def test_O12_normalised_residual_hand_worked():
+    """Three cells in a chain, a non-symmetric matrix
+        A = [[2, -1, 0], [-0.5, 4, -2], [0, -1, 3]]
+    (upper = A(own, nei) = (-1, -2), lower = A(nei, own) = (-0.5, -1)),
+    x = (1, 2, 3), b = (1, 1, 1).  By hand: xbar = 2, A 1 = (1, 1.5, 2),
+    A x = (0, 1.5, 7), so
+        n_f = |0-2| + |1.5-3| + |7-4|  +  |1-2| + |1-3| + |1-4| = 6.5 + 6 = 12.5
+        sum |b - A x| = 1 + 0.5 + 6 = 7.5,  nres = 7.5 / 12.5 = 0.6."""
+    own = np.array([0, 1], np.int32); nei = np.array([1, 2], np.int32)
+    diag = np.array([2.0, 4.0, 3.0]); up = np.array([-1.0, -2.0]); lo = np.array([-0.5, -1.0])
+    b = np.ones(3); x = np.array([1.0, 2.0, 3.0])
+    assert orc.nres(own, nei, diag, up, lo, b, x) == pytest.approx(0.6, rel=1e-15)
+    # upper and lower swapped is A^T, another value: A^T x = (1, 4, 5), A^T 1 = (1.5, 2, 1),
+    #   n_f = |1-3| + |4-4| + |5-2|  +  |1-3| + |1-4| + |1-2| = 5 + 6 = 11, sum|b - A^T x| = 0 + 3 + 4 = 7
+    assert orc.nres(own, nei, diag, lo, up, b, x) == pytest.approx(7.0 / 11.0, rel=1e-15)
+    # a solve reports this value as its initial residual and stops before
+    # its first iteration when it is within the tolerance
+    _, info = orc.pbicg(own, nei, diag, up, lo, b, x, 0.61)
+    assert info["iters"] == 0 and info["res_initial"] == pytest.approx(0.6, rel=1e-15)
+    _, info = orc.pbicg(own, nei, diag, up, lo, b, x, 0.59)
+    assert info["iters"] >= 1 and info["res_initial"] == pytest.approx(0.6, rel=1e-15)
+    # relative tolerance: stop when nres <= rel_tol * nres0
+    _, info = orc.pbicg(own, nei, diag, up, lo, b, x, 0.0, rel_tol=0.5)
+    assert info["iters"] >= 1 and info["res_final"] <= 0.3 + 1e-15
+
+
+def test_O12_normaliser_is_scale_and_shift_invariant():
+    """n_f makes the residual independent of the level of x on a singular
+    (zero row sum) system: for A 1 = 0 the normaliser is sum|A x| + sum|b|,
+    and nres(x + k 1) = nres(x) for every k.  Scaling A, b together leaves
+    nres unchanged."""
+    m = mg.box_mesh(5, 4, 1)
+    Fi = m.n_internal
+    own, nei = m.owner[:Fi].copy(), m.neighbour.copy()
+    rng = np.random.default_rng(3)
+    g = rng.uniform(0.5, 2.0, Fi)
+    diag = np.zeros(m.n_cells)
+    np.add.at(diag, own, g); np.add.at(diag, nei, g)
+    off = -g
+    x = rng.normal(size=m.n_cells)
+    b = rng.normal(size=m.n_cells); b -= b.mean()
+    r0 = orc.nres(own, nei, diag, off, off, b, x)
+    Ax = orc.amul(own, nei, diag, off, off, x)
+    assert r0 == pytest.approx(np.abs(b - Ax).sum() / (np.abs(Ax).sum() + np.abs(b).sum()), rel=1e-13)
+    assert orc.nres(own, nei, diag, off, off, b, x + 7.5) == pytest.approx(r0, rel=1e-11)
+    assert orc.nres(own, nei, 3 * diag, 3 * off, 3 * off, 3 * b, x) == pytest.approx(r0, rel=1e-13)
