@@ -106,6 +106,10 @@ class GpuBackend:
         return fields
 
 
+# status of a request that was never admitted (the values of the C interface)
+STATUS_EINVAL, STATUS_ENOMEM = -1, -2
+
+
 class Server:
     """Admission by device footprint and slots; round-robin stepping of
     resident cases in groups of `group` cases, `chunk` steps at a time."""
@@ -122,7 +126,17 @@ class Server:
         self.clock = clock
         self.sleep = sleep
 
+    def _rejected(self, req: Request, t0: float, status: int, why: str) -> Result:
+        now = self.clock() - t0
+        self.rejections.append((req.rid, why))
+        return Result(req.rid, req.arrival_s, now, now, getattr(req.spec.mesh, "n_cells", 0), req.n_steps, 0, status,
+                      0, None)
+
     def run(self, requests: Sequence[Request], log: Optional[Callable[[str], None]] = None) -> List[Result]:
+        """Serve every request; one that cannot be admitted (invalid, larger
+        than the whole budget, or failing at creation) comes back at once
+        with a negative status, and the others go on."""
+        self.rejections = []
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
         active: Dict[int, dict] = {}
         results: List[Result] = []
@@ -137,17 +151,31 @@ class Server:
                 req = pending[0]
                 need = foot_cache.get(req.rid)
                 if need is None:
-                    need = foot_cache[req.rid] = self.backend.footprint(req.spec)
+                    try:
+                        need = foot_cache[req.rid] = int(self.backend.footprint(req.spec))
+                    except Exception as e:   # invalid mesh or options: reject this request only
+                        pending.popleft()
+                        results.append(self._rejected(req, t0, STATUS_EINVAL, f"footprint: {e}"))
+                        continue
                 if need > self.budget:
-                    raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
+                    pending.popleft()
+                    results.append(self._rejected(req, t0, STATUS_ENOMEM,
+                                                  f"needs {need} bytes, more than the whole budget {self.budget}"))
+                    continue
                 if used + need > self.budget:
                     break
                 pending.popleft()
-                case = self.backend.create(req.spec)
+                try:
+                    case = self.backend.create(req.spec)
+                except Exception as e:       # e.g. a hierarchy that cannot be built for this mesh
+                    results.append(self._rejected(req, t0, STATUS_EINVAL, f"create: {e}"))
+                    continue
                 used += need
                 active[req.rid] = dict(req=req, case=case, bytes=need, left=req.n_steps, admitted=self.clock() - t0,
                                        p_iters=0, status=0)
             if not active:
+                if not pending:
+                    break
                 # idle until the next arrival
                 wait = pending[0].arrival_s - (self.clock() - t0)
                 if wait > 0:

@@ -132,11 +132,50 @@ def test_budget_holds_requests_in_queue():
     assert adm[2] > adm[0]
 
 
-def test_request_larger_than_budget_is_rejected():
+def test_request_larger_than_budget_is_rejected_and_others_served():
+    """An oversized request comes back at once with FVM_ENOMEM; the requests
+    around it are served, and the budget never counts it."""
     clk = VClock()
     be = FakeBackend(clk, bytes_per_cell=1000)
-    with pytest.raises(ValueError):
-        _server(be, clk, 10_000).run([Request(0, 0.0, _spec(1000), 1)])
+    reqs = [Request(0, 0.0, _spec(5), 3), Request(1, 0.0, _spec(1000), 1), Request(2, 0.0, _spec(8), 3)]
+    srv = _server(be, clk, 10_000)
+    res = {r.rid: r for r in srv.run(reqs)}
+    assert res[1].status == -2 and res[1].bytes == 0
+    assert res[0].status == 0 and res[2].status == 0
+    assert be.max_resident_bytes <= 10_000 and not be.resident
+    assert [rid for rid, _ in srv.rejections] == [1]
+
+
+class _FailingBackend(FakeBackend):
+    """footprint() raises for one request (an invalid mesh), create() for
+    another (a hierarchy that cannot be built)."""
+
+    def __init__(self, clock, bad_foot, bad_create):
+        super().__init__(clock)
+        self.bad_foot, self.bad_create = bad_foot, bad_create
+
+    def footprint(self, spec):
+        if getattr(spec, "rid", None) == self.bad_foot:
+            raise RuntimeError("invalid mesh")
+        return super().footprint(spec)
+
+    def create(self, spec):
+        if getattr(spec, "rid", None) == self.bad_create:
+            raise RuntimeError("coarsening stalled")
+        return super().create(spec)
+
+
+def test_errors_of_one_request_do_not_stop_the_server():
+    clk = VClock()
+    be = _FailingBackend(clk, bad_foot=1, bad_create=3)
+    reqs = [Request(i, 0.001 * i, _spec(100, rid=i), 4) for i in range(5)]
+    res = {r.rid: r for r in _server(be, clk, 10**9, slots=2, group=2, chunk=2).run(reqs)}
+    assert sorted(res) == [0, 1, 2, 3, 4]
+    assert res[1].status == -1 and res[3].status == -1
+    for i in (0, 2, 4):
+        assert res[i].status == 0 and res[i].p_iters == 5 * 4
+    assert not be.resident
+    assert summarize(list(res.values()))["failed"] == 2
 
 
 def test_slots_limit_resident_cases():
@@ -189,3 +228,10 @@ def test_bad_server_parameters():
     clk = VClock()
     with pytest.raises(ValueError):
         _server(FakeBackend(clk), clk, 10, slots=0)
+
+
+def test_stream_ending_with_a_rejected_request():
+    clk = VClock()
+    be = FakeBackend(clk, bytes_per_cell=1000)
+    res = _server(be, clk, 10_000).run([Request(0, 0.0, _spec(5), 2), Request(1, 0.5, _spec(1000), 1)])
+    assert sorted((r.rid, r.status) for r in res) == [(0, 0), (1, -2)]
