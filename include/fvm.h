@@ -150,6 +150,19 @@ void fvm_mesh_destroy(fvm_mesh *mesh);
 fvm_status fvm_mesh_info(const fvm_mesh *mesh, int32_t *n_cells, int32_t *n_faces, int32_t *n_internal_faces,
                          int32_t *non_orthogonal);
 
+/* Structure of the sliced-ELL copy of the pressure matrix that the CG's
+ * matrix-vector product reads (rows in slices of 256 consecutive cells,
+ * w_slots entries per row, slot-major): the number of slices, how many of
+ * them store explicit int32 column indices (a slice whose column offsets
+ * j - i take at most w_slots values stores one offset per slot and no
+ * index), the entries (internal faces seen from one of their two cells) in
+ * explicit slices, and the entries of regular slices read through a mirror
+ * slot (their symmetric coefficient is taken from the neighbour's upper
+ * slot instead of a second copy).  Measurement support: it gives the bytes a
+ * product must move.  Any pointer may be NULL. */
+fvm_status fvm_mesh_sell_info(const fvm_mesh *mesh, int32_t *w_slots, int32_t *n_slices, int32_t *n_explicit_slices,
+                              int64_t *explicit_entries, int64_t *mirrored_entries);
+
 /* Exact device workspace size of a case of this mesh with these options
  * (admission control of many resident cases relies on it being exact). */
 fvm_status fvm_case_workspace_bytes(const fvm_mesh *mesh, const fvm_case_opts *opts, size_t *bytes);

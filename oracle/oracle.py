@@ -57,24 +57,44 @@ class OrcStepInfo(ct.Structure):
                     p=[self.p[k].as_dict() for k in range(self.n_p_solves)], status=self.status)
 
 
-def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (ISO C99, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+
+
+def build(force: bool = False, native: bool = False) -> str:
+    """Compile liboracle.so with gcc (ISO C99, no fast-math, no contraction
+    of multiply-adds).  native=True builds liboracle_native.so for the host
+    it runs on (-O3 -march=native), used to time the oracle as a CPU
+    baseline; both give the same results (the same IEEE operations in the
+    same order)."""
+    out = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
+        subprocess.check_call(["gcc", "-std=c99", *opt, "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+                               "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
+_use_native = False
+
+
+def select_native() -> str:
+    """Load the host-tuned build in this process (must come before the
+    first use of the oracle); returns its path."""
+    global _use_native
+    if _lib is not None and not _use_native:
+        raise RuntimeError("the oracle library is already loaded")
+    _use_native = True
+    return build(force=True, native=True)
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ct.CDLL(_LIB)
+        path = build(native=_use_native)
+        L = ct.CDLL(path)
         M, O = ct.POINTER(OrcMesh), ct.POINTER(OrcOpts)
         SI, STI = ct.POINTER(OrcSolveInfo), ct.POINTER(OrcStepInfo)
         L.orc_flux_from_U.argtypes = [M, f64p, f64p]

@@ -583,3 +583,29 @@ extern "C" fvm_status fvm_mesh_info(const fvm_mesh *m, int32_t *n_cells, int32_t
     if (non_orthogonal) *non_orthogonal = m->nonorth ? 1 : 0;
     return FVM_OK;
 }
+
+extern "C" fvm_status fvm_mesh_sell_info(const fvm_mesh *m, int32_t *w_slots, int32_t *n_slices,
+                                         int32_t *n_explicit_slices, int64_t *explicit_entries,
+                                         int64_t *mirrored_entries)
+{
+    if (!m) return fvm_fail(FVM_EINVAL, "mesh: null handle");
+    const int32_t W = m->sell_W, ns = (int32_t)m->sell_mode.size();
+    int32_t nx = 0;
+    int64_t ex = 0, mir = 0;
+    for (int32_t s = 0; s < ns; ++s) {
+        const bool explicit_cols = m->sell_mode[s] != 0;
+        nx += explicit_cols ? 1 : 0;
+        for (int32_t k = 0; k < W; ++k) {
+            int64_t used = 0;
+            for (int32_t l = 0; l < kBlock; ++l) used += m->sell_fe[((size_t)s * W + k) * kBlock + l] >= 0;
+            if (explicit_cols) ex += used;
+            else if (m->sell_mir[(size_t)s * W + k] >= 0) mir += used;
+        }
+    }
+    if (w_slots) *w_slots = W;
+    if (n_slices) *n_slices = ns;
+    if (n_explicit_slices) *n_explicit_slices = nx;
+    if (explicit_entries) *explicit_entries = ex;
+    if (mirrored_entries) *mirrored_entries = mir;
+    return FVM_OK;
+}

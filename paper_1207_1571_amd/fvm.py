@@ -80,7 +80,7 @@ _lib = None
 EXPORTS = ("fvm_mesh_create", "fvm_mesh_destroy", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
            "fvm_case_destroy", "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
            "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read",
-           "fvm_last_error", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg")
+           "fvm_last_error", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg", "fvm_mesh_sell_info")
 
 
 def lib():
@@ -116,10 +116,12 @@ def lib():
         L.fvm_mesh_hybrid.argtypes = [vp, ct.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, i32p]
         L.fvm_case_operator.argtypes = [vp, ct.c_int32, vp, vp, vp]
         L.fvm_mesh_amg.argtypes = [vp, ct.c_int32, i32p, i32p, i32p, i32p, i32p, i32p]
+        i64p = ct.POINTER(ct.c_int64)
+        L.fvm_mesh_sell_info.argtypes = [vp, i32p, i32p, i32p, i64p, i64p]
         for name in ("fvm_mesh_create", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
                      "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
                      "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable",
-                     "fvm_profile_read", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg"):
+                     "fvm_profile_read", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg", "fvm_mesh_sell_info"):
             getattr(L, name).restype = ct.c_int32
         _lib = L
     return _lib
@@ -263,6 +265,15 @@ class Case:
         st = _check(lib().solve_pressure(self.handle, _dptr(gamma), _dptr(rhs), _dptr(p), ct.byref(ctl),
                                          ct.c_void_p(_stream_ptr(self.stream)), ct.byref(info)))
         return st, info.as_dict()
+
+
+def mesh_sell_info(mesh: Mesh) -> dict:
+    """Structure of the sliced-ELL copy the CG's product reads."""
+    w, ns, nx = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    ex, mir = ct.c_int64(), ct.c_int64()
+    _check(lib().fvm_mesh_sell_info(mesh.handle, ct.byref(w), ct.byref(ns), ct.byref(nx), ct.byref(ex), ct.byref(mir)))
+    return dict(w_slots=w.value, n_slices=ns.value, n_explicit_slices=nx.value, explicit_entries=ex.value,
+                mirrored_entries=mir.value)
 
 
 def mesh_amg(mesh: Mesh):

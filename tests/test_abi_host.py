@@ -50,6 +50,29 @@ def _mesh(case):
     return fvm.Mesh(case.mesh, case.bcs)
 
 
+def test_sell_info_regular_and_explicit_slices():
+    """A lexicographic 16^3 box: a slice of 256 cells is one z-layer, whose
+    column offsets are among +-1, +-16, +-256, so no slice stores indices.
+    A lower entry (offset -1, -16, -256) is read through a mirror when the
+    neighbour's slices hold the opposite offset in one common slot.  Slice 0
+    has no z-neighbour below, so its offsets (-16, -1, 1, 16, 256) sit in
+    other slots than the interior slices' (-256, -16, -1, 1, 16, 256): its
+    own in-layer lower entries (no lower slice at all) and slice 1's -1 and
+    -16 entries (whose neighbours span slices 0 and 1) keep their own copies,
+    2 x 2 x 240 entries; every other internal face is read once.  A randomly
+    renumbered box stores explicit columns in every slice: two entries per
+    internal face."""
+    m = _mesh(wl.cavity((16, 16, 16), Re=10.0, dt=0.01))
+    si = fvm.mesh_sell_info(m)
+    assert si["w_slots"] == 6 and si["n_slices"] == 16 and si["n_explicit_slices"] == 0
+    assert si["explicit_entries"] == 0
+    assert si["mirrored_entries"] == m.n_internal - 4 * 240
+    r = _mesh(wl.cavity((16, 16, 16), Re=10.0, dt=0.01, perm_seed=3))
+    si = fvm.mesh_sell_info(r)
+    assert si["n_explicit_slices"] == 16 and si["explicit_entries"] == 2 * r.n_internal
+    assert si["mirrored_entries"] == 0
+
+
 def test_mesh_info_counts():
     c = wl.cavity((5, 4, 3), Re=10.0, dt=0.01)
     m = _mesh(c)

@@ -25,9 +25,13 @@ def _rel(a, b):
 
 # The meshes give one and two levels (no fused smallest-levels launch),
 # three levels with that launch from level 1, and (32^3) four levels with
-# wave-per-row kernels on level 1 and the fused launch from level 2.
+# wave-per-row kernels on level 1 and the fused launch from level 2.  The
+# 60x50 sheets end on a coarsest level of 47 and 68 rows inside the fused
+# launch, above the 32 rows whose inverse it prefetches with the image: the
+# coarse solve then reads the inverse's rows from device memory.
 @pytest.mark.parametrize("shape,perm", [((4, 4, 3), None), ((8, 7, 6), 3), ((15, 13, 9), 6), ((40, 35, 1), 2),
-                                        ((24, 22, 20), None), ((32, 32, 32), 5)])
+                                        ((24, 22, 20), None), ((32, 32, 32), 5), ((60, 50, 1), 1),
+                                        ((60, 50, 1), None)])
 def test_solve_pressure_amg_matches_oracle(shape, perm):
     import torch
     from paper_1207_1571_amd import fvm

@@ -428,6 +428,35 @@ def test_mixed_precision_error_at_benchmark_tolerance():
     eU, ep = _rel(g["U"], o["U"]), _rel(g["p"], o["p"])
     _say(f"  mixed at tol 1e-6: relL2 U {eU:.2e} p {ep:.2e}; p iters gpu {_counts(g['info'])} oracle {_counts(o['info'])}")
     assert eU <= 1e-4 and ep <= 1e-3
+    # against the FP64 path at the same stopping threshold the mixed result
+    # is within the mixed-precision tolerance: both stop on the same
+    # normalised residual, and the FP32 inner work changes only rounding
+    f = _gpu(case.with_(precision=wl.FP64), 5)
+    eU, ep = _rel(g["U"], f["U"]), _rel(g["p"], f["p"])
+    _say(f"  mixed vs FP64 GPU at tol 1e-6: relL2 U {eU:.2e} p {ep:.2e}; iters {_counts(g['info'])} {_counts(f['info'])}")
+    assert eU <= TOL_MIXED and ep <= TOL_MIXED
+
+
+@pytest.mark.timeout(600)
+def test_cav200_settings_on_a_64_cube():
+    """The 200^3 configuration's settings (lexicographic numbering, Re 1000,
+    dt 0.001, Jacobi PCG / PBiCG, tol 1e-6) on 64^3 cells: the z-neighbour
+    lies 4096 cells, 16 slices of the sliced-ELL copy, away, so the
+    index-free regular slices and the mirrored lower-slot reads cross slices
+    as they do at 200^3.  FP64 under the parity protocol (1e-9); the mixed
+    path against the oracle with both at an outer tolerance of 1e-10 (1e-6);
+    and mixed against FP64 at the configuration's 1e-6 (1e-6)."""
+    case = wl.cavity((64, 64, 64), Re=1000.0, dt=0.001, tol=1e-6)
+    g, _ = _parity(case, 3, what="64^3 lexicographic, FP64")
+    m = _gpu(case.with_(precision=wl.MIXED), 3)
+    eU, ep = _rel(m["U"], g["U"]), _rel(m["p"], g["p"])
+    _say(f"  mixed vs FP64 at tol 1e-6: relL2 U {eU:.2e} p {ep:.2e}; iters {_counts(m['info'])} {_counts(g['info'])}")
+    assert m["st"] == 0 and eU <= TOL_MIXED and ep <= TOL_MIXED
+    tight = case.with_(p_ctl=wl.SolverCtl(1e-10), u_ctl=wl.SolverCtl(1e-10), precision=wl.MIXED)
+    m = _gpu(tight, 3)
+    o = _oracle(tight, 3)
+    assert m["st"] == o["st"] == 0
+    _compare(m, o, tol=TOL_MIXED, what="64^3 lexicographic, mixed at 1e-10")
 
 
 def test_mixed_solve_pressure_and_simple():

@@ -22,13 +22,13 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _requests(precision, n_steps):
+def _requests(precision, n_steps, tol=1e-6):
     rng = np.random.default_rng(11)
     specs = []
     for rid, (kind, n) in enumerate([("cavity", 9), ("duct", 7), ("cavity", 12), ("duct", 10), ("cavity", 6),
                                       ("cavity", 11)]):
         req = wl.ServeRequest(rid, 0.0, kind, n, float(rng.uniform(10.0, 1000.0)), 0.2 / n, n_steps)
-        specs.append(wl.serve_case(req, precision=precision))
+        specs.append(wl.serve_case(req, precision=precision, tol=tol))
     return specs
 
 
@@ -147,3 +147,41 @@ def test_mixed_options_stream():
         assert r.status == 0, r
         for a, b in zip(r.fields, alone[r.rid]):
             assert np.array_equal(a, b), r.rid
+
+
+@pytest.mark.parametrize("precision", [wl.FP64, wl.MIXED])
+def test_served_cases_match_the_oracle(precision):
+    """Every case of a served stream against the FP64 oracle, all at an
+    outer tolerance of 1e-10: FP64 within 1e-9, with the oracle's pressure
+    iteration counts at the ends of the advances; mixed precision within
+    1e-6."""
+    from oracle import oracle as orc
+    from paper_1207_1571_amd.serve import GpuBackend, Request, Server
+
+    n_steps, chunk = 4, 2
+    specs = _requests(precision, n_steps, tol=1e-10)
+    be = GpuBackend(keep_fields=True)
+    budget = sum(be.footprint(s) for s in specs)
+    reqs = [Request(rid, 0.0, spec, n_steps) for rid, spec in enumerate(specs)]
+    res = Server(be, budget, slots=len(specs), group=len(specs), chunk=chunk).run(reqs)
+    assert sorted(r.rid for r in res) == list(range(len(specs)))
+    tol = 1e-9 if precision == wl.FP64 else 1e-6
+    for r in sorted(res, key=lambda r: r.rid):
+        assert r.status == 0, r
+        spec = specs[r.rid].with_(precision=wl.FP64)
+        oc = orc.OracleCase(spec)
+        p_iters = 0
+        for k in range(n_steps):
+            st, info = oc.piso(1)
+            assert st == 0
+            if (k + 1) % chunk == 0:
+                p_iters += sum(s["iters"] for s in info["p"])
+        errs = []
+        for a, b in zip(r.fields, (oc.U, oc.p, oc.phi)):
+            nb = np.linalg.norm(b)
+            errs.append(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+        _say(f"  served rid={r.rid} N={r.n_cells}: relL2 U {errs[0]:.2e} p {errs[1]:.2e} phi {errs[2]:.2e}; "
+             f"p iters {r.p_iters} oracle {p_iters}")
+        assert max(errs) <= tol, (r.rid, errs)
+        if precision == wl.FP64:
+            assert r.p_iters == p_iters, (r.rid, r.p_iters, p_iters)
