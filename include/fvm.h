@@ -125,7 +125,20 @@ typedef struct {
     int32_t u_solver;      /* FVM_SOLVER_* for the momentum equation */
     int32_t hybrid_K;      /* > 0: also lay out the paper's hybrid matrix format with this many ELL slots per
                               row, for fvm_case_operator's FVM_OP_HY_* operators (comparison layout); 0: none */
+    int32_t step_kernel;   /* FVM_STEP_AUTO or FVM_STEP_LAUNCHED (below) */
 } fvm_case_opts;
+
+/* How piso_step and piso_step_batch run a case.  FVM_STEP_AUTO: a small
+ * case (at most 32 768 cells, orthogonal mesh, Jacobi pressure CG, BiCG
+ * momentum, at most 4 correctors, no non-orthogonal correctors) runs its
+ * whole PISO steps, Krylov loops included, in one workgroup of one kernel
+ * launch (many such cases side by side, one per compute unit), since at that
+ * size launches and host round trips per Krylov iteration would cost more
+ * than the arithmetic; any other case, and every case under
+ * FVM_STEP_LAUNCHED, runs each phase of each iteration as a grid-wide launch.
+ * Both give the method's result (they differ only in the order of the
+ * floating-point sums). */
+enum { FVM_STEP_AUTO = 0, FVM_STEP_LAUNCHED = 1 };
 
 typedef struct {
     int32_t iters, status;
@@ -280,9 +293,12 @@ fvm_status fvm_case_operator(fvm_case *c, int32_t op, const double *d_in, double
 
 /* piso_step_batch -- advance several resident cases by n_steps PISO steps,
  * their kernels batched into shared launches (continuous-batching serving).
- * Every case must be FVM_MIXED or every case FVM_FP64.  infos[i] (may be
- * NULL) receives case i's last-step record.  Each case's result is the same
- * as piso_step on it alone. */
+ * Every case must be FVM_MIXED or every case FVM_FP64.  When every case
+ * qualifies for whole-step kernels (FVM_STEP_AUTO above), one launch runs
+ * all n_steps steps of all cases, one workgroup per case, with no host
+ * round trip in between; otherwise every case runs launched phases.
+ * infos[i] (may be NULL) receives case i's last-step record.  Each case's
+ * result is the same as piso_step on it alone. */
 fvm_status piso_step_batch(fvm_case *const *cases, int32_t n_cases, int32_t n_steps, void *stream,
                            fvm_step_info *infos);
 

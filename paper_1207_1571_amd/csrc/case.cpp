@@ -318,6 +318,8 @@ fvm_status check_opts(const fvm_mesh *m, const fvm_case_opts *o)
     if (o->hybrid_K < 0 || o->hybrid_K > 64) return fvm_fail(FVM_EINVAL, "case: hybrid_K must be in [0, 64]");
     if (o->hybrid_K > 0 && (int64_t)o->hybrid_K * m->N >= INT32_MAX)
         return fvm_fail(FVM_EINVAL, "case: hybrid_K * n_cells exceeds int32");
+    if (o->step_kernel != FVM_STEP_AUTO && o->step_kernel != FVM_STEP_LAUNCHED)
+        return fvm_fail(FVM_EINVAL, "case: bad step_kernel");
     return FVM_OK;
 }
 
@@ -366,6 +368,12 @@ struct fvm_case {
     std::vector<fvm_patch> patches;
     Poller poll;
     int last_iters[4] = {0, 0, 0, 0};   // momentum, pressure, momentum inner; chunk sizing
+    // whole PISO steps in one workgroup (see FVM_STEP_AUTO)
+    bool solo() const
+    {
+        return o.step_kernel == FVM_STEP_AUTO && N <= kSoloMaxCells && !nonorth && o.n_non_orth_corr == 0 &&
+               o.n_corr <= kSoloMaxCorr && o.p_ctl.precond == FVM_PC_JACOBI && o.u_solver == FVM_SOLVER_BICG;
+    }
 };
 
 namespace {
@@ -957,6 +965,52 @@ fvm_status rollback_failed(Group &g, const std::vector<fvm_step_info> &info)
 // ---------------------------------------------------------------------------
 // public: PISO, SIMPLE, stand-alone pressure solve, batch
 // ---------------------------------------------------------------------------
+namespace {
+// n_steps PISO steps of every case of the group in one launch, one
+// workgroup per case; the kernel leaves each case's last-step record in its
+// Krylov state slots: 0..2 momentum, 3.. the pressure solves, the last one a
+// summary (iters: pressure solves recorded, status: worst over the steps,
+// done: steps completed, first: 1 when a step failed and was rolled back)
+fvm_status piso_solo(Group &g, int32_t n_steps, fvm_step_info *infos)
+{
+    const int n = g.n();
+    if (n_steps > 0) launch_solo_piso(g.bs, n_steps, g.cs[0]->o.n_corr, g.s);
+    HIPCHK(hipGetLastError());
+    std::vector<KState> res;
+    int32_t all = FVM_OK;
+    if (n_steps > 0) {
+        fvm_status st = snapshot(g, res);
+        if (st != FVM_OK) return st;
+    }
+    bool failed = false;
+    for (int i = 0; i < n; ++i) {
+        fvm_step_info info{};
+        if (n_steps > 0) {
+            const KState *r = res.data() + (size_t)i * kNumKs;
+            const KState &m = r[kNumKs - 1];
+            for (int c = 0; c < 3; ++c) {
+                to_info(r[c], info.u[c]);
+                worst(info.status, r[c].status);
+            }
+            info.n_p_solves = std::min(m.iters, kNumKs - 4);
+            for (int k = 0; k < info.n_p_solves; ++k) {
+                to_info(r[3 + k], info.p[k]);
+                worst(info.status, r[3 + k].status);
+            }
+            worst(all, m.status);
+            failed = failed || m.first != 0;
+            int32_t &li = g.cs[i]->last_iters[1];
+            li = info.n_p_solves > 0 ? info.p[info.n_p_solves - 1].iters : li;
+        }
+        if (infos) infos[i] = info;
+    }
+    if (all < 0 || failed)
+        return fvm_fail(all < 0 ? all : FVM_ENUMERIC,
+                        "piso: a solve failed (non-finite value or breakdown); the case was rolled back");
+    return all;
+}
+}  // namespace
+
 extern "C" fvm_status piso_step(fvm_case *c, int32_t n_steps, void *stream, fvm_step_info *last)
 {
     if (!c) return fvm_fail(FVM_EINVAL, "piso: null handle");
@@ -1087,6 +1141,9 @@ extern "C" fvm_status piso_step_batch(fvm_case *const *cases, int32_t n, int32_t
         P = &t_batch_poll;
     }
     Group g(cases, n, P, s);
+    bool all_solo = true;
+    for (int i = 0; i < n; ++i) all_solo = all_solo && cases[i]->solo();
+    if (all_solo) return piso_solo(g, n_steps, infos);
     std::vector<int> idx(n);                 // group member -> caller's index
     for (int i = 0; i < n; ++i) idx[i] = i;
     std::vector<int32_t> acc(n, FVM_OK);

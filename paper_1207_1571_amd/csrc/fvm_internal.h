@@ -249,8 +249,10 @@ struct Batch {
     int32_t n;
 };
 // grid kinds: one block per 256 cells / faces / internal faces / max(N, Fi),
-// and per 512 / 1024 cells for kernels that take 2 / 4 cells per thread
-enum { SZ_CELL = 0, SZ_FACE = 1, SZ_FACEI = 2, SZ_MAXNF = 3, SZ_CELL2 = 4, SZ_CELL4 = 5, SZ_KINDS = 6 };
+// and per 512 / 1024 / 2048 / 4096 cells for kernels that take several cells
+// per thread or several slices per block
+enum { SZ_CELL = 0, SZ_FACE = 1, SZ_FACEI = 2, SZ_MAXNF = 3, SZ_CELL2 = 4, SZ_CELL4 = 5, SZ_CELL8 = 6, SZ_CELL16 = 7,
+       SZ_KINDS = 8 };
 struct BatchSet {
     Batch b[SZ_KINDS];
     const DevCase *host[kMaxBatch];   // host copies (sizes, pointers) of the same cases
@@ -322,6 +324,13 @@ void launch_operator(const BatchSet &bs, int op, const double *in, double *out, 
 // r.z -> rho, beta
 void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s);
 void launch_hybrid_geometry(const BatchSet &bs, hipStream_t s);
+// whole PISO steps, one workgroup per case (small orthogonal Jacobi/BiCG
+// cases, n_corr <= kSoloMaxCorr): grid = the batch's cases; the last
+// step's record is left in each case's Krylov state slots (see
+// k_solo_piso)
+void launch_solo_piso(const BatchSet &bs, int n_steps, int n_corr, hipStream_t s);
+constexpr int kSoloMaxCells = 1 << 15;
+constexpr int kSoloMaxCorr = kNumKs - 4;
 void launch_rr_start(const BatchSet &bs, hipStream_t s);
 void launch_rr_iter(const BatchSet &bs, hipStream_t s);
 void launch_rr_replace(const BatchSet &bs, hipStream_t s);
@@ -329,3 +338,4 @@ void launch_rr_replace(const BatchSet &bs, hipStream_t s);
 // profiling
 void prof_begin(const char *cls, hipStream_t s);
 void prof_end(const char *cls, hipStream_t s);
+

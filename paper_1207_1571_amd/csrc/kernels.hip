@@ -452,11 +452,8 @@ __global__ void k_gradU(Batch bt)
 
 // upper = F(1-w) - nu dl, lower = -F w - nu dl; non-orthogonal source
 // ns_c = nu k.(w gradU_c,P + (1-w) gradU_c,N)
-__global__ void k_mom_face(Batch bt)
+__device__ __forceinline__ void el_mom_face(const DevCase &d, int f)
 {
-    CASE_OF(bt);
-    const int f = K.raw * kBlock + threadIdx.x;
-    if (f >= d.Fi) return;
     const double nu = d.nu;
     const double Fl = d.phi[f];
     const double w = d.upwind ? (Fl >= 0.0 ? 1.0 : 0.0) : d.w[f];
@@ -478,14 +475,19 @@ __global__ void k_mom_face(Batch bt)
     }
 }
 
+__global__ void k_mom_face(Batch bt)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.Fi) return;
+    el_mom_face(d, f);
+}
+
 // diag, src (without the pressure gradient) and rhs = src - V grad p.
 // mode 0 (PISO): transient term V/dt, V U/dt.  mode 1 (SIMPLE): implicit
 // relaxation diag <- diag/alpha_u, src += (1-alpha_u)/alpha_u diag_orig U.
-__global__ void k_mom_cell(Batch bt, int mode)
+__device__ __forceinline__ void el_mom_cell(const DevCase &d, int i, int mode)
 {
-    CASE_OF(bt);
-    const int i = K.raw * kBlock + threadIdx.x;
-    if (i >= d.N) return;
     const long N = d.N;
     const double nu = d.nu;
     const int upwind = d.upwind;
@@ -554,16 +556,21 @@ __global__ void k_mom_cell(Batch bt, int mode)
     d.rhs[2 * N + i] = s2 - V * (g2 / V);
 }
 
+__global__ void k_mom_cell(Batch bt, int mode)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    el_mom_cell(d, i, mode);
+}
+
 // ---------------------------------------------------------------------------
 // Pressure corrector
 // ---------------------------------------------------------------------------
 
 // H = src - sum a_PN U_N, rAU = V/a_PP, HbyA = H/a_PP; optional grad p
-__global__ void k_hbya(Batch bt, int with_gradp)
+__device__ __forceinline__ void el_hbya(const DevCase &d, int i, int with_gradp)
 {
-    CASE_OF(bt);
-    const int i = K.raw * kBlock + threadIdx.x;
-    if (i >= d.N) return;
     const long N = d.N;
     double h0 = d.src[i], h1 = d.src[N + i], h2 = d.src[2 * N + i];
     const double *U = d.U;
@@ -588,6 +595,14 @@ __global__ void k_hbya(Batch bt, int with_gradp)
     }
 }
 
+__global__ void k_hbya(Batch bt, int with_gradp)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    el_hbya(d, i, with_gradp);
+}
+
 __global__ void k_gradp(Batch bt)
 {
     CASE_OF(bt);
@@ -601,11 +616,8 @@ __global__ void k_gradp(Batch bt)
 
 // face pass: phiH = S.interp(HbyA) (boundary per U kind), gam = interp(rAU)
 // (boundary rAU_P), poff = -gam dl, tno = gam k.interp(grad p)
-__global__ void k_p_face(Batch bt)
+__device__ __forceinline__ void el_p_face(const DevCase &d, int f)
 {
-    CASE_OF(bt);
-    const int f = K.raw * kBlock + threadIdx.x;
-    if (f >= d.F) return;
     const long N = d.N;
     const double *H = d.HbyA;
     if (f < d.Fi) {
@@ -637,13 +649,18 @@ __global__ void k_p_face(Batch bt)
     }
 }
 
-// cell pass: pdiag, pb (divergence, fixed-p terms, non-orthogonal part), pin.
-// with_div = 0: the stand-alone pressure system (pb holds the given rhs)
-__global__ void k_p_cell(Batch bt, int with_div)
+__global__ void k_p_face(Batch bt)
 {
     CASE_OF(bt);
-    const int i = K.raw * kBlock + threadIdx.x;
-    if (i >= d.N) return;
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    el_p_face(d, f);
+}
+
+// cell pass: pdiag, pb (divergence, fixed-p terms, non-orthogonal part), pin.
+// with_div = 0: the stand-alone pressure system (pb holds the given rhs)
+__device__ __forceinline__ void el_p_cell(const DevCase &d, int i, int with_div)
+{
     double dg = 0.0, b = 0.0;
     for (int f = d.own_start[i]; f < d.own_start[i + 1]; ++f) {
         dg += -d.poff[f];
@@ -676,6 +693,14 @@ __global__ void k_p_cell(Batch bt, int with_div)
     else d.pb[i] += b;
 }
 
+__global__ void k_p_cell(Batch bt, int with_div)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    el_p_cell(d, i, with_div);
+}
+
 // gamma given per face (canonical order) -> poff, gam
 __global__ void k_p_face_gamma(Batch bt, const double *__restrict__ gam)
 {
@@ -688,11 +713,8 @@ __global__ void k_p_face_gamma(Batch bt, const double *__restrict__ gam)
 }
 
 // phi = phiH - g (p_N - p_P) - tno (internal); p FIXED: phiH - g_b (p_b - p_P)
-__global__ void k_flux_corr(Batch bt)
+__device__ __forceinline__ void el_flux_corr(const DevCase &d, int f)
 {
-    CASE_OF(bt);
-    const int f = K.raw * kBlock + threadIdx.x;
-    if (f >= d.F) return;
     if (f < d.Fi) {
         double v = d.phiH[f] - d.gam[f] * d.dl[f] * (d.p[d.nei[f]] - d.p[d.own[f]]);
         if (d.nonorth) v -= d.tno[f];
@@ -706,6 +728,14 @@ __global__ void k_flux_corr(Batch bt)
     }
 }
 
+__global__ void k_flux_corr(Batch bt)
+{
+    CASE_OF(bt);
+    const int f = K.raw * kBlock + threadIdx.x;
+    if (f >= d.F) return;
+    el_flux_corr(d, f);
+}
+
 __global__ void k_p_relax(Batch bt)
 {
     CASE_OF(bt);
@@ -715,11 +745,8 @@ __global__ void k_p_relax(Batch bt)
 }
 
 // U = HbyA - rAU grad p (new p)
-__global__ void k_U_corr(Batch bt)
+__device__ __forceinline__ void el_U_corr(const DevCase &d, int i)
 {
-    CASE_OF(bt);
-    const int i = K.raw * kBlock + threadIdx.x;
-    if (i >= d.N) return;
     const long N = d.N;
     double g0, g1, g2;
     gauss_sum(d, i, d.p, d.patch_pk, d.patch_pv, 1, g0, g1, g2);
@@ -727,6 +754,14 @@ __global__ void k_U_corr(Batch bt)
     d.U[i] = d.HbyA[i] - r * (g0 / V);
     d.U[N + i] = d.HbyA[N + i] - r * (g1 / V);
     d.U[2 * N + i] = d.HbyA[2 * N + i] - r * (g2 / V);
+}
+
+__global__ void k_U_corr(Batch bt)
+{
+    CASE_OF(bt);
+    const int i = K.raw * kBlock + threadIdx.x;
+    if (i >= d.N) return;
+    el_U_corr(d, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -1227,7 +1262,7 @@ __global__ void __launch_bounds__(kBlock) k_sell_fill(Batch bt)
 // Laplacian of the rounded face weights plus the rounded row sums,
 // spectrally within (1 +- eps32) of the FP64 one.  Products of FP32 values
 // are exact in FP64 and the sums are FP64.
-template <class T>
+template <class T, int WC>
 __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v, int sl, int i)
 {
     // per-slice tables are read as uniform scalar loads, coefficients and
@@ -1236,14 +1271,14 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
     typedef const __attribute__((address_space(1))) T gT;
     typedef const __attribute__((address_space(1))) int gint;
     constexpr bool kDiff = sizeof(T) == 4;
-    const int W = d.sell_W;
-    const size_t base = (size_t)sl * W * kBlock + threadIdx.x;
+    const int W = WC > 0 ? WC : d.sell_W;
+    const size_t base = (size_t)sl * W * kBlock + (i & (kBlock - 1));   // slices start at multiples of kBlock
     gT *__restrict__ sv = (gT *)v.sval;
     gT *__restrict__ val = sv + base;
     gT *__restrict__ p = (gT *)v.p;
     const double pi = (double)p[i];
     double qa = kDiff ? 0.0 : (double)((gT *)v.diag)[i] * pi, so = 0.0;
-    if (d.sell_mode[sl] == 0) {
+    if (((cint *)d.sell_mode)[sl] == 0) {
         cint *off = (cint *)(d.sell_off + (size_t)sl * W);
         cint *mir = (cint *)(d.sell_mir + (size_t)sl * W);
         const int last = d.N - 1;
@@ -1273,8 +1308,12 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
     return pi * (double)q;
 }
 
-// S slices per block (grid SZ_CELL for S = 1, SZ_CELL2 for S = 2)
-template <class T, int S>
+// A block takes the slices of its range one after the other (one cell per
+// thread per slice), so its set-up (case descriptor, controls) and the grid
+// reduction at its end are paid once for several slices.  WC > 0: the slot
+// count is fixed at compile time (6 on hex meshes): the loop is unrolled and
+// a slice's offsets and mirror slots are fetched together.
+template <class T, int WC>
 __global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
 {
     CASE_OF(bt);
@@ -1282,12 +1321,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
     if (v.ks->done) return;
     const Range rg = block_range(d.N, K);
     double acc[1] = {0.0};
-    for (int base = rg.beg; base < rg.end; base += S * kBlock) {
-#pragma unroll
-        for (int u = 0; u < S; ++u) {
-            const int i = base + u * kBlock + threadIdx.x;
-            if (i < rg.end) acc[0] += spmv_cell<T>(d, v, (base + u * kBlock) / kBlock, i);
-        }
+    for (int base = rg.beg; base < rg.end; base += kBlock) {
+        const int i = base + threadIdx.x;
+        if (i < rg.end) acc[0] += spmv_cell<T, WC>(d, v, base / kBlock, i);
     }
     __shared__ double tot[1];
     if (reduce_last<1>(acc, d, K, tot) && threadIdx.x == 0) {
@@ -1974,6 +2010,572 @@ __global__ void __launch_bounds__(kBlock) k_mx_resid(Batch bt)
 }
 
 // ---------------------------------------------------------------------------
+// Whole PISO steps of small cases, one workgroup per case
+//
+// A case of a few thousand cells cannot fill the GPU, and at that size a
+// solve driven by a few launches per Krylov iteration is bound by launch and
+// host-polling latency.  k_solo_piso runs complete PISO steps of a case in
+// one workgroup of kSolo threads: the same per-cell and per-face arithmetic
+// as the launched kernels (the el_* functions and the same Krylov
+// recurrences), phases separated by workgroup barriers, sums formed in LDS
+// in a fixed order, and the Krylov loops on the device: every thread sees
+// the same totals and the same stopping decisions.  A launch holds many
+// cases side by side, one per CU.  The case's Krylov states live in LDS
+// during the step; at the end the last step's record is left in the case's
+// state slots for the host: ks[0..2] momentum, ks[3..6] the pressure solves,
+// ks[7] a summary (iters: pressure solves of the last step, status: worst
+// status over the steps, done: steps completed, first: 1 when a step failed
+// and was rolled back).  Scope (the host checks it): orthogonal meshes, at
+// most 4 pressure correctors without non-orthogonal correction, Jacobi CG
+// and BiCG, FP64 or mixed precision.
+// ---------------------------------------------------------------------------
+constexpr int kSolo = 512;
+constexpr int kSoloWaves = kSolo / 64;
+
+struct SoloShared {
+    double red[12][kSoloWaves];
+    KState ks[kNumKs];
+    KState rec[kNumKs];
+};
+
+#define SOLO_FOR(var, n) for (int var = (int)threadIdx.x; var < (n); var += kSolo)
+
+// fixed-order workgroup sum of NV values; every thread receives the totals
+template <int NV>
+__device__ __forceinline__ void solo_sum(double (&v)[NV], SoloShared &sh)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    wave_sum(v);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh.red[k][wv] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = sh.red[k][0];
+        for (int w = 1; w < kSoloWaves; ++w) t += sh.red[k][w];
+        v[k] = t;
+    }
+}
+
+// the controls of k_set_ctl (src 0 momentum, 1 pressure, 3 FP32 inner)
+__device__ __forceinline__ void solo_ctl(const DevCase &d, KState &s, int src)
+{
+    if (src == 0) { s.tol = d.u_tol; s.rel_tol = d.u_rel_tol; s.max_iter = d.u_max_iter; }
+    else if (src == 1) { s.tol = d.p_tol; s.rel_tol = d.p_rel_tol; s.max_iter = d.p_max_iter; }
+    else { s.tol = 0.0; s.rel_tol = d.inner_rel_tol; s.max_iter = d.inner_max_iter; }
+}
+
+// ---- momentum: BiCG on the three components (k_bicg_* in one workgroup)
+
+// FP64 start (k_bicg_sumx, k_bicg_init): r = b - A x, r~ = r, n_f, rho
+__device__ void solo_bicg_init(const DevCase &d, SoloShared &sh)
+{
+    const long N = d.N;
+    double xb[3] = {0.0, 0.0, 0.0};
+    SOLO_FOR(i, d.N) for (int c = 0; c < 3; ++c) xb[c] += d.U[c * N + i];
+    solo_sum<3>(xb, sh);
+    for (int c = 0; c < 3; ++c) xb[c] /= (double)N;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    SOLO_FOR(i, d.N) {
+        const double a1 = row_sum(d, i, d.mdiag, d.upper, d.lower);
+        const double dg = d.mdiag[i];
+        for (int c = 0; c < 3; ++c) {
+            const double ax = row_apply<double>(d, i, d.mdiag, d.upper, d.lower, d.U + c * N);
+            const double b = d.rhs[c * N + i];
+            const double r = b - ax;
+            d.r[c * N + i] = r;
+            d.rt[c * N + i] = r;
+            v[c] += fabs(ax - xb[c] * a1) + fabs(b - xb[c] * a1);
+            v[3 + c] += fabs(r);
+            v[6 + c] += (r / dg) * r;
+        }
+    }
+    solo_sum<9>(v, sh);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) {
+            KState &s = sh.ks[c];
+            s.xbar = xb[c];
+            s.nf = v[c] + 1e-20;
+            s.nres0 = v[3 + c] / s.nf;
+            s.nres = s.nres0;
+            s.tol_eff = fmax(s.tol, s.rel_tol * s.nres0);
+            s.iters = 0;
+            s.done = 0;
+            s.status = FVM_OK;
+            s.first = 1;
+            s.beta = 0.0;
+            if (!isfinite(s.nres0)) set_done(s, FVM_ENUMERIC);
+            else if (s.nres0 <= s.tol_eff) set_done(s, FVM_OK);
+            else if (v[6 + c] == 0.0 || !isfinite(v[6 + c])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+            else s.rho = v[6 + c];
+        }
+    __syncthreads();
+}
+
+// BiCG iterations until the three systems (states ks0..ks0+2) are done;
+// at most `limit` iterations (the launched solver's bound)
+template <class T>
+__device__ void solo_bicg_iterate(const DevCase &d, SoloShared &sh, const BiArr<T> &v, int ks0, long limit)
+{
+    const long N = d.N;
+    KState *ks = sh.ks + ks0;
+    for (long it = 0; it < limit; ++it) {
+        int act[3];
+        for (int c = 0; c < 3; ++c) act[c] = !ks[c].done;
+        if (!act[0] && !act[1] && !act[2]) break;
+        // direction (k_bicg_dir)
+        SOLO_FOR(i, d.N) {
+            const T dg = v.diag[i];
+            for (int c = 0; c < 3; ++c) {
+                if (!act[c]) continue;
+                const long j = c * N + i;
+                const T z = v.r[j] / dg, zt = v.rt[j] / dg;
+                if (ks[c].first) {
+                    v.p[j] = z;
+                    v.pt[j] = zt;
+                } else {
+                    const T be = (T)ks[c].beta;
+                    v.p[j] = z + be * v.p[j];
+                    v.pt[j] = zt + be * v.pt[j];
+                }
+            }
+        }
+        __syncthreads();
+        // products (k_bicg_spmv)
+        double acc[3] = {0.0, 0.0, 0.0};
+        SOLO_FOR(i, d.N) {
+            for (int c = 0; c < 3; ++c) {
+                if (!act[c]) continue;
+                const T *p = v.p + c * N, *pt = v.pt + c * N;
+                const T q = row_apply<T>(d, i, v.diag, v.up, v.lo, p);
+                const T qt = row_apply<T>(d, i, v.diag, v.lo, v.up, pt);
+                v.q[c * N + i] = q;
+                v.qt[c * N + i] = qt;
+                acc[c] += (double)pt[i] * (double)q;
+            }
+        }
+        solo_sum<3>(acc, sh);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 3; ++c) {
+                if (!act[c]) continue;
+                KState &s = ks[c];
+                if (acc[c] == 0.0 || !isfinite(acc[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+                else s.alpha = s.rho / acc[c];
+            }
+        __syncthreads();
+        // update (k_bicg_update)
+        T al[3];
+        for (int c = 0; c < 3; ++c) { act[c] = !ks[c].done; al[c] = (T)ks[c].alpha; }
+        double u6[6] = {0, 0, 0, 0, 0, 0};
+        SOLO_FOR(i, d.N) {
+            const T dg = v.diag[i];
+            for (int c = 0; c < 3; ++c) {
+                if (!act[c]) continue;
+                const long j = c * N + i;
+                v.x[j] += al[c] * v.p[j];
+                const T r = v.r[j] - al[c] * v.q[j];
+                const T rt = v.rt[j] - al[c] * v.qt[j];
+                v.r[j] = r;
+                v.rt[j] = rt;
+                u6[c] += (double)(r / dg) * (double)rt;
+                u6[3 + c] += fabs((double)r);
+            }
+        }
+        solo_sum<6>(u6, sh);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 3; ++c) {
+                if (!act[c]) continue;
+                KState &s = ks[c];
+                s.iters += 1;
+                s.nres = u6[3 + c] / s.nf;
+                s.first = 0;
+                if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
+                else if (s.nres <= s.tol_eff) set_done(s, FVM_OK);
+                else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+                else if (u6[c] == 0.0 || !isfinite(u6[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+                else {
+                    s.beta = u6[c] / s.rho;
+                    s.rho = u6[c];
+                }
+            }
+        __syncthreads();
+    }
+    // a bound reached without a stop flag: the launched driver reports an
+    // error there too
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c)
+            if (!ks[c].done) set_done(ks[c], FVM_ENUMERIC);
+    __syncthreads();
+}
+
+// momentum solve: FP64 BiCG, or FP64 refinement around restarted FP32 BiCG
+__device__ void solo_momentum(const DevCase &d, SoloShared &sh, bool mixed)
+{
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) solo_ctl(d, sh.ks[c], 0);
+    __syncthreads();
+    solo_bicg_init(d, sh);
+    if (!mixed) {
+        solo_bicg_iterate<double>(d, sh, bi_arrays<double>(d), 0, (long)d.u_max_iter + 1);
+        return;
+    }
+    const long N = d.N;
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) solo_ctl(d, sh.ks[4 + c], 3);
+    SOLO_FOR(t, d.N > d.Fi ? d.N : d.Fi) {   // k_mx_cvt, momentum
+        if (t < d.N) d.f_diag[t] = (float)d.mdiag[t];
+        if (t < d.Fi) { d.f_up[t] = (float)d.upper[t]; d.f_lo[t] = (float)d.lower[t]; }
+    }
+    __syncthreads();
+    for (int outer = 0;; ++outer) {
+        int act[3];
+        for (int c = 0; c < 3; ++c) act[c] = !sh.ks[c].done;
+        if (!act[0] && !act[1] && !act[2]) break;
+        if (outer >= 1000) {
+            if (threadIdx.x == 0)
+                for (int c = 0; c < 3; ++c)
+                    if (act[c]) set_done(sh.ks[c], FVM_ENUMERIC);
+            __syncthreads();
+            break;
+        }
+        // inner start (k_mx_inner_init)
+        double sc[3];
+        for (int c = 0; c < 3; ++c) sc[c] = act[c] ? mx_scale(sh.ks[c], d.N) : 0.0;
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        SOLO_FOR(i, d.N) {
+            const float dg = d.f_diag[i];
+            for (int c = 0; c < 3; ++c) {
+                if (!act[c]) continue;
+                const long j = c * N + i;
+                const float r = (float)(sc[c] * d.r[j]);
+                d.f_r[j] = r;
+                d.f_rt[j] = r;
+                d.f_x[j] = 0.0f;
+                v[c] += fabs((double)r);
+                v[3 + c] += (double)(r / dg) * (double)r;
+            }
+        }
+        solo_sum<6>(v, sh);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 3; ++c) {
+                KState &s = sh.ks[4 + c];
+                if (!act[c]) { set_done(s, FVM_OK); s.iters = 0; continue; }
+                s.nf = v[c];
+                s.nres0 = 1.0;
+                s.nres = 1.0;
+                s.tol_eff = fmax(s.tol, s.rel_tol);
+                s.iters = 0;
+                s.done = 0;
+                s.status = FVM_OK;
+                s.first = 1;
+                s.beta = 0.0;
+                if (!isfinite(v[c]) || !(v[c] > 0.0)) set_done(s, FVM_ENUMERIC);
+                else if (v[3 + c] == 0.0 || !isfinite(v[3 + c])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+                else s.rho = v[3 + c];
+            }
+        __syncthreads();
+        solo_bicg_iterate<float>(d, sh, bi_arrays<float>(d), 4, (long)d.inner_max_iter + 1);
+        // correction and outer residual (k_mx_correct, k_mx_resid)
+        SOLO_FOR(i, d.N)
+            for (int c = 0; c < 3; ++c)
+                if (act[c]) d.U[(long)c * N + i] += (double)d.f_x[(long)c * N + i] / sc[c];
+        __syncthreads();
+        double w[3] = {0, 0, 0};
+        SOLO_FOR(i, d.N)
+            for (int c = 0; c < 3; ++c) {
+                if (!act[c]) continue;
+                const long j = c * N + i;
+                const double r = d.rhs[j] - row_apply<double>(d, i, d.mdiag, d.upper, d.lower, d.U + c * N);
+                d.r[j] = r;
+                w[c] += fabs(r);
+            }
+        solo_sum<3>(w, sh);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 3; ++c) {
+                if (!act[c]) continue;
+                KState &o = sh.ks[c];
+                const KState &in = sh.ks[4 + c];
+                o.iters += in.iters;
+                o.nres = w[c] / o.nf;
+                if (in.status == FVM_ENUMERIC || !isfinite(o.nres)) set_done(o, FVM_ENUMERIC);
+                else if (o.nres <= o.tol_eff) set_done(o, FVM_OK);
+                else if (o.iters >= o.max_iter) set_done(o, FVM_WARN_MAXITER);
+            }
+        __syncthreads();
+    }
+}
+
+// ---- pressure: Jacobi CG (k_cg_*, k_pcg_init; mixed: k_rr_*) -----------
+
+template <class T>
+__device__ __forceinline__ double solo_spmv_cell(const DevCase &d, const CGArr<T> &v, int i)
+{
+    return d.sell_W == 6 ? spmv_cell<T, 6>(d, v, i / kBlock, i) : spmv_cell<T, 0>(d, v, i / kBlock, i);
+}
+
+// one FP64 or FP32 CG iteration on state s (dir, product, update of the
+// launched kernels); mixed: the FP32 recurrence with the FP64 solution
+template <class T>
+__device__ void solo_cg_iteration(const DevCase &d, SoloShared &sh, const CGArr<T> &v, KState &s)
+{
+    constexpr bool kMixed = sizeof(T) == 4;
+    const bool first = s.first;
+    const T beta = (T)s.beta;
+    SOLO_FOR(i, d.N) {
+        const T z = v.r[i] / v.diag[i];
+        v.p[i] = first ? z : z + beta * v.p[i];
+    }
+    __syncthreads();
+    double pq[1] = {0.0};
+    SOLO_FOR(i, d.N) pq[0] += solo_spmv_cell<T>(d, v, i);
+    solo_sum<1>(pq, sh);
+    if (threadIdx.x == 0) {
+        if (!(pq[0] > 0.0) || !isfinite(pq[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else s.alpha = s.rho / pq[0];
+    }
+    __syncthreads();
+    if (s.done) return;
+    const double al = s.alpha;
+    double acc[2] = {0.0, 0.0};
+    if (!kMixed) {
+        SOLO_FOR(i, d.N) {
+            d.p[i] += al * (double)v.p[i];
+            const double r = (double)v.r[i] - al * (double)v.q[i];
+            v.r[i] = (T)r;
+            acc[0] += fabs(r);
+            acc[1] += r * (r / (double)v.diag[i]);
+        }
+    } else {
+        const float alf = (float)al;
+        SOLO_FOR(i, d.N) {
+            d.p[i] = d.p[i] + al * (double)v.p[i];
+            const float ri = (float)v.r[i] - alf * (float)v.q[i];
+            v.r[i] = (T)ri;
+            acc[0] += fabs((double)ri);
+            acc[1] += (double)ri * (double)(ri / (float)v.diag[i]);
+        }
+    }
+    solo_sum<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        s.iters += 1;
+        s.nres = acc[0] / s.nf;
+        s.first = 0;
+        if (kMixed) s.xbar = s.rho;   // rho of the previous iteration (for a replacement)
+        if (!isfinite(s.nres)) set_done(s, FVM_ENUMERIC);
+        else if (kMixed && (s.nres <= s.tol_eff || s.iters >= s.max_iter)) s.done = 2;   // verify on the true residual
+        else if (!kMixed && s.nres <= s.tol_eff) set_done(s, FVM_OK);
+        else if (!kMixed && s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+        else if (!(acc[1] > 0.0) || !isfinite(acc[1])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else {
+            s.beta = acc[1] / s.rho;
+            s.rho = acc[1];
+        }
+    }
+    __syncthreads();
+}
+
+// mixed precision: residual replacement (k_rr_replace)
+__device__ void solo_rr_replace(const DevCase &d, SoloShared &sh, KState &s)
+{
+    if (s.done == 1) return;
+    if (s.done == 0 && !(s.nres < 0.1 * s.scale)) return;
+    double acc[2] = {0.0, 0.0};
+    SOLO_FOR(i, d.N) {
+        const double r = d.pb[i] - row_apply<double>(d, i, d.pdiag, d.poff, d.poff, d.p);
+        const float rf = (float)r;
+        d.f_r[i] = rf;
+        acc[0] += fabs(r);
+        acc[1] += (double)rf * (double)(rf / d.f_pdiag[i]);
+    }
+    solo_sum<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        const double nres = acc[0] / s.nf;
+        s.nres = nres;
+        s.scale = nres;
+        if (!isfinite(nres)) set_done(s, FVM_ENUMERIC);
+        else if (nres <= s.tol_eff) set_done(s, FVM_OK);
+        else if (s.iters >= s.max_iter) set_done(s, FVM_WARN_MAXITER);
+        else if (!(acc[1] > 0.0) || !isfinite(acc[1])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else {
+            s.beta = s.first ? 0.0 : acc[1] / s.xbar;
+            s.rho = acc[1];
+            s.done = 0;
+        }
+    }
+    __syncthreads();
+}
+
+// pressure solve of the assembled system (pdiag, poff, pb), x = p
+__device__ void solo_pressure(const DevCase &d, SoloShared &sh, bool mixed)
+{
+    KState &s = sh.ks[3];
+    if (threadIdx.x == 0) solo_ctl(d, s, 1);
+    // sliced-ELL values (k_sell_fill) and, mixed, the FP32 copies (k_mx_cvt)
+    const int nsl = (d.N + kBlock - 1) / kBlock;
+    SOLO_FOR(e, nsl * d.sell_W * kBlock) {
+        const int fe = d.sell_fe[e];
+        const double a = fe < 0 ? 0.0 : d.poff[fe >> 1];
+        if (mixed) d.f_sell_val[e] = (float)a;
+        else d.sell_val[e] = a;
+    }
+    if (mixed)
+        SOLO_FOR(t, d.N > d.Fi ? d.N : d.Fi) {
+            if (t < d.N) {
+                d.f_pdiag[t] = (float)d.pdiag[t];
+                d.f_pexc[t] = (float)row_sum(d, t, d.pdiag, d.poff, d.poff);
+            }
+            if (t < d.Fi) d.f_poff[t] = (float)d.poff[t];
+        }
+    // start (k_pcg_sumx, k_pcg_init with Jacobi)
+    double xb[1] = {0.0};
+    SOLO_FOR(i, d.N) xb[0] += d.p[i];
+    solo_sum<1>(xb, sh);
+    const double xbar = xb[0] / (double)d.N;
+    double v[3] = {0.0, 0.0, 0.0};
+    SOLO_FOR(i, d.N) {
+        const double a1 = row_sum(d, i, d.pdiag, d.poff, d.poff);
+        const double ax = row_apply<double>(d, i, d.pdiag, d.poff, d.poff, d.p);
+        const double b = d.pb[i];
+        const double r = b - ax;
+        d.r[i] = r;
+        v[0] += fabs(ax - xbar * a1) + fabs(b - xbar * a1);
+        v[1] += fabs(r);
+        v[2] += r * (r / d.pdiag[i]);
+    }
+    solo_sum<3>(v, sh);
+    if (threadIdx.x == 0) {
+        s.xbar = xbar;
+        s.nf = v[0] + 1e-20;
+        s.nres0 = v[1] / s.nf;
+        s.nres = s.nres0;
+        s.tol_eff = fmax(s.tol, s.rel_tol * s.nres0);
+        s.iters = 0;
+        s.done = 0;
+        s.status = FVM_OK;
+        s.first = 1;
+        s.beta = 0.0;
+        if (!isfinite(s.nres0)) set_done(s, FVM_ENUMERIC);
+        else if (s.nres0 <= s.tol_eff) set_done(s, FVM_OK);
+        else if (!(v[2] > 0.0) || !isfinite(v[2])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+        else s.rho = v[2];
+    }
+    __syncthreads();
+    if (!mixed) {
+        const CGArr<double> a = cg_arrays<double>(d, 0);
+        for (long it = 0; it <= (long)d.p_max_iter && !s.done; ++it) solo_cg_iteration<double>(d, sh, a, s);
+    } else {
+        // k_rr_start: r32 = r64, rho = r32.(r32/diag32)
+        if (!s.done) {
+            double rho[1] = {0.0};
+            SOLO_FOR(i, d.N) {
+                const float r = (float)d.r[i];
+                d.f_r[i] = r;
+                rho[0] += (double)r * (double)(r / d.f_pdiag[i]);
+            }
+            solo_sum<1>(rho, sh);
+            if (threadIdx.x == 0) {
+                s.scale = s.nres;
+                if (!(rho[0] > 0.0) || !isfinite(rho[0])) { set_done(s, FVM_ENUMERIC); s.iters = 1; }
+                else s.rho = rho[0];
+            }
+            __syncthreads();
+        }
+        // iterations with a replacement check after every fourth, as the
+        // launched driver enqueues them (a paused recurrence waits for it)
+        constexpr int kReplaceEvery = 4;
+        const CGArr<float> a = cg_arrays<float>(d, 0);
+        const long limit = ((long)d.p_max_iter + 2) * kReplaceEvery;
+        for (long k = 0; k < limit && s.done != 1; ++k) {
+            if (!s.done) solo_cg_iteration<float>(d, sh, a, s);
+            if ((k + 1) % kReplaceEvery == 0) solo_rr_replace(d, sh, s);
+        }
+    }
+    if (threadIdx.x == 0 && s.done != 1) set_done(s, FVM_ENUMERIC);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void worst_status(int32_t &acc, int32_t s)
+{
+    if (s < 0) { if (acc >= 0 || s < acc) acc = s; }
+    else if (acc >= 0 && s > acc) acc = s;
+}
+
+// n_steps PISO steps of case blockIdx.x of the batch (orthogonal mesh)
+__global__ void __launch_bounds__(kSolo) k_solo_piso(Batch bt, int n_steps, int n_corr)
+{
+    __shared__ SoloShared sh;
+    if ((int)blockIdx.x >= bt.n) return;
+    const DevCase &d = *bt.dc[blockIdx.x];
+    const bool mixed = d.f_x != nullptr;
+    const long N = d.N, F = d.F;
+    int32_t worst = FVM_OK;
+    int steps_done = 0, failed = 0, np = 0;
+    for (int step = 0; step < n_steps; ++step) {
+        // start-of-step copies for a rollback (k_save)
+        SOLO_FOR(t, (int)(4 * N + F)) {
+            if (t < 3 * N) d.U_save[t] = d.U[t];
+            else if (t < 4 * N) d.p_save[t - 3 * N] = d.p[t - 3 * N];
+            else d.phi_save[t - 4 * N] = d.phi[t - 4 * N];
+        }
+        __syncthreads();
+        // momentum predictor
+        SOLO_FOR(f, d.Fi) el_mom_face(d, f);
+        __syncthreads();
+        SOLO_FOR(i, d.N) el_mom_cell(d, i, 0);
+        __syncthreads();
+        solo_momentum(d, sh, mixed);
+        int32_t st = FVM_OK;
+        for (int c = 0; c < 3; ++c) worst_status(st, sh.ks[c].status);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 3; ++c) sh.rec[c] = sh.ks[c];
+        np = 0;
+        if (st >= 0)
+            for (int corr = 0; corr < n_corr; ++corr) {
+                SOLO_FOR(i, d.N) el_hbya(d, i, 0);
+                __syncthreads();
+                SOLO_FOR(f, d.F) el_p_face(d, f);
+                __syncthreads();
+                SOLO_FOR(i, d.N) el_p_cell(d, i, 1);
+                __syncthreads();
+                solo_pressure(d, sh, mixed);
+                if (threadIdx.x == 0) sh.rec[3 + np] = sh.ks[3];
+                ++np;
+                worst_status(st, sh.ks[3].status);
+                if (st < 0) break;
+                SOLO_FOR(f, d.F) el_flux_corr(d, f);
+                __syncthreads();
+                SOLO_FOR(i, d.N) el_U_corr(d, i);
+                __syncthreads();
+            }
+        worst_status(worst, st);
+        if (st < 0) {
+            // roll the case back to the start of the failing step
+            __syncthreads();
+            SOLO_FOR(t, (int)(4 * N + F)) {
+                if (t < 3 * N) d.U[t] = d.U_save[t];
+                else if (t < 4 * N) d.p[t - 3 * N] = d.p_save[t - 3 * N];
+                else d.phi[t - 4 * N] = d.phi_save[t - 4 * N];
+            }
+            failed = 1;
+            break;
+        }
+        ++steps_done;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3 + np && k < kNumKs - 1; ++k) d.ks[k] = sh.rec[k];
+        KState m{};
+        m.iters = np;
+        m.status = worst;
+        m.done = steps_done;
+        m.first = failed;
+        d.ks[kNumKs - 1] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Operators one at a time (the assembly set of the paper's Table 3 plus the
 // matrix products), in the solver's face-major layout and in the paper's
 // hybrid layout (Section 3.1), for comparing the two
@@ -2028,7 +2630,7 @@ __global__ void __launch_bounds__(kBlock) k_op_spmv(Batch bt, const double *__re
     if (K.raw * kBlock >= d.N) return;
     const CGArr<double> v{d.pdiag, d.poff, nullptr, d.sell_val, nullptr, nullptr, const_cast<double *>(x), y, nullptr,
                           nullptr};
-    if (i < d.N) (void)spmv_cell<double>(d, v, K.raw, i);
+    if (i < d.N) (void)spmv_cell<double, 0>(d, v, K.raw, i);
 }
 
 // hybrid layout: device position of the entry whose transpose code is Jc in
@@ -2702,7 +3304,7 @@ __global__ void __launch_bounds__(kBlock) k_amg_sell(Batch bt, int up)
     for (int base = rg.beg; base < rg.end; base += kBlock) {
         const int i = base + threadIdx.x;
         if (i >= rg.end) continue;
-        (void)spmv_cell<double>(d, v, base / kBlock, i);   // L.r[i] = (A x)_i
+        (void)spmv_cell<double, 0>(d, v, base / kBlock, i);   // L.r[i] = (A x)_i
         const double bi = L.b[i];
         if (!up) L.r[i] = bi - L.r[i];
         else {
@@ -2756,6 +3358,8 @@ void batch_add(BatchSet &bs, const DevCase *dev, const DevCase *host)
         else if (k == SZ_FACEI) n = host->Fi;
         else if (k == SZ_CELL2) n = (host->N + 1) / 2;
         else if (k == SZ_CELL4) n = (host->N + 3) / 4;
+        else if (k == SZ_CELL8) n = (host->N + 7) / 8;
+        else if (k == SZ_CELL16) n = (host->N + 15) / 16;
         b.start[c + 1] = b.start[c] + blocks_for(n);
         b.n = c + 1;
     }
@@ -2888,6 +3492,17 @@ void launch_bicg_iter(const BatchSet &bs, hipStream_t s)
     run(k_bicg_update<double>, bs, SZ_CELL, s);
 }
 
+// every case of the batch has 6 slots per sliced-ELL row (hex meshes)
+bool sell_w6(const BatchSet &bs)
+{
+    for (int c = 0; c < bs.n; ++c)
+        if (bs.host[c]->sell_W != 6) return false;
+    return true;
+}
+
+// grid of the CG products: several slices per block
+constexpr int kSpmvGrid = SZ_CELL8;
+
 void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s)
 {
     run(k_sell_fill, bs, SZ_CELL, s);
@@ -2931,7 +3546,8 @@ void launch_pcg_iter(const BatchSet &bs, int pc, hipStream_t s)
     }
     {
         Prof p("pcg_spmv", s);
-        run(k_cg_spmv<double, 1>, bs, SZ_CELL, s, pc != 0 ? 1 : 0);
+        if (sell_w6(bs)) run(k_cg_spmv<double, 6>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0);
+        else run(k_cg_spmv<double, 0>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0);
     }
     {
         Prof p("pcg_update", s);
@@ -2942,6 +3558,13 @@ void launch_pcg_iter(const BatchSet &bs, int pc, hipStream_t s)
 }
 
 void launch_mx_cvt(const BatchSet &bs, int kind, hipStream_t s) { run(k_mx_cvt, bs, SZ_MAXNF, s, kind); }
+
+void launch_solo_piso(const BatchSet &bs, int n_steps, int n_corr, hipStream_t s)
+{
+    Prof p("solo_piso", s);
+    const Batch &b = bs.b[SZ_CELL];
+    hipLaunchKernelGGL(k_solo_piso, dim3((unsigned)b.n), dim3(kSolo), 0, s, b, n_steps, n_corr);
+}
 void launch_mx_inner_init(const BatchSet &bs, int, hipStream_t s) { run(k_mx_inner_init, bs, SZ_CELL, s); }
 void launch_mx_inner_iter(const BatchSet &bs, int, hipStream_t s)
 {
@@ -2972,7 +3595,8 @@ void launch_rr_iter(const BatchSet &bs, hipStream_t s)
     }
     {
         Prof p("pcg32_spmv", s);
-        run(k_cg_spmv<float, 2>, bs, SZ_CELL2, s, 0);
+        if (sell_w6(bs)) run(k_cg_spmv<float, 6>, bs, kSpmvGrid, s, 0);
+        else run(k_cg_spmv<float, 0>, bs, kSpmvGrid, s, 0);
     }
     {
         Prof p("pcg32_update", s);
@@ -3107,3 +3731,4 @@ void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
         run(k_amg_sell, bs, SZ_CELL, s, 1);
     } else run(k_amg_rz, bs, SZ_CELL, s);
 }
+

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libfvm.so")
 FVM_OK, FVM_WARN_MAXITER, FVM_EINVAL, FVM_ENOMEM, FVM_ENUMERIC, FVM_EDEVICE = 0, 1, -1, -2, -3, -4
 BC_FIXED, BC_ZERO_GRAD, BC_EMPTY = 0, 1, 2
 PC_JACOBI, PC_DIC, PC_AMG = 0, 1, 2
+STEP_AUTO, STEP_LAUNCHED = 0, 1
 # fvm_case_operator: face-major layout, then the paper's hybrid layout
 OP_GRAD, OP_DIV, OP_LAP, OP_SPMV = 0, 1, 2, 3
 OP_HY_GRAD, OP_HY_DIV, OP_HY_LAP, OP_HY_SPMV, OP_HY_STMVP, OP_HY_SETMAT = 4, 5, 6, 7, 8, 9
@@ -49,7 +50,8 @@ class FvmCaseOpts(ct.Structure):
                 ("p_ref_value", ct.c_double), ("inner_rel_tol", ct.c_double), ("n_corr", ct.c_int32),
                 ("n_non_orth_corr", ct.c_int32), ("convection", ct.c_int32), ("precision", ct.c_int32),
                 ("p_ref_cell", ct.c_int32), ("inner_max_iter", ct.c_int32), ("p_ctl", FvmSolverCtl),
-                ("u_ctl", FvmSolverCtl), ("u_solver", ct.c_int32), ("hybrid_K", ct.c_int32)]
+                ("u_ctl", FvmSolverCtl), ("u_solver", ct.c_int32), ("hybrid_K", ct.c_int32),
+                ("step_kernel", ct.c_int32)]
 
 
 class FvmSolveInfo(ct.Structure):
@@ -183,7 +185,7 @@ def opts_from_case(case) -> FvmCaseOpts:
                        case.inner_max_iter,
                        FvmSolverCtl(case.p_ctl.tol, case.p_ctl.rel_tol, case.p_ctl.max_iter, case.p_ctl.precond),
                        FvmSolverCtl(case.u_ctl.tol, case.u_ctl.rel_tol, case.u_ctl.max_iter, case.u_ctl.precond),
-                       getattr(case, "u_solver", 0), getattr(case, "hybrid_K", 0))
+                       getattr(case, "u_solver", 0), getattr(case, "hybrid_K", 0), getattr(case, "step_kernel", 0))
 
 
 def workspace_bytes(mesh: Mesh, opts: FvmCaseOpts) -> int:

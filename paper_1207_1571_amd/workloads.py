@@ -22,6 +22,7 @@ from . import meshgen as mg
 
 FIXED, ZERO_GRAD, EMPTY = 0, 1, 2
 PC_JACOBI, PC_DIC, PC_AMG = 0, 1, 2
+STEP_AUTO, STEP_LAUNCHED = 0, 1
 FP64, MIXED = 0, 1
 CONV_LINEAR, CONV_UPWIND = 0, 1
 SOLVER_BICG, SOLVER_BICGSTAB = 0, 1   # momentum solver
@@ -64,6 +65,7 @@ class CaseSpec:
     inner_max_iter: int = 2000
     u_solver: int = SOLVER_BICG
     hybrid_K: int = 0            # > 0: the case also holds the paper's hybrid layout (comparison operators)
+    step_kernel: int = 0         # 0: small cases run whole steps in one workgroup; 1: always launched phases
     p_ctl: SolverCtl = field(default_factory=lambda: SolverCtl(1e-6))
     u_ctl: SolverCtl = field(default_factory=lambda: SolverCtl(1e-6))
     mode: str = "piso"            # "piso" | "simple"

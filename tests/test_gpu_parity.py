@@ -151,7 +151,7 @@ def test_captured_iteration_chunks_equal_direct_launches(variant):
         kw["p_precond"] = wl.PC_AMG
     if variant == "mixed":
         kw["precision"] = wl.MIXED
-    case = wl.cavity((14, 12, 10), **kw)
+    case = wl.cavity((14, 12, 10), **kw).with_(step_kernel=wl.STEP_LAUNCHED)
     if variant == "bicgstab":
         case = case.with_(u_solver=wl.SOLVER_BICGSTAB)
     out = []
@@ -517,3 +517,27 @@ def test_degenerate_meshes(shape, variant):
         assert np.all(np.isfinite(a))
         err = np.linalg.norm(a - b) / max(np.linalg.norm(b), floor)
         assert err <= tol, (k, err)
+
+
+@pytest.mark.parametrize("precision", [wl.FP64, wl.MIXED])
+@pytest.mark.parametrize("shape,perm", [((9, 7, 5), 3), ((32, 32, 1), 1), ((17, 1, 13), None), ((32, 32, 32), 2)])
+def test_whole_step_kernel_against_launched_phases_and_oracle(shape, perm, precision):
+    """Small cases run whole PISO steps in one workgroup (the default for
+    them); the same case with every phase launched over the grid, and the
+    oracle, give the same fields: FP64 under the parity protocol (1e-9),
+    mixed precision within 1e-6 with both at an outer tolerance of 1e-10.
+    32^3 is the largest size that runs whole steps."""
+    tol = 1e-9 if precision == wl.FP64 else 1e-10
+    case = wl.cavity(shape, Re=300.0, dt=0.01, perm_seed=perm, tol=tol, precision=precision)
+    _say(f"[whole-step] {shape} precision {precision}")
+    solo = _gpu(case, 4)
+    launched = _gpu(case.with_(step_kernel=wl.STEP_LAUNCHED), 4)
+    assert solo["st"] == launched["st"] == 0
+    if precision == wl.FP64:
+        _say(f"  iters whole-step {_counts(solo['info'])} launched {_counts(launched['info'])}")
+        _compare(solo, launched, what="whole-step vs launched")
+        _parity(case, 4, what="whole-step vs oracle")
+    else:
+        o = _oracle(case, 4)
+        _compare(solo, o, tol=TOL_MIXED, what="whole-step mixed vs oracle")
+        _compare(solo, launched, tol=TOL_MIXED, what="whole-step mixed vs launched")

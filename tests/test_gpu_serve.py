@@ -32,14 +32,15 @@ def _requests(precision, n_steps, tol=1e-6):
     return specs
 
 
+@pytest.mark.parametrize("step_kernel", [wl.STEP_AUTO, wl.STEP_LAUNCHED])
 @pytest.mark.parametrize("precision", [wl.MIXED, wl.FP64])
-def test_alone_equals_in_the_mix(precision):
+def test_alone_equals_in_the_mix(precision, step_kernel):
     import torch
     from paper_1207_1571_amd import fvm
     from paper_1207_1571_amd.serve import GpuBackend, Request, Server
 
     n_steps = 6
-    specs = _requests(precision, n_steps)
+    specs = [s.with_(step_kernel=step_kernel) for s in _requests(precision, n_steps)]
     alone = {}
     for rid, spec in enumerate(specs):
         _say(f"alone rid={rid} N={spec.mesh.n_cells} precision={precision}")

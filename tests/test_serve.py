@@ -235,3 +235,95 @@ def test_stream_ending_with_a_rejected_request():
     be = FakeBackend(clk, bytes_per_cell=1000)
     res = _server(be, clk, 10_000).run([Request(0, 0.0, _spec(5), 2), Request(1, 0.5, _spec(1000), 1)])
     assert sorted((r.rid, r.status) for r in res) == [(0, 0), (1, -2)]
+
+
+# ---------------------------------------------------------------- lanes
+
+import threading  # noqa: E402
+import time  # noqa: E402
+
+
+class LaneBackend:
+    """Two lanes ('small' below 500 cells, 'large' otherwise) advanced by
+    separate threads in real time; an advance sleeps `cost` seconds per
+    step.  Records residency and which lanes overlapped in time."""
+
+    LANES = {"small": (4, 3), "large": (2, 2)}
+
+    def __init__(self, cost=2e-3, bytes_per_cell=100, fail_rid=None, raise_rid=None):
+        self.cost, self.bpc, self.fail_rid, self.raise_rid = cost, bytes_per_cell, fail_rid, raise_rid
+        self.mu = threading.Lock()
+        self.resident = {}
+        self.max_bytes = 0
+        self.running = {"small": 0, "large": 0}
+        self.overlap = False
+        self.groups = []
+
+    def lane_of(self, spec):
+        return "small" if spec.mesh.n_cells < 500 else "large"
+
+    def footprint(self, spec):
+        return spec.mesh.n_cells * self.bpc
+
+    def create(self, spec):
+        case = object()
+        with self.mu:
+            self.resident[id(case)] = (self.footprint(spec), spec)
+            self.max_bytes = max(self.max_bytes, sum(b for b, _ in self.resident.values()))
+        return case
+
+    def advance(self, cases, n_steps, lane):
+        with self.mu:
+            self.running[lane] += 1
+            self.overlap = self.overlap or all(v > 0 for v in self.running.values())
+            self.groups.append((lane, len(cases), n_steps))
+            specs = [self.resident[id(c)][1] for c in cases]
+        if any(getattr(s, "rid", None) == self.raise_rid for s in specs):
+            raise RuntimeError("device error")
+        time.sleep(self.cost * n_steps)
+        with self.mu:
+            self.running[lane] -= 1
+        return [{"p": [{"iters": 3}] * n_steps,
+                 "status": -3 if getattr(s, "rid", None) == self.fail_rid else 0} for s in specs]
+
+    def finish(self, case):
+        with self.mu:
+            del self.resident[id(case)]
+        return None
+
+
+def test_lanes_overlap_and_every_request_completes():
+    be = LaneBackend()
+    reqs = [Request(0, 0.0, _spec(2000, rid=0), 30)]
+    reqs += [Request(i, 0.005 * i, _spec(100 + i, rid=i), 6) for i in range(1, 9)]
+    reqs += [Request(9, 0.01, _spec(3000, rid=9), 8)]
+    res = {r.rid: r for r in Server(be, 10**9, slots=8).run(reqs)}
+    assert sorted(res) == list(range(10))
+    assert all(r.status == 0 for r in res.values())
+    assert be.overlap                       # both lanes had work on the device at once
+    # the small cases did not wait for the long large one
+    assert max(res[i].done_s for i in range(1, 9)) < res[0].done_s
+    assert {g[0] for g in be.groups} == {"small", "large"}
+    assert all(g[1] <= 4 and g[2] <= 3 for g in be.groups if g[0] == "small")
+    assert all(g[1] <= 2 and g[2] <= 2 for g in be.groups if g[0] == "large")
+    assert not be.resident
+    assert res[3].p_iters == 3 * 6
+
+
+def test_lanes_budget_rejections_and_failures():
+    be = LaneBackend(bytes_per_cell=1000, fail_rid=2)
+    reqs = [Request(i, 0.0, _spec(n, rid=i), 4) for i, n in enumerate([100, 200, 300, 5000, 150, 400])]
+    srv = Server(be, 700_000, slots=8)
+    res = {r.rid: r for r in srv.run(reqs)}
+    assert sorted(res) == list(range(6))
+    assert res[3].status == -2 and res[3].bytes == 0      # larger than the whole budget
+    assert res[2].status == -3                            # failed on the device, released
+    assert all(res[i].status == 0 for i in (0, 1, 4, 5))
+    assert be.max_bytes <= 700_000 and not be.resident
+
+
+def test_lanes_device_error_is_raised():
+    be = LaneBackend(raise_rid=1)
+    reqs = [Request(i, 0.0, _spec(100, rid=i), 3) for i in range(3)]
+    with pytest.raises(RuntimeError, match="device error"):
+        Server(be, 10**9).run(reqs)
