@@ -23,7 +23,8 @@
  *     memory; the library never allocates device memory: every case lives in
  *     the caller's workspace buffer.
  *   - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
- *     it; calls that return solver information synchronise on it.
+ *     it; calls that return solver information synchronise on it and return
+ *     once all of their work on it is complete.
  *   - All indices are in the caller's numbering: cells are never renumbered,
  *     faces are reordered internally and mapped back on output.
  *   - A handle is not thread-safe; distinct cases may run on distinct streams.

@@ -1044,6 +1044,7 @@ extern "C" fvm_status simple_iterate(fvm_case *c, int32_t max_iters, double res_
             info[0].u[2].res_initial <= res_tol && info[0].p[0].res_initial <= res_tol)
             break;
     }
+    if (last) HIPCHK(hipStreamSynchronize(s));
     if (iters_done) *iters_done = it;
     if (last) *last = info[0];
     return acc;
@@ -1173,6 +1174,9 @@ extern "C" fvm_status piso_step_batch(fvm_case *const *cases, int32_t n, int32_t
             idx = kidx;
         }
     }
+    // with an info record the call returns once all of its work is done,
+    // so the fields may be read on any stream afterwards
+    if (infos) HIPCHK(hipStreamSynchronize(s));
     // report in the caller's order
     int32_t all = FVM_OK;
     for (int i = 0; i < n; ++i) {

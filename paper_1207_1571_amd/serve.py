@@ -107,10 +107,15 @@ class GpuBackend:
         return self.fvm.workspace_bytes(m, self.fvm.opts_from_case(spec))
 
     def create(self, spec):
+        """The case's workspace and uploads are enqueued on the admission
+        stream; the call returns once they are complete, because the case is
+        then advanced on a lane's stream."""
         with self._mu:
             mesh = self._meshes.pop(id(spec), None)
         with self.torch.cuda.stream(self.stream):
-            return self.fvm.Case(spec, device=self.device, stream=self.stream, mesh=mesh)
+            case = self.fvm.Case(spec, device=self.device, stream=self.stream, mesh=mesh)
+        self.stream.synchronize()
+        return case
 
     def advance(self, cases: Sequence, n_steps: int, lane: Optional[str] = None) -> List[dict]:
         """piso_step_batch over sub-batches of cases that may share launches
@@ -169,7 +174,8 @@ class Server:
     def describe(self) -> dict:
         lanes = getattr(self.backend, "LANES", None) if getattr(self.backend, "lane_of", None) else None
         return dict(slots=self.slots, group=self.group, chunk=self.chunk,
-                    lanes={k: dict(group=g, chunk=c) for k, (g, c) in lanes.items()} if lanes else None)
+                    lanes={k: dict(group=min(g, self.group), chunk=min(c, self.chunk)) for k, (g, c) in lanes.items()}
+                    if lanes else None)
 
     def run(self, requests: Sequence[Request], log: Optional[Callable[[str], None]] = None) -> List[Result]:
         """Serve every request; one that cannot be admitted (invalid, larger
@@ -253,7 +259,7 @@ class Server:
     def _run_lanes(self, requests: Sequence[Request], log) -> List[Result]:
         """Admission on the calling thread; one worker thread per lane
         advances the lane's resident cases round-robin (the backend's group
-        size and step count per lane).  Shared state is guarded by one
+        size and step count per lane, capped by the server's).  Shared state is guarded by one
         condition variable; device work and case set-up run outside it."""
         self.rejections = []
         lanes = dict(self.backend.LANES)
@@ -281,7 +287,7 @@ class Server:
                     log(f"done rid={req.rid} N={req.spec.mesh.n_cells} latency={done - req.arrival_s:.3f}s")
 
         def worker(lane):
-            group, chunk = lanes[lane]
+            group, chunk = min(lanes[lane][0], self.group), min(lanes[lane][1], self.chunk)
             rr = 0
             try:
                 while True:

@@ -61,9 +61,9 @@ def test_alone_equals_in_the_mix(precision, step_kernel):
     groups = []
     orig_advance = be.advance
 
-    def advance(cases, steps):
+    def advance(cases, steps, lane=None):
         groups.append(tuple(id(c) for c in cases))
-        return orig_advance(cases, steps)
+        return orig_advance(cases, steps, lane)
 
     be.advance = advance
     res = Server(be, budget, slots=3, group=3, chunk=2).run(reqs)
