@@ -494,6 +494,7 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
     DevCase &d = c->d;
     const int np = c->npatch;
     std::vector<int32_t> uk(np), pk(np);
+    std::vector<int32_t> smode = m->sell_mode;   // uploaded below; alive until the final synchronisation
     std::vector<double> uv(3 * (size_t)np), pv(np);
     for (int p = 0; p < np; ++p) {
         uk[p] = c->patches[p].u_kind; pk[p] = c->patches[p].p_kind; pv[p] = c->patches[p].p_value;
@@ -518,7 +519,26 @@ extern "C" fvm_status fvm_case_create(const fvm_mesh *m, const fvm_case_opts *o,
         UPCHK(up(d.dl_pos, m->dl_pos, s)); UPCHK(up(d.dl_face, m->dl_face, s));
         UPCHK(up(d.du_pos, m->du_pos, s)); UPCHK(up(d.du_face, m->du_face, s));
     }
-    UPCHK(up(d.sell_mode, m->sell_mode, s)); UPCHK(up(d.sell_off, m->sell_off, s)); UPCHK(up(d.sell_mir, m->sell_mir, s));
+    {
+        // a regular slice none of whose cells has a fixed-pressure face or
+        // the reference pin has each diagonal equal to minus the sum of its
+        // row's coefficients (mode 2: the product derives it)
+        std::vector<int32_t> &mode = smode;
+        const int32_t ns = (int32_t)mode.size();
+        for (int32_t sl = 0; sl < ns; ++sl) {
+            if (mode[sl] != 0) continue;
+            bool plain = true;
+            const int32_t i0 = sl * kBlock, i1 = std::min(m->N, i0 + kBlock);
+            for (int32_t i = i0; i < i1 && plain; ++i) {
+                if (i == o->p_ref_cell && !m->has_fixed_p) plain = false;
+                for (int32_t k = m->bnd_start[i]; k < m->bnd_start[i + 1] && plain; ++k)
+                    plain = pk[m->bpatch[m->bnd_list[k]]] != FVM_BC_FIXED;
+            }
+            if (plain) mode[sl] = 2;
+        }
+        UPCHK(up(d.sell_mode, mode, s));
+    }
+    UPCHK(up(d.sell_off, m->sell_off, s)); UPCHK(up(d.sell_mir, m->sell_mir, s));
     UPCHK(up(d.sell_fe, m->sell_fe, s)); UPCHK(up(d.sell_col, m->sell_col, s));
     if (d.amg_nl > 0) {
         const AmgHost &A = mesh_amg(*m);

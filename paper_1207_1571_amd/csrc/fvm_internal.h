@@ -200,7 +200,9 @@ struct DevCase {
     int32_t *dl_pos, *dl_face, *du_pos, *du_face;
     double *dl_val, *du_val;
     double *dq, *yq, *zq;
-    // sliced-ELL copy of the pressure matrix (structure as in fvm_mesh)
+    // sliced-ELL copy of the pressure matrix (structure as in fvm_mesh;
+    // sell_mode 2 marks a regular slice whose diagonals the product derives
+    // from the coefficients: no fixed-pressure face, no reference pin)
     int32_t sell_W;
     int32_t *sell_mode, *sell_off, *sell_fe, *sell_col, *sell_mir;
     double *sell_val;                            // FP64 values (FP64 cases)

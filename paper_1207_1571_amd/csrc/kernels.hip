@@ -1277,30 +1277,70 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
     gT *__restrict__ val = sv + base;
     gT *__restrict__ p = (gT *)v.p;
     const double pi = (double)p[i];
-    double qa = kDiff ? 0.0 : (double)((gT *)v.diag)[i] * pi, so = 0.0;
-    if (((cint *)d.sell_mode)[sl] == 0) {
+    const int mode = ((cint *)d.sell_mode)[sl];
+    double qa, so = 0.0;
+    if (WC > 0 && mode != 1) {
+        // regular slice, slot count known: every load issued before use.
+        // Mode 2 (FP64): the diagonal is minus the row's coefficient sum,
+        // formed in the order the pressure assembly forms it (upper entries
+        // by ascending column, then lower ones), so it equals the stored
+        // diagonal bit for bit and is not read.
         cint *off = (cint *)(d.sell_off + (size_t)sl * W);
         cint *mir = (cint *)(d.sell_mir + (size_t)sl * W);
         const int last = d.N - 1;
-#pragma unroll 6
+        T a[WC > 0 ? WC : 1], pj[WC > 0 ? WC : 1];
+        int o[WC > 0 ? WC : 1];
+#pragma unroll
         for (int k = 0; k < W; ++k) {
-            const int j = min(max(i + off[k], 0), last);
+            o[k] = off[k];
+            const int j = min(max(i + o[k], 0), last);
             // a lower slot with a mirror reads a_ji from the neighbour's
             // upper slot (a stream read moments ago, still in cache) instead
             // of its own copy of the same value
             const int mk = mir[k];
             gT *src = mk < 0 ? val + (size_t)k * kBlock : sv + ((size_t)(j / kBlock) * W + mk) * kBlock + (j % kBlock);
-            const T a = *src;
-            qa += (double)a * (double)p[j];
-            if (kDiff) so += (double)a;
+            a[k] = *src;
+            pj[k] = p[j];
+        }
+        if (kDiff) qa = 0.0;
+        else if (mode == 2) {
+            double dg = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (o[k] > 0) dg += -(double)a[k];
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                if (o[k] < 0) dg += -(double)a[k];
+            qa = dg * pi;
+        } else qa = (double)((gT *)v.diag)[i] * pi;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            qa += (double)a[k] * (double)pj[k];
+            if (kDiff) so += (double)a[k];
         }
     } else {
-        gint *__restrict__ col = (gint *)(d.sell_col + base);
+        qa = kDiff ? 0.0 : (double)((gT *)v.diag)[i] * pi;
+        if (mode != 1) {
+            cint *off = (cint *)(d.sell_off + (size_t)sl * W);
+            cint *mir = (cint *)(d.sell_mir + (size_t)sl * W);
+            const int last = d.N - 1;
 #pragma unroll 6
-        for (int k = 0; k < W; ++k) {
-            const T a = val[(size_t)k * kBlock];
-            qa += (double)a * (double)p[col[(size_t)k * kBlock]];
-            if (kDiff) so += (double)a;
+            for (int k = 0; k < W; ++k) {
+                const int j = min(max(i + off[k], 0), last);
+                const int mk = mir[k];
+                gT *src = mk < 0 ? val + (size_t)k * kBlock : sv + ((size_t)(j / kBlock) * W + mk) * kBlock + (j % kBlock);
+                const T a = *src;
+                qa += (double)a * (double)p[j];
+                if (kDiff) so += (double)a;
+            }
+        } else {
+            gint *__restrict__ col = (gint *)(d.sell_col + base);
+#pragma unroll 6
+            for (int k = 0; k < W; ++k) {
+                const T a = val[(size_t)k * kBlock];
+                qa += (double)a * (double)p[col[(size_t)k * kBlock]];
+                if (kDiff) so += (double)a;
+            }
         }
     }
     const T q = kDiff ? (T)(qa + ((double)((gT *)v.exc)[i] - so) * pi) : (T)qa;
@@ -3501,7 +3541,7 @@ bool sell_w6(const BatchSet &bs)
 }
 
 // grid of the CG products: several slices per block
-constexpr int kSpmvGrid = SZ_CELL8;
+constexpr int kSpmvGrid = SZ_CELL4;
 
 void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s)
 {
