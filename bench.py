@@ -58,19 +58,40 @@ METRIC = "cell-updates/s + PCG SpMV HBM GB/s (FP64 vs mixed); serving p50/p99 la
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(cls: str, N: int, Fi: int, sell: dict | None = None) -> float:
+def diag_read_cells(spec, sell: dict) -> int:
+    """Cells whose FP64 CG product reads the stored diagonal: those of the
+    256-cell slices holding a cell with a fixed-pressure boundary face, or
+    the reference pin when no patch fixes the pressure, and those of the
+    slices with explicit columns (the other slices form each diagonal from
+    the row's coefficients)."""
+    import numpy as np
+    m = spec.mesh
+    N = m.n_cells
+    marked = np.zeros((N + 255) // 256, dtype=bool)
+    fixed = [k for k, bc in enumerate(spec.bcs) if bc.p_kind == 0]
+    for k in fixed:
+        st, sz = int(m.patch_start[k]), int(m.patch_size[k])
+        marked[np.asarray(m.owner[st:st + sz]) // 256] = True
+    if not fixed:
+        marked[spec.p_ref_cell // 256] = True
+    return int(min(N, marked.sum() * 256 + sell.get("n_explicit_slices", 0) * 256))
+
+
+def algorithmic_bytes(cls: str, N: int, Fi: int, sell: dict | None = None, diag_cells: int | None = None) -> float:
     """Bytes per launch that the operation itself must move.
 
-    Symmetric SpMV (the CG's q = A p on the sliced-ELL copy): diag (or the
-    FP32 row sums), x and y, one coefficient per internal face (the matrix
-    is symmetric; regular slices read the lower triangle through mirror
-    slots), and one int32 column index per entry of the slices that store
-    explicit columns (regular slices store none).  Other classes: every
-    cell-sized array read or written once, every face coefficient once, plus
-    two int32 per face where faces are walked through index lists."""
+    Symmetric SpMV (the CG's q = A p on the sliced-ELL copy): x and y, one
+    coefficient per internal face (the matrix is symmetric; regular slices
+    read the lower triangle through mirror slots), the diagonal where it is
+    read (FP64: diag_cells cells; the FP32 form always reads its row sums),
+    and one int32 column index per entry of the slices that store explicit
+    columns (regular slices store none).  Other classes: every cell-sized
+    array read or written once, every face coefficient once, plus two int32
+    per face where faces are walked through index lists."""
     ex = 4 * (sell["explicit_entries"] if sell else 2 * Fi)
+    dcells = N if diag_cells is None else diag_cells
     table = {
-        "pcg_spmv": 24 * N + 8 * Fi + ex,
+        "pcg_spmv": 16 * N + 8 * dcells + 8 * Fi + ex,
         "pcg_update": 56 * N,                      # x, p, r, q, diag in; x, r out
         "pcg_dir": 32 * N,                         # r, diag, p in; p out (Jacobi)
         "pcg_dir_dic": 24 * N,                     # z, p in; p out
@@ -94,11 +115,11 @@ def algorithmic_bytes(cls: str, N: int, Fi: int, sell: dict | None = None) -> fl
     return float(table.get(cls, 0))
 
 
-def cg_iteration_bytes(N: int, Fi: int, sell: dict, mixed: bool) -> float:
+def cg_iteration_bytes(N: int, Fi: int, sell: dict, mixed: bool, diag_cells: int | None = None) -> float:
     """One Jacobi CG iteration: direction, SpMV, update."""
     if mixed:
         return sum(algorithmic_bytes(c, N, Fi, sell) for c in ("pcg32_dir", "pcg32_spmv", "pcg32_update"))
-    return sum(algorithmic_bytes(c, N, Fi, sell) for c in ("pcg_dir", "pcg_spmv", "pcg_update"))
+    return sum(algorithmic_bytes(c, N, Fi, sell, diag_cells) for c in ("pcg_dir", "pcg_spmv", "pcg_update"))
 
 
 KERNEL_CLASSES = ["pcg_spmv", "pcg_update", "pcg_dir", "dic_setup", "dic_fwd", "dic_bwd", "bicg_spmv", "mom_face",
@@ -121,7 +142,7 @@ _P_WORK = ("pcg_spmv", "pcg_update", "pcg_dir", "dic_fwd", "dic_bwd", "pcg32_spm
 _U_WORK = ("bicg_spmv",)
 
 
-def profile_classes(fvm, case, steps, N, Fi, dic, sell):
+def profile_classes(fvm, case, steps, N, Fi, dic, sell, diag_cells=None):
     """Per-class device time of `steps` PISO steps (HIP events per launch).
 
     mean_us is over every launch (as a kernel trace reports it); us_per_work
@@ -142,7 +163,7 @@ def profile_classes(fvm, case, steps, N, Fi, dic, sell):
         work = min(n, p_work if cls in _P_WORK else u_work if cls in _U_WORK else n)
         mean_us = 1e3 * ms / n
         work_us = 1e3 * ms / max(work, 1)
-        b = algorithmic_bytes("pcg_dir_dic" if (cls == "pcg_dir" and dic) else cls, N, Fi, sell)
+        b = algorithmic_bytes("pcg_dir_dic" if (cls == "pcg_dir" and dic) else cls, N, Fi, sell, diag_cells)
         out[cls] = dict(total_ms=round(ms, 4), launches=n, work_launches=work, mean_us=round(mean_us, 3),
                         us_per_work=round(work_us, 3),
                         alg_bytes=b or None,
@@ -235,7 +256,9 @@ def cav200_section(fvm, wl, n, steps, warmup, profile_steps, log):
     mesh = fvm.Mesh(spec.mesh, spec.bcs)
     N, Fi = mesh.n_cells, mesh.n_internal
     sell = fvm.mesh_sell_info(mesh)
-    log(f"cav{n} mesh: {N} cells, {Fi} internal faces in {time.perf_counter() - t:.1f}s; sliced ELL {sell}")
+    dcells = diag_read_cells(spec, sell)
+    log(f"cav{n} mesh: {N} cells, {Fi} internal faces in {time.perf_counter() - t:.1f}s; sliced ELL {sell}; "
+        f"FP64 product reads the diagonal of {dcells} cells")
     if warmup > 0:
         w = fvm.Case(spec, mesh=mesh)
         w.piso(warmup)
@@ -256,11 +279,11 @@ def cav200_section(fvm, wl, n, steps, warmup, profile_steps, log):
         k = {}
         if profile_steps > 0:
             pc = fvm.Case(sp, mesh=mesh)
-            k = profile_classes(fvm, pc, profile_steps, N, Fi, False, sell)
+            k = profile_classes(fvm, pc, profile_steps, N, Fi, False, sell, dcells)
             del pc
         pre = "pcg32" if prec == wl.MIXED else "pcg"
         it_us = sum(k[c_]["us_per_work"] for c_ in (pre + "_dir", pre + "_spmv", pre + "_update") if c_ in k)
-        it_bytes = cg_iteration_bytes(N, Fi, sell, prec == wl.MIXED)
+        it_bytes = cg_iteration_bytes(N, Fi, sell, prec == wl.MIXED, dcells)
         ptot = int(sum(map(sum, p_iters)))
         spmv_cls = pre + "_spmv"
         tr = measured_traffic(spmv_cls, f"cav{n}") if name != "amg_fp64" else None
@@ -269,7 +292,7 @@ def cav200_section(fvm, wl, n, steps, warmup, profile_steps, log):
                  u_iters_first_last=[u_iters[0], u_iters[-1]],
                  ms_per_p_iteration=round(1e3 * wall / max(ptot, 1), 4),
                  spmv_us=k.get(spmv_cls, {}).get("us_per_work"),
-                 spmv_alg_bytes=algorithmic_bytes(spmv_cls, N, Fi, sell),
+                 spmv_alg_bytes=algorithmic_bytes(spmv_cls, N, Fi, sell, dcells),
                  spmv_alg_GBps=k.get(spmv_cls, {}).get("alg_GBps"),
                  spmv_counter_bytes=round(tr["bytes_per_working_launch"]) if tr else None,
                  spmv_counter_GBps=counter_GBps(tr),
@@ -286,7 +309,7 @@ def cav200_section(fvm, wl, n, steps, warmup, profile_steps, log):
                                       p=rel(fields["mixed"][1], fields["fp64"][1]))
     res["amg_vs_fp64_relL2"] = dict(U=rel(fields["amg_fp64"][0], fields["fp64"][0]),
                                     p=rel(fields["amg_fp64"][1], fields["fp64"][1]))
-    res["sliced_ell"] = sell
+    res["sliced_ell"] = dict(sell, fp64_diag_read_cells=dcells)
     res["workload"] = (f"cav{n}: 3-D lid-driven cavity {n}^3 hex cells, lexicographic, Re=1000, PISO dt=0.001, 2 "
                        f"correctors, {steps} steps from rest, PCG-Jacobi / PBiCG-Jacobi tol 1e-6 (normalised "
                        f"residual); mixed = FP32 inner (eta 1e-3) + FP64 refinement; amg_fp64 = FP64 with the "
@@ -379,7 +402,7 @@ def cav100_section(fvm, wl, steps, profile_steps, precond_compare, log):
         log(f"cav100 {name}: {out[name]['ms_per_step']} ms/step, {out[name]['p_iters_per_step']} CG iterations/step")
     if profile_steps > 0:
         pc_ = fvm.Case(spec, mesh=mesh)
-        k = profile_classes(fvm, pc_, profile_steps, N, Fi, True, sell)
+        k = profile_classes(fvm, pc_, profile_steps, N, Fi, True, sell, diag_read_cells(spec, sell))
         del pc_
         out["kernels"] = k
         tr = {cls: measured_traffic(cls, "cav100") for cls in ("dic_fwd", "dic_bwd")}
