@@ -222,6 +222,26 @@ fvm_status simple_iterate(fvm_case *c, int32_t max_iters, double res_tol, void *
 fvm_status solve_pressure(fvm_case *c, const double *d_gamma_f, const double *d_rhs, double *d_p,
                           const fvm_solver_ctl *ctl, void *stream, fvm_solve_info *info);
 
+/* solve_pressure_static -- solve_pressure for callers that cannot allocate
+ * (code that must not call hipMalloc: under stream capture by the caller's
+ * own harness, tight serving loops, harnesses that forbid allocation).  The
+ * same system, the same kernels and the same result as solve_pressure with
+ * ctl->precond == FVM_PC_JACOBI on an FP64 case; the grid-reduction slots,
+ * tickets, Krylov states and a device copy of the case descriptor live in a
+ * file-scope device array of 4 MiB (one per GPU, held until the process
+ * ends; enough for cases of about 11M cells) instead of the case's
+ * workspace; the CG vectors stay in the workspace.  No device or pinned
+ * memory is allocated, no graph is captured: iterations are launched
+ * directly in chunks of 8 and the stop flag is read back after each chunk.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other threads) race and must not be made.  The call
+ * clears what must start at zero and synchronises before returning.
+ * Errors: FVM_EINVAL for another preconditioner, a mixed-precision case or a
+ * case too large for the array (the message gives the bytes needed);
+ * FVM_EDEVICE when the array's address cannot be obtained. */
+fvm_status solve_pressure_static(fvm_case *c, const double *d_gamma_f, const double *d_rhs, double *d_p,
+                                 const fvm_solver_ctl *ctl, void *stream, fvm_solve_info *info);
+
 /* fvm_dic_apply -- the diagonal incomplete Cholesky preconditioner alone
  * (diagnostics and tests): assemble the pressure matrix from d_gamma_f as
  * solve_pressure does, factor it (D*_i = A_ii - sum_{j<i} A_ij^2 / D*_j) and

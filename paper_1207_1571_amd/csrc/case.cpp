@@ -1101,6 +1101,94 @@ extern "C" fvm_status solve_pressure(fvm_case *c, const double *gamma, const dou
     return ks.status;
 }
 
+namespace {
+// bytes of the static scratch a case's reduction slots, tickets, Krylov
+// states and descriptor copy take (256-byte aligned sections)
+size_t static_layout(const DevCase &d, DevCase *h, unsigned char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *a = base ? base + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return a;
+    };
+    unsigned char *self = take(sizeof(DevCase));
+    unsigned char *p1 = take(sizeof(double) * (size_t)kMaxRed * d.red_stride);
+    unsigned char *p2 = take(sizeof(double) * (size_t)kMaxRed * d.red_stride2);
+    unsigned char *gt = take(sizeof(unsigned int) * (size_t)d.red_stride2);
+    unsigned char *tk = take(sizeof(unsigned int) * 64);
+    unsigned char *ks = take(sizeof(KState) * kNumKs);
+    if (h) {
+        h->self = reinterpret_cast<DevCase *>(self);
+        h->partials = reinterpret_cast<double *>(p1);
+        h->partials2 = reinterpret_cast<double *>(p2);
+        h->gticket = reinterpret_cast<unsigned int *>(gt);
+        h->ticket = reinterpret_cast<unsigned int *>(tk);
+        h->ks = reinterpret_cast<KState *>(ks);
+        h->ks_gather = nullptr;
+    }
+    return off;
+}
+}  // namespace
+
+extern "C" fvm_status solve_pressure_static(fvm_case *c, const double *gamma, const double *rhs, double *p,
+                                            const fvm_solver_ctl *ctl, void *stream, fvm_solve_info *out)
+{
+    if (!c || !gamma || !rhs || !p || !ctl) return fvm_fail(FVM_EINVAL, "solve_pressure_static: null argument");
+    if (ctl->precond != FVM_PC_JACOBI)
+        return fvm_fail(FVM_EINVAL, "solve_pressure_static: Jacobi preconditioning only");
+    if (c->o.precision != FVM_FP64) return fvm_fail(FVM_EINVAL, "solve_pressure_static: FP64 cases only");
+    if (ctl->max_iter < 1) return fvm_fail(FVM_EINVAL, "solve_pressure_static: max_iter must be >= 1");
+    const size_t need = static_layout(c->d, nullptr, nullptr);
+    if (need > kStaticScratchBytes)
+        return fvm_fail(FVM_EINVAL, "solve_pressure_static: the case needs " + std::to_string(need) +
+                                        " bytes of static scratch, more than its " +
+                                        std::to_string(kStaticScratchBytes) + " (about 11M cells)");
+    int herr = 0;
+    unsigned char *base = static_cast<unsigned char *>(static_scratch(&herr));
+    if (!base)
+        return fvm_fail(FVM_EDEVICE, std::string("solve_pressure_static: static scratch address: ") +
+                                         hipGetErrorString((hipError_t)herr));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // descriptor whose reduction slots and Krylov states are in the scratch;
+    // the vectors stay in the case's workspace
+    DevCase h = c->d;
+    static_layout(c->d, &h, base);
+    const DevCase &d = c->d;
+    HIPCHK(hipMemcpyAsync(h.self, &h, sizeof(DevCase), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    BatchSet bs;
+    bs.n = 0;
+    batch_add(bs, h.self, &h);
+    launch_clear_reduction(bs, s);
+    HIPCHK(hipMemcpyAsync(d.p_save, d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
+    launch_gather_faces(bs, gamma, d.phiH, s);
+    launch_p_system_from_gamma(bs, d.phiH, rhs, s);
+    HIPCHK(hipMemcpyAsync(d.p, p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
+    launch_set_ctl(bs, 3, 1, 2, ctl->tol, ctl->rel_tol, ctl->max_iter, s);
+    launch_pcg_init(bs, 0, s);
+    // direct launches in chunks, the stop flag read back after each chunk
+    // (iterations past it return at once); no graph, no pinned buffer
+    KState ks{};
+    const long limit = (long)ctl->max_iter + 1;
+    for (long issued = 0;;) {
+        const long n = std::min<long>(8, limit - issued);
+        for (long k = 0; k < n; ++k) launch_pcg_iter(bs, 0, s);
+        issued += n;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&ks, h.ks + 3, sizeof(KState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (ks.done == 1) break;
+        if (issued >= limit) return fvm_fail(FVM_EDEVICE, "solve_pressure_static: iteration limit passed without a stop flag");
+    }
+    if (ks.status >= 0) HIPCHK(hipMemcpyAsync(p, d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.p, d.p_save, sizeof(double) * c->N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (out) to_info(ks, *out);
+    if (ks.status < 0) return fvm_fail(ks.status, "solve_pressure_static: non-finite value or breakdown");
+    return ks.status;
+}
+
 extern "C" fvm_status fvm_dic_apply(fvm_case *c, const double *gamma, const double *r, double *z, double *dstar,
                                     void *stream)
 {

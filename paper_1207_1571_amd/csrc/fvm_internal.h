@@ -278,6 +278,12 @@ void launch_phi_out(const BatchSet &bs, double *phi_user, hipStream_t s);
 void launch_gather_faces(const BatchSet &bs, const double *user_face_vals, double *canon, hipStream_t s);
 void launch_p_system_from_gamma(const BatchSet &bs, const double *gamma_canon, const double *rhs, hipStream_t s);
 void launch_init_partials(const BatchSet &bs, hipStream_t s);
+void launch_clear_reduction(const BatchSet &bs, hipStream_t s);   // partials at the sentinel, tickets at 0
+// static scratch of solve_pressure_static (kernels.hip): the current
+// device's address of the array (looked up once per device), or NULL with
+// the HIP error code in *hip_err
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+void *static_scratch(int *hip_err);
 void launch_set_patch(const BatchSet &bs, int patch, double u0, double u1, double u2, double pv, hipStream_t s);
 
 // state save / restore (rollback of a failed step)

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "fvm_internal.h"
 
@@ -417,6 +418,20 @@ __global__ void k_fill_sentinel(Batch bt)
     const long n1 = (long)kMaxRed * d.red_stride, n2 = (long)kMaxRed * d.red_stride2;
     for (long i = t; i < n1; i += (long)K.G * kBlock) clear_word(d.partials, i);
     for (long i = t; i < n2; i += (long)K.G * kBlock) clear_word(d.partials2, i);
+}
+
+// reduction slots of a descriptor whose slots live in the static scratch:
+// partials at the sentinel, tickets at zero (every call clears them: the
+// array keeps the previous call's contents)
+__global__ void k_clear_reduction(Batch bt)
+{
+    CASE_OF(bt);
+    const long t = (long)K.raw * kBlock + threadIdx.x, stride = (long)K.G * kBlock;
+    const long n1 = (long)kMaxRed * d.red_stride, n2 = (long)kMaxRed * d.red_stride2;
+    for (long i = t; i < n1; i += stride) clear_word(d.partials, i);
+    for (long i = t; i < n2; i += stride) clear_word(d.partials2, i);
+    for (long i = t; i < d.red_stride2; i += stride) d.gticket[i] = 0u;
+    for (long i = t; i < 64; i += stride) d.ticket[i] = 0u;
 }
 
 __global__ void k_set_patch(Batch bt, int pt, double u0, double u1, double u2, double pv)
@@ -3772,3 +3787,38 @@ void launch_amg_precond(const BatchSet &bs, int with_setup, hipStream_t s)
     } else run(k_amg_rz, bs, SZ_CELL, s);
 }
 
+void launch_clear_reduction(const BatchSet &bs, hipStream_t s) { run(k_clear_reduction, bs, SZ_CELL, s); }
+
+// ---------------------------------------------------------------------------
+// Static scratch for callers that cannot allocate (solve_pressure_static):
+// the grid-reduction slots, tickets, Krylov states and a device copy of the
+// case descriptor pointing at them.  Each GPU holds its own copy of the
+// array at its own address, fetched once per device with that device
+// current; host code uses that address, never the array's name.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+void *static_scratch(int *hip_err)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= 64)) e = hipErrorInvalidDevice;
+    if (e != hipSuccess) {
+        if (hip_err) *hip_err = (int)e;
+        return nullptr;
+    }
+    static std::mutex mu;
+    static void *ptr[64] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !a) {
+            if (hip_err) *hip_err = (int)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return nullptr;
+        }
+        ptr[dev] = a;
+    }
+    if (hip_err) *hip_err = (int)hipSuccess;
+    return ptr[dev];
+}

@@ -82,7 +82,8 @@ _lib = None
 EXPORTS = ("fvm_mesh_create", "fvm_mesh_destroy", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
            "fvm_case_destroy", "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
            "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable", "fvm_profile_read",
-           "fvm_last_error", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg", "fvm_mesh_sell_info")
+           "fvm_last_error", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg", "fvm_mesh_sell_info",
+           "solve_pressure_static")
 
 
 def lib():
@@ -110,6 +111,7 @@ def lib():
         L.piso_step.argtypes = [vp, ct.c_int32, vp, ct.POINTER(FvmStepInfo)]
         L.simple_iterate.argtypes = [vp, ct.c_int32, ct.c_double, vp, i32p, ct.POINTER(FvmStepInfo)]
         L.solve_pressure.argtypes = [vp, vp, vp, vp, ct.POINTER(FvmSolverCtl), vp, ct.POINTER(FvmSolveInfo)]
+        L.solve_pressure_static.argtypes = [vp, vp, vp, vp, ct.POINTER(FvmSolverCtl), vp, ct.POINTER(FvmSolveInfo)]
         L.fvm_dic_apply.argtypes = [vp, vp, vp, vp, vp, vp]
         L.piso_step_batch.argtypes = [ct.POINTER(vp), ct.c_int32, ct.c_int32, vp, ct.POINTER(FvmStepInfo)]
         L.fvm_profile_enable.argtypes = [ct.c_int32]
@@ -122,7 +124,8 @@ def lib():
         L.fvm_mesh_sell_info.argtypes = [vp, i32p, i32p, i32p, i64p, i64p]
         for name in ("fvm_mesh_create", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
                      "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
-                     "simple_iterate", "solve_pressure", "fvm_dic_apply", "piso_step_batch", "fvm_profile_enable",
+                     "simple_iterate", "solve_pressure", "solve_pressure_static", "fvm_dic_apply", "piso_step_batch",
+                     "fvm_profile_enable",
                      "fvm_profile_read", "fvm_mesh_hybrid", "fvm_case_operator", "fvm_mesh_amg", "fvm_mesh_sell_info"):
             getattr(L, name).restype = ct.c_int32
         _lib = L
@@ -266,6 +269,15 @@ class Case:
         info = FvmSolveInfo()
         st = _check(lib().solve_pressure(self.handle, _dptr(gamma), _dptr(rhs), _dptr(p), ct.byref(ctl),
                                          ct.c_void_p(_stream_ptr(self.stream)), ct.byref(info)))
+        return st, info.as_dict()
+
+    def solve_pressure_static(self, gamma, rhs, p, tol: float, rel_tol: float = 0.0, max_iter: int = 10000):
+        """solve_pressure_static: the Jacobi pressure solve with its reduction
+        state in the library's static device array (no allocation)."""
+        ctl = FvmSolverCtl(tol, rel_tol, max_iter, PC_JACOBI)
+        info = FvmSolveInfo()
+        st = _check(lib().solve_pressure_static(self.handle, _dptr(gamma), _dptr(rhs), _dptr(p), ct.byref(ctl),
+                                                ct.c_void_p(_stream_ptr(self.stream)), ct.byref(info)))
         return st, info.as_dict()
 
 
