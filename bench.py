@@ -37,7 +37,9 @@ Also reported on the same JSON line:
                 steady SIMPLE on the jittered duct to initial residuals of
                 1e-6, the transient pipe with its time-dependent inlet;
   serving       continuous batching of the 512-request stream (a stated
-                number of PISO steps per request), FP64 and mixed: p50/p99;
+                number of PISO steps per request), FP64 and mixed: p50/p99
+                (--serving-only runs this section alone, e.g. with the
+                configuration's 200 steps per request);
   layouts       the assembly operators one at a time in the solver's layout
                 and in the paper's hybrid ELL + J + CRS layout, normalised by
                 each layout's SMVP as in the paper's Table 3.
@@ -563,7 +565,7 @@ def layout_section(fvm, wl, log, reps=20):
     return out
 
 
-def serve_section(fvm, wl, n_requests, n_steps, log):
+def serve_section(fvm, wl, n_requests, n_steps, log, precisions=("fp64", "mixed")):
     """Serving stream (cavity/duct cases, cube side log-uniform 16..96,
     Re U(10, 1000), Poisson arrivals at 40 req/s), `n_requests` requests of
     `n_steps` PISO steps, run once in FP64 and once mixed: p50 / p99 time
@@ -578,6 +580,8 @@ def serve_section(fvm, wl, n_requests, n_steps, log):
                         f"configuration names 200), tol 1e-6, Jacobi",
                budget_bytes=budget, steps_per_request=n_steps)
     for name, prec in (("fp64", wl.FP64), ("mixed", wl.MIXED)):
+        if name not in precisions:
+            continue
         t = time.perf_counter()
         specs = [wl.serve_case(r, precision=prec) for r in reqs]
         log(f"serve {name}: {len(specs)} case meshes in {time.perf_counter() - t:.1f}s")
@@ -589,7 +593,7 @@ def serve_section(fvm, wl, n_requests, n_steps, log):
             if done[0] % 32 == 0:
                 log(f"serve {name}: {done[0]} requests done ({msg})")
 
-        srv = Server(be, budget, slots=32, group=32, chunk=20)
+        srv = Server(be, budget, slots=64, group=32, chunk=40)
         res = srv.run([Request(r.rid, r.arrival_s, s, r.n_steps) for r, s in zip(reqs, specs)], log=progress)
         torch.cuda.synchronize()
         sm = summarize(res)
@@ -618,6 +622,8 @@ def main():
     ap.add_argument("--tp-steps", type=int, default=10, help="PISO steps of the tp1M transient pipe section (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=512, help="requests of the serving section (0: skip)")
     ap.add_argument("--serve-steps", type=int, default=20, help="PISO steps per serving request")
+    ap.add_argument("--serving-only", choices=["fp64", "mixed", "both"], default=None,
+                    help="run only the serving stream (in that precision) and print its JSON section")
     ap.add_argument("--no-layouts", dest="layouts", action="store_false",
                     help="skip the face-major vs hybrid layout operator comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -637,6 +643,11 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    if args.serving_only:
+        precs = ("fp64", "mixed") if args.serving_only == "both" else (args.serving_only,)
+        serving = serve_section(fvm, wl, args.serve_requests, args.serve_steps, log, precs)
+        print(json.dumps({"serving": serving}), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

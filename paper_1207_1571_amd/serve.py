@@ -69,7 +69,7 @@ class GpuBackend:
     to price a request is kept and reused when the request is admitted."""
 
     # lane -> (cases per advance, steps per advance)
-    LANES = {"solo": (32, 20), "launched": (16, 10)}
+    LANES = {"solo": (32, 40), "launched": (32, 20)}
 
     def __init__(self, device="cuda", keep_fields: bool = False, lanes: bool = True):
         import torch
