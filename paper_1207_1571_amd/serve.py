@@ -391,4 +391,5 @@ def summarize(results: Sequence[Result]) -> dict:
                 mean_s=float(lat.mean()), max_s=float(lat.max()), makespan_s=float(span),
                 cases_per_s=float(len(results) / span) if span > 0 else None,
                 cell_updates_per_s=float(cu / span) if span > 0 else None,
-                failed=int(sum(1 for r in results if r.status < 0)))
+                failed=int(sum(1 for r in results if r.status < 0)),
+                failures=[dict(rid=r.rid, n_cells=r.n_cells, status=r.status) for r in results if r.status < 0])
