@@ -867,6 +867,17 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
             record_iters(g, res, 4, 3, 2);
             launch_mx_correct_resid(bs, 0, s);
         }
+        // components whose FP32 inner solve broke down continue as FP64
+        // BiCG solves from their current iterate
+        bool fb = false;
+        for (int i = 0; i < g.n(); ++i)
+            for (int k = 0; k < 3; ++k) fb = fb || res[(size_t)i * kNumKs + k].status == kStatusFallback;
+        if (fb) {
+            launch_bicg_fallback(bs, s);
+            st = iterate_until_done(g, 0, 3, predicted_iters(g, kind), max_iter + 1, 0,
+                                    [&](hipStream_t st_, long) { launch_bicg_iter(bs, st_); }, res);
+            if (st != FVM_OK) return st;
+        }
     }
     record_iters(g, res, first, count, kind);
     return FVM_OK;

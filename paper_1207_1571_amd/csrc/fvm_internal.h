@@ -137,6 +137,11 @@ struct KState {
     int32_t pad[2];
 };
 static_assert(sizeof(KState) == 128, "KState layout");
+// internal status of a mixed-precision momentum component whose FP32 inner
+// solve broke down (non-finite value or a zero denominator): the component
+// stops its refinement there and continues as an FP64 BiCG solve from the
+// current iterate (never reported: the FP64 solve sets the final status)
+constexpr int32_t kStatusFallback = 3;
 
 constexpr int kBlock = 256;
 constexpr int kGroup = 64;           // blocks per first-level reduction group
@@ -318,6 +323,7 @@ void launch_bicgstab_iter(const BatchSet &bs, hipStream_t s);
 // Krylov: pressure CG (FP64), Jacobi or DIC
 void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s);
 void launch_pcg_iter(const BatchSet &bs, int dic, hipStream_t s);
+void launch_bicg_fallback(const BatchSet &bs, hipStream_t s);   // restart kStatusFallback components as FP64 BiCG
 void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s);
 void launch_dic_reset(const BatchSet &bs, hipStream_t s);
 // mixed precision momentum (restarted FP32 BiCG inside FP64 refinement)

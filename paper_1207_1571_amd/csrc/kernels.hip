@@ -2015,6 +2015,7 @@ __global__ void __launch_bounds__(kBlock) k_mx_inner_init(Batch bt)
 }
 
 // x += e / s (FP64), for the components whose outer loop is still running
+// and whose inner solve did not break down (its e is then discarded)
 __global__ void k_mx_correct(Batch bt)
 {
     CASE_OF(bt);
@@ -2022,7 +2023,7 @@ __global__ void k_mx_correct(Batch bt)
     if (i >= d.N) return;
     for (int c = 0; c < 3; ++c) {
         const KState &o = d.ks[c];
-        if (o.done) continue;
+        if (o.done || d.ks[4 + c].status == FVM_ENUMERIC) continue;
         const double s = mx_scale(o, d.N);
         const long j = (long)c * d.N + i;
         d.U[j] += (double)d.f_x[j] / s;
@@ -2057,9 +2058,46 @@ __global__ void __launch_bounds__(kBlock) k_mx_resid(Batch bt)
             const KState &in = d.ks[4 + c];
             o.iters += in.iters;
             o.nres = tot[c] / o.nf;
-            if (in.status == FVM_ENUMERIC || !isfinite(o.nres)) set_done(o, FVM_ENUMERIC);
+            if (!isfinite(o.nres)) set_done(o, FVM_ENUMERIC);
+            else if (in.status == FVM_ENUMERIC) set_done(o, kStatusFallback);
             else if (o.nres <= o.tol_eff) set_done(o, FVM_OK);
             else if (o.iters >= o.max_iter) set_done(o, FVM_WARN_MAXITER);
+        }
+    }
+}
+
+// FP64 BiCG restart of the components marked kStatusFallback, from the
+// current iterate: r (already b - A x) is its own shadow, rho = z.r~
+__global__ void __launch_bounds__(kBlock) k_bicg_fallback(Batch bt)
+{
+    CASE_OF(bt);
+    int act[3];
+    for (int c = 0; c < 3; ++c) act[c] = d.ks[c].status == kStatusFallback;
+    if (!act[0] && !act[1] && !act[2]) return;
+    const Range rg = block_range(d.N, K);
+    const long N = d.N;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = rg.beg + threadIdx.x; i < rg.end; i += kBlock) {
+        const double dg = d.mdiag[i];
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const long j = c * N + i;
+            const double r = d.r[j];
+            d.rt[j] = r;
+            v[c] += (r / dg) * r;
+        }
+    }
+    __shared__ double tot[3];
+    if (reduce_last<3>(v, d, K, tot) && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            KState &s = d.ks[c];
+            s.first = 1;
+            s.beta = 0.0;
+            s.status = FVM_OK;
+            s.done = 0;
+            if (tot[c] == 0.0 || !isfinite(tot[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else s.rho = tot[c];
         }
     }
 }
@@ -2333,9 +2371,11 @@ __device__ void solo_momentum(const DevCase &d, SoloShared &sh, bool mixed)
         __syncthreads();
         solo_bicg_iterate<float>(d, sh, bi_arrays<float>(d), 4, (long)d.inner_max_iter + 1);
         // correction and outer residual (k_mx_correct, k_mx_resid)
+        int keep[3];
+        for (int c = 0; c < 3; ++c) keep[c] = act[c] && sh.ks[4 + c].status != FVM_ENUMERIC;
         SOLO_FOR(i, d.N)
             for (int c = 0; c < 3; ++c)
-                if (act[c]) d.U[(long)c * N + i] += (double)d.f_x[(long)c * N + i] / sc[c];
+                if (keep[c]) d.U[(long)c * N + i] += (double)d.f_x[(long)c * N + i] / sc[c];
         __syncthreads();
         double w[3] = {0, 0, 0};
         SOLO_FOR(i, d.N)
@@ -2354,12 +2394,43 @@ __device__ void solo_momentum(const DevCase &d, SoloShared &sh, bool mixed)
                 const KState &in = sh.ks[4 + c];
                 o.iters += in.iters;
                 o.nres = w[c] / o.nf;
-                if (in.status == FVM_ENUMERIC || !isfinite(o.nres)) set_done(o, FVM_ENUMERIC);
+                if (!isfinite(o.nres)) set_done(o, FVM_ENUMERIC);
+                else if (in.status == FVM_ENUMERIC) set_done(o, kStatusFallback);
                 else if (o.nres <= o.tol_eff) set_done(o, FVM_OK);
                 else if (o.iters >= o.max_iter) set_done(o, FVM_WARN_MAXITER);
             }
         __syncthreads();
     }
+    // components whose FP32 inner solve broke down continue in FP64
+    // (k_bicg_fallback, then the FP64 BiCG iterations)
+    int fb[3];
+    for (int c = 0; c < 3; ++c) fb[c] = sh.ks[c].status == kStatusFallback;
+    if (!fb[0] && !fb[1] && !fb[2]) return;
+    double v[3] = {0.0, 0.0, 0.0};
+    SOLO_FOR(i, d.N) {
+        const double dg = d.mdiag[i];
+        for (int c = 0; c < 3; ++c) {
+            if (!fb[c]) continue;
+            const long j = c * N + i;
+            const double r = d.r[j];
+            d.rt[j] = r;
+            v[c] += (r / dg) * r;
+        }
+    }
+    solo_sum<3>(v, sh);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) {
+            if (!fb[c]) continue;
+            KState &s = sh.ks[c];
+            s.first = 1;
+            s.beta = 0.0;
+            s.status = FVM_OK;
+            s.done = 0;
+            if (v[c] == 0.0 || !isfinite(v[c])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+            else s.rho = v[c];
+        }
+    __syncthreads();
+    solo_bicg_iterate<double>(d, sh, bi_arrays<double>(d), 0, (long)d.u_max_iter + 1);
 }
 
 // ---- pressure: Jacobi CG (k_cg_*, k_pcg_init; mixed: k_rr_*) -----------
@@ -3630,6 +3701,7 @@ void launch_mx_inner_iter(const BatchSet &bs, int, hipStream_t s)
     }
     run(k_bicg_update<float>, bs, SZ_CELL, s);
 }
+void launch_bicg_fallback(const BatchSet &bs, hipStream_t s) { run(k_bicg_fallback, bs, SZ_CELL, s); }
 void launch_mx_correct_resid(const BatchSet &bs, int, hipStream_t s)
 {
     run(k_mx_correct, bs, SZ_CELL, s);

@@ -437,6 +437,41 @@ def test_mixed_precision_error_at_benchmark_tolerance():
     assert eU <= TOL_MIXED and ep <= TOL_MIXED
 
 
+def _giant_cavity(precision, step_kernel):
+    """An 8^3 cavity of side 1e12 at Re 100 with dt = 1e-6: the momentum
+    diagonal V/dt (about 2e39) lies beyond the FP32 range while the pressure
+    system (coefficients about 1e5) does not, so the FP32 inner momentum
+    solve of the mixed path breaks down at its first step."""
+    from paper_1207_1571_amd import meshgen as mgen
+    L = 1e12
+    base = wl.cavity((8, 8, 8), Re=100.0, dt=1e-6, tol=1e-10, precision=precision)
+    mesh = mgen.box_mesh(8, 8, 8, lengths=(L, L, L))
+    assert mesh.patch_names == base.mesh.patch_names
+    return base.with_(mesh=mesh, nu=L / 100.0, step_kernel=step_kernel)
+
+
+@pytest.mark.parametrize("step_kernel", [wl.STEP_AUTO, wl.STEP_LAUNCHED])
+def test_mixed_momentum_falls_back_to_fp64(step_kernel):
+    """Mixed precision: a momentum component whose FP32 inner solve breaks
+    down continues as an FP64 BiCG solve from its current iterate (whole-step
+    kernel and launched phases), instead of failing the step: the result
+    agrees with the oracle within the mixed tolerance, and the momentum
+    solves reach the oracle's residuals."""
+    case = _giant_cavity(wl.MIXED, step_kernel)
+    v = case.mesh.V[0]
+    assert v / case.dt > 3.5e38 and case.mesh.n_cells <= 32768
+    _say(f"[fallback] giant cavity, step kernel {step_kernel}")
+    g = _gpu(case, 3)
+    o = _oracle(case.with_(precision=wl.FP64), 3)
+    assert g["st"] == 0 and o["st"] == 0
+    for su, so in zip(g["info"]["u"], o["info"]["u"]):
+        assert su["status"] == 0 and su["iters"] >= 1
+        assert su["res_final"] <= case.u_ctl.tol
+    _compare(g, o, tol=TOL_MIXED, what="mixed with FP64 momentum fallback")
+    f = _gpu(case.with_(precision=wl.FP64), 3)
+    _compare(f, o, what="FP64, same case")
+
+
 @pytest.mark.timeout(600)
 def test_cav200_settings_on_a_64_cube():
     """The 200^3 configuration's settings (lexicographic numbering, Re 1000,
