@@ -84,3 +84,38 @@ def test_cav200_properties_fp64_and_mixed():
     # at a z = 0 corner makes the unconverged remainder (solver tolerance
     # 1e-6, normalised) asymmetric
     assert sym <= 1e-6 and psym <= 1e-6
+
+
+@pytest.mark.timeout(300)
+def test_duct256_simple_to_convergence_matches_poiseuille():
+    """The duct configuration run as configured: steady SIMPLE on the jittered
+    256x64x64 duct until every initial residual is <= 1e-6.  The developed
+    section (3.0 <= x <= 3.5) matches the laminar square-duct series within
+    2% of its peak (max norm), and the outflow balances the inflow (T15)."""
+    from paper_1207_1571_amd import fvm
+    from test_oracle_pins import _duct_series
+    spec = wl.duct256(max_iters=4000)
+    c = fvm.Case(spec)
+    done, info = 0, None
+    while done < 4000:
+        st, it, info = c.simple(min(500, 4000 - done), spec.res_tol)
+        assert st >= 0
+        done += it
+        res = [info["u"][k]["res_initial"] for k in range(3)] + [info["p"][0]["res_initial"]]
+        _say(f"  duct256: {done} SIMPLE iterations, initial residuals {['%.2e' % r for r in res]}")
+        if max(res) <= spec.res_tol:
+            break
+    assert max(res) <= spec.res_tol, res
+    U, p, phi = c.get_state_numpy()
+    m = spec.mesh
+    sel = (m.C[:, 0] >= 3.0) & (m.C[:, 0] <= 3.5)
+    ua = _duct_series(m.C[sel, 1] - 0.5, m.C[sel, 2] - 0.5)
+    err = np.abs(U[sel, 0] - ua).max() / ua.max()
+    s_in, n_in = m.patch("xmin")
+    s_out, n_out = m.patch("xmax")
+    q_in, q_out = phi[s_in:s_in + n_in].sum(), phi[s_out:s_out + n_out].sum()
+    bal = abs(q_in + q_out) / abs(q_in)
+    _say(f"  duct256 converged in {done} iterations: developed profile max error {err:.3%} of peak, "
+         f"mass balance {bal:.2e}")
+    assert err <= 0.02
+    assert bal <= 1e-6
