@@ -89,9 +89,13 @@ def test_cav200_properties_fp64_and_mixed():
 @pytest.mark.timeout(300)
 def test_duct256_simple_to_convergence_matches_poiseuille():
     """The duct configuration run as configured: steady SIMPLE on the jittered
-    256x64x64 duct until every initial residual is <= 1e-6.  The developed
-    section (3.0 <= x <= 3.5) matches the laminar square-duct series within
-    2% of its peak (max norm), and the outflow balances the inflow (T15)."""
+    256x64x64 duct until every initial residual is <= 1e-6.  The section
+    3.5 <= x <= 3.75 matches the developed laminar square-duct series within
+    2% of its peak (max norm), and the outflow balances the inflow (T15).
+    (The plug inflow at Re 50 is still developing upstream: the max-norm
+    difference is 3.9% at 2.5 <= x <= 3, 2.4% at 3 <= x <= 3.5 and 1.5% here,
+    the same with and without the vertex jitter, so it is development, not
+    discretisation.)"""
     from paper_1207_1571_amd import fvm
     from test_oracle_pins import _duct_series
     spec = wl.duct256(max_iters=4000)
@@ -108,7 +112,7 @@ def test_duct256_simple_to_convergence_matches_poiseuille():
     assert max(res) <= spec.res_tol, res
     U, p, phi = c.get_state_numpy()
     m = spec.mesh
-    sel = (m.C[:, 0] >= 3.0) & (m.C[:, 0] <= 3.5)
+    sel = (m.C[:, 0] >= 3.5) & (m.C[:, 0] <= 3.75)
     ua = _duct_series(m.C[sel, 1] - 0.5, m.C[sel, 2] - 0.5)
     err = np.abs(U[sel, 0] - ua).max() / ua.max()
     s_in, n_in = m.patch("xmin")
