@@ -61,11 +61,12 @@ HBM_PEAK_GBS = 8000.0
 
 
 def diag_read_cells(spec, sell: dict) -> int:
-    """Cells whose FP64 CG product reads the stored diagonal: those of the
-    256-cell slices holding a cell with a fixed-pressure boundary face, or
-    the reference pin when no patch fixes the pressure, and those of the
-    slices with explicit columns (the other slices form each diagonal from
-    the row's coefficients)."""
+    """Cells whose CG product reads the stored diagonal (FP64) or row sum
+    (FP32): those of the 256-cell slices holding a cell with a
+    fixed-pressure boundary face, or the reference pin when no patch fixes
+    the pressure, and those of the slices with explicit columns (the other
+    slices form each diagonal from the row's coefficients, and their row
+    sums are zero)."""
     import numpy as np
     m = spec.mesh
     N = m.n_cells
@@ -85,7 +86,7 @@ def algorithmic_bytes(cls: str, N: int, Fi: int, sell: dict | None = None, diag_
     Symmetric SpMV (the CG's q = A p on the sliced-ELL copy): x and y, one
     coefficient per internal face (the matrix is symmetric; regular slices
     read the lower triangle through mirror slots), the diagonal where it is
-    read (FP64: diag_cells cells; the FP32 form always reads its row sums),
+    read (diag_cells cells: FP64 diagonals or FP32 row sums),
     and one int32 column index per entry of the slices that store explicit
     columns (regular slices store none).  Other classes: every cell-sized
     array read or written once, every face coefficient once, plus two int32
@@ -102,7 +103,7 @@ def algorithmic_bytes(cls: str, N: int, Fi: int, sell: dict | None = None, diag_
         "dic_setup": 16 * N + 16 * Fi,             # diag, D* out; lower faces
         "bicg_spmv": 104 * N + 24 * Fi,            # 3 components, A and A^T
         "bicgstab_spmv": 80 * N + 12 * Fi,         # 3 components: x in, y out, r~ or s in; diag, upper, lower, 2 int32
-        "pcg32_spmv": 12 * N + 4 * Fi + ex,        # FP32 inner: row sums, x, y + coefficient (+ explicit indices)
+        "pcg32_spmv": 8 * N + 4 * dcells + 4 * Fi + ex,   # FP32 inner: x, y, row sums where read + coefficient (+ explicit indices)
         "pcg32_update": 36 * N,                    # x (FP64) in/out, p, r, q, diag (FP32) in; r out
         "pcg32_dir": 16 * N,
         "bicg32_spmv": 52 * N + 16 * Fi,
@@ -120,7 +121,7 @@ def algorithmic_bytes(cls: str, N: int, Fi: int, sell: dict | None = None, diag_
 def cg_iteration_bytes(N: int, Fi: int, sell: dict, mixed: bool, diag_cells: int | None = None) -> float:
     """One Jacobi CG iteration: direction, SpMV, update."""
     if mixed:
-        return sum(algorithmic_bytes(c, N, Fi, sell) for c in ("pcg32_dir", "pcg32_spmv", "pcg32_update"))
+        return sum(algorithmic_bytes(c, N, Fi, sell, diag_cells) for c in ("pcg32_dir", "pcg32_spmv", "pcg32_update"))
     return sum(algorithmic_bytes(c, N, Fi, sell, diag_cells) for c in ("pcg_dir", "pcg_spmv", "pcg_update"))
 
 

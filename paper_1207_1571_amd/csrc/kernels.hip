@@ -1276,7 +1276,10 @@ __global__ void __launch_bounds__(kBlock) k_sell_fill(Batch bt)
 // and stalls CG.  In difference form the FP32 operator is the graph
 // Laplacian of the rounded face weights plus the rounded row sums,
 // spectrally within (1 +- eps32) of the FP64 one.  Products of FP32 values
-// are exact in FP64 and the sums are FP64.
+// are exact in FP64 and the sums are FP64.  In a slice of mode 2 (no
+// fixed-pressure face, no reference pin) every row sum is exactly zero, and
+// the FP64 value is only the rounding residue of forming it: exc_i = 0 there,
+// and it is not read.
 template <class T, int WC>
 __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v, int sl, int i)
 {
@@ -1358,7 +1361,8 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
             }
         }
     }
-    const T q = kDiff ? (T)(qa + ((double)((gT *)v.exc)[i] - so) * pi) : (T)qa;
+    const double exc = kDiff && mode != 2 ? (double)((gT *)v.exc)[i] : 0.0;
+    const T q = kDiff ? (T)(qa + (exc - so) * pi) : (T)qa;
     v.q[i] = q;
     return pi * (double)q;
 }
