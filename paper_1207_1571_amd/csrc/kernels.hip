@@ -1280,8 +1280,20 @@ __global__ void __launch_bounds__(kBlock) k_sell_fill(Batch bt)
 // fixed-pressure face, no reference pin) every row sum is exactly zero, and
 // the FP64 value is only the rounding residue of forming it: exc_i = 0 there,
 // and it is not read.
+// the sliced-ELL structure a product reads, held in registers by a kernel
+// that loops over slices (the case descriptor lives in memory the product's
+// stores could alias, so its fields would otherwise be reloaded per slice)
+struct SellView {
+    const int32_t *mode, *off, *mir, *col;
+    int N, W;
+};
+__device__ __forceinline__ SellView sell_view(const DevCase &d)
+{
+    return SellView{d.sell_mode, d.sell_off, d.sell_mir, d.sell_col, d.N, d.sell_W};
+}
+
 template <class T, int WC>
-__device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v, int sl, int i)
+__device__ __forceinline__ double spmv_cell(const SellView &sw, const CGArr<T> &v, int sl, int i)
 {
     // per-slice tables are read as uniform scalar loads, coefficients and
     // gathers as global-space vector loads (no flat-load waits)
@@ -1289,34 +1301,39 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
     typedef const __attribute__((address_space(1))) T gT;
     typedef const __attribute__((address_space(1))) int gint;
     constexpr bool kDiff = sizeof(T) == 4;
-    const int W = WC > 0 ? WC : d.sell_W;
+    const int W = WC > 0 ? WC : sw.W;
     const size_t base = (size_t)sl * W * kBlock + (i & (kBlock - 1));   // slices start at multiples of kBlock
     gT *__restrict__ sv = (gT *)v.sval;
     gT *__restrict__ val = sv + base;
     gT *__restrict__ p = (gT *)v.p;
     const double pi = (double)p[i];
-    const int mode = ((cint *)d.sell_mode)[sl];
+    const int mode = ((cint *)sw.mode)[sl];
     double qa, so = 0.0;
     if (WC > 0 && mode != 1) {
-        // regular slice, slot count known: every load issued before use.
+        // regular slice, slot count known: the slice's offsets and mirror
+        // slots are fetched together, then every load is issued before use.
         // Mode 2 (FP64): the diagonal is minus the row's coefficient sum,
         // formed in the order the pressure assembly forms it (upper entries
         // by ascending column, then lower ones), so it equals the stored
         // diagonal bit for bit and is not read.
-        cint *off = (cint *)(d.sell_off + (size_t)sl * W);
-        cint *mir = (cint *)(d.sell_mir + (size_t)sl * W);
-        const int last = d.N - 1;
+        cint *off = (cint *)(sw.off + (size_t)sl * W);
+        cint *mir = (cint *)(sw.mir + (size_t)sl * W);
+        const int last = sw.N - 1;
         T a[WC > 0 ? WC : 1], pj[WC > 0 ? WC : 1];
-        int o[WC > 0 ? WC : 1];
+        int o[WC > 0 ? WC : 1], m[WC > 0 ? WC : 1];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             o[k] = off[k];
+            m[k] = mir[k];
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
             const int j = min(max(i + o[k], 0), last);
             // a lower slot with a mirror reads a_ji from the neighbour's
             // upper slot (a stream read moments ago, still in cache) instead
             // of its own copy of the same value
-            const int mk = mir[k];
-            gT *src = mk < 0 ? val + (size_t)k * kBlock : sv + ((size_t)(j / kBlock) * W + mk) * kBlock + (j % kBlock);
+            gT *src = m[k] < 0 ? val + (size_t)k * kBlock
+                               : sv + ((size_t)(j / kBlock) * W + m[k]) * kBlock + (j % kBlock);
             a[k] = *src;
             pj[k] = p[j];
         }
@@ -1339,9 +1356,9 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
     } else {
         qa = kDiff ? 0.0 : (double)((gT *)v.diag)[i] * pi;
         if (mode != 1) {
-            cint *off = (cint *)(d.sell_off + (size_t)sl * W);
-            cint *mir = (cint *)(d.sell_mir + (size_t)sl * W);
-            const int last = d.N - 1;
+            cint *off = (cint *)(sw.off + (size_t)sl * W);
+            cint *mir = (cint *)(sw.mir + (size_t)sl * W);
+            const int last = sw.N - 1;
 #pragma unroll 6
             for (int k = 0; k < W; ++k) {
                 const int j = min(max(i + off[k], 0), last);
@@ -1352,7 +1369,7 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
                 if (kDiff) so += (double)a;
             }
         } else {
-            gint *__restrict__ col = (gint *)(d.sell_col + base);
+            gint *__restrict__ col = (gint *)(sw.col + base);
 #pragma unroll 6
             for (int k = 0; k < W; ++k) {
                 const T a = val[(size_t)k * kBlock];
@@ -1367,6 +1384,12 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
     return pi * (double)q;
 }
 
+template <class T, int WC>
+__device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v, int sl, int i)
+{
+    return spmv_cell<T, WC>(sell_view(d), v, sl, i);
+}
+
 // A block takes the slices of its range one after the other (one cell per
 // thread per slice), so its set-up (case descriptor, controls) and the grid
 // reduction at its end are paid once for several slices.  WC > 0: the slot
@@ -1379,10 +1402,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
     const CGArr<T> v = cg_arrays<T>(d, dic);
     if (v.ks->done) return;
     const Range rg = block_range(d.N, K);
+    const SellView sw = sell_view(d);
     double acc[1] = {0.0};
     for (int base = rg.beg; base < rg.end; base += kBlock) {
         const int i = base + threadIdx.x;
-        if (i < rg.end) acc[0] += spmv_cell<T, WC>(d, v, base / kBlock, i);
+        if (i < rg.end) acc[0] += spmv_cell<T, WC>(sw, v, base / kBlock, i);
     }
     __shared__ double tot[1];
     if (reduce_last<1>(acc, d, K, tot) && threadIdx.x == 0) {
