@@ -13,6 +13,7 @@
 // while chunk k+1 runs, so the GPU never waits for the host and the host
 // never synchronises per iteration.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -436,6 +437,19 @@ struct Group {
 
 thread_local Poller t_batch_poll;
 
+}  // namespace
+
+namespace {
+// a roctx range over one phase of the host driver (momentum assembly and
+// solve, pressure assembly and solve, corrections, whole steps): rocprofv3
+// --marker-trace shows where a step's time goes; without a tool attached a
+// range costs a function call
+struct Phase {
+    explicit Phase(const char *name) { roctxRangePushA(name); }
+    ~Phase() { roctxRangePop(); }
+    Phase(const Phase &) = delete;
+    Phase &operator=(const Phase &) = delete;
+};
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -900,11 +914,18 @@ void worst(int32_t &acc, int32_t s)
 // momentum matrix + predictor solve; mode 0 PISO, 1 SIMPLE
 fvm_status momentum_predictor(Group &g, int mode, std::vector<fvm_step_info> &info)
 {
-    launch_gradU(g.bs, g.s);
-    launch_mom_face(g.bs, g.s);
-    launch_mom_cell(g.bs, mode, g.s);
+    {
+        Phase ph("momentum assembly");
+        launch_gradU(g.bs, g.s);
+        launch_mom_face(g.bs, g.s);
+        launch_mom_cell(g.bs, mode, g.s);
+    }
     std::vector<KState> res;
-    fvm_status st = run_solve(g, 0, 0, nullptr, res);
+    fvm_status st;
+    {
+        Phase ph("momentum solve");
+        st = run_solve(g, 0, 0, nullptr, res);
+    }
     if (st != FVM_OK) return st;
     for (int i = 0; i < g.n(); ++i)
         for (int k = 0; k < 3; ++k) {
@@ -917,7 +938,11 @@ fvm_status momentum_predictor(Group &g, int mode, std::vector<fvm_step_info> &in
 fvm_status pressure_solve(Group &g, std::vector<fvm_step_info> &info)
 {
     std::vector<KState> res;
-    fvm_status st = run_solve(g, 1, 1, nullptr, res);
+    fvm_status st;
+    {
+        Phase ph("pressure solve");
+        st = run_solve(g, 1, 1, nullptr, res);
+    }
     if (st != FVM_OK) return st;
     for (int i = 0; i < g.n(); ++i) {
         const KState &k = res[(size_t)i * kNumKs + 3];
@@ -945,14 +970,18 @@ fvm_status piso_one(Group &g, std::vector<fvm_step_info> &info)
     if (!(g.n() == 1 && any_failed(info)))
         for (int corr = 0; corr < c0->o.n_corr; ++corr) {
             for (int k = 0; k <= c0->o.n_non_orth_corr; ++k) {
-                if (k == 0) launch_hbya(g.bs, 1, g.s);
-                else launch_gradp(g.bs, g.s);
-                launch_p_face(g.bs, g.s);
-                launch_p_cell(g.bs, g.s);
+                {
+                    Phase ph("pressure assembly");
+                    if (k == 0) launch_hbya(g.bs, 1, g.s);
+                    else launch_gradp(g.bs, g.s);
+                    launch_p_face(g.bs, g.s);
+                    launch_p_cell(g.bs, g.s);
+                }
                 st = pressure_solve(g, info);
                 if (st != FVM_OK) return st;
                 if (g.n() == 1 && any_failed(info)) return FVM_OK;
             }
+            Phase ph("corrections");
             launch_flux_corr(g.bs, g.s);
             launch_U_corr(g.bs, g.s);
         }
@@ -965,13 +994,17 @@ fvm_status simple_one(Group &g, std::vector<fvm_step_info> &info)
     info.assign(g.n(), fvm_step_info{});
     fvm_status st = momentum_predictor(g, 1, info);
     if (st != FVM_OK || any_failed(info)) return st;
-    for (auto *c : g.cs)
-        HIPCHK(hipMemcpyAsync(c->d.p_prev, c->d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, g.s));
-    launch_hbya(g.bs, 1, g.s);
-    launch_p_face(g.bs, g.s);
-    launch_p_cell(g.bs, g.s);
+    {
+        Phase ph("pressure assembly");
+        for (auto *c : g.cs)
+            HIPCHK(hipMemcpyAsync(c->d.p_prev, c->d.p, sizeof(double) * c->N, hipMemcpyDeviceToDevice, g.s));
+        launch_hbya(g.bs, 1, g.s);
+        launch_p_face(g.bs, g.s);
+        launch_p_cell(g.bs, g.s);
+    }
     st = pressure_solve(g, info);
     if (st != FVM_OK || any_failed(info)) return st;
+    Phase ph("corrections");
     launch_flux_corr(g.bs, g.s);
     launch_p_relax(g.bs, g.s);
     launch_U_corr(g.bs, g.s);
@@ -1005,6 +1038,7 @@ namespace {
 fvm_status piso_solo(Group &g, int32_t n_steps, fvm_step_info *infos)
 {
     const int n = g.n();
+    Phase ph("whole-step launch");
     if (n_steps > 0) launch_solo_piso(g.bs, n_steps, g.cs[0]->o.n_corr, g.s);
     HIPCHK(hipGetLastError());
     std::vector<KState> res;
@@ -1060,6 +1094,7 @@ extern "C" fvm_status simple_iterate(fvm_case *c, int32_t max_iters, double res_
     int32_t acc = FVM_OK, it = 0;
     std::vector<fvm_step_info> info(1, fvm_step_info{});
     for (it = 0; it < max_iters;) {
+        Phase ph("simple iteration");
         launch_save(g.bs, 0, s);
         fvm_status st = simple_one(g, info);
         if (st != FVM_OK) return st;
@@ -1270,6 +1305,7 @@ extern "C" fvm_status piso_step_batch(fvm_case *const *cases, int32_t n, int32_t
     std::vector<fvm_step_info> info;
     std::vector<fvm_step_info> last(n, fvm_step_info{});
     for (int32_t k = 0; k < n_steps; ++k) {
+        Phase ph("piso step");
         launch_save(g.bs, 0, s);
         fvm_status st = piso_one(g, info);
         if (st != FVM_OK) return st;

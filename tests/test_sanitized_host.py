@@ -41,7 +41,7 @@ def sanitized_libs(tmp_path_factory):
         objs.append(o)
     fvm_so = str(d / "libfvm_san.so")
     subprocess.check_call(["g++", "-shared", "-fPIC", "-fsanitize=address,undefined", "-o", fvm_so, KERNELS_OBJ, *objs,
-                           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
+                           "-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
     orc_so = str(d / "liboracle_san.so")
     subprocess.check_call(["gcc", "-std=c99", "-fPIC", "-shared", *SAN, "-o", orc_so,
                            os.path.join(ROOT, "oracle", "fvm_oracle.c"), "-lm"])
