@@ -594,7 +594,7 @@ def serve_section(fvm, wl, n_requests, n_steps, log, precisions=("fp64", "mixed"
             if done[0] % 32 == 0:
                 log(f"serve {name}: {done[0]} requests done ({msg})")
 
-        srv = Server(be, budget, slots=64, group=32, chunk=40)
+        srv = Server(be, budget, slots=256, group=32, chunk=40)
         res = srv.run([Request(r.rid, r.arrival_s, s, r.n_steps) for r, s in zip(reqs, specs)], log=progress)
         torch.cuda.synchronize()
         sm = summarize(res)

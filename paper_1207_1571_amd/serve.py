@@ -154,9 +154,17 @@ class Server:
     resident cases in groups of `group` cases, `chunk` steps at a time."""
 
     def __init__(self, backend, budget_bytes: int, slots: int = 32, group: int = 16, chunk: int = 10,
-                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
+                 order: str = "size"):
         if slots < 1 or group < 1 or chunk < 1:
             raise ValueError("slots, group and chunk must be positive")
+        if order not in ("size", "id"):
+            raise ValueError("order must be 'size' or 'id'")
+        # lanes walk their resident cases round-robin in this order: by cell
+        # count ("size"), so a group holds cases of similar size, whose
+        # solves end after similar iteration counts (a shared launch runs
+        # until its slowest case is done), or by request id
+        self.order = order
         self.backend = backend
         self.budget = int(budget_bytes)
         self.slots = int(slots)
@@ -173,7 +181,7 @@ class Server:
 
     def describe(self) -> dict:
         lanes = getattr(self.backend, "LANES", None) if getattr(self.backend, "lane_of", None) else None
-        return dict(slots=self.slots, group=self.group, chunk=self.chunk,
+        return dict(slots=self.slots, group=self.group, chunk=self.chunk, order=self.order,
                     lanes={k: dict(group=min(g, self.group), chunk=min(c, self.chunk)) for k, (g, c) in lanes.items()}
                     if lanes else None)
 
@@ -293,7 +301,9 @@ class Server:
                 while True:
                     with cv:
                         while True:
-                            ids = sorted(r for r, a in active.items() if a["lane"] == lane)
+                            ids = sorted((r for r, a in active.items() if a["lane"] == lane),
+                                         key=(lambda r: (active[r]["req"].spec.mesh.n_cells, r)) if self.order == "size"
+                                         else None)
                             if ids or state["stop"]:
                                 break
                             cv.wait(0.05)
