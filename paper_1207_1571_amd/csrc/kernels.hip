@@ -3656,6 +3656,7 @@ bool sell_w6(const BatchSet &bs)
 
 // grid of the CG products: several slices per block
 constexpr int kSpmvGrid = SZ_CELL4;
+constexpr int kWideDirCells = 4 << 20;   // 2048 blocks of 8 x 256 cells
 
 void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s)
 {
@@ -3696,7 +3697,13 @@ void launch_pcg_iter(const BatchSet &bs, int pc, hipStream_t s)
 {
     {
         Prof p("pcg_dir", s);
-        run(k_cg_dir<double, 4>, bs, SZ_CELL4, s, pc != 0 ? 1 : 0);
+        // 8 cells per thread pays once every case has enough blocks to fill
+        // the GPU at that width (an element-wise kernel: the result does
+        // not depend on the width)
+        bool wide = true;
+        for (int c = 0; c < bs.n; ++c) wide = wide && bs.host[c]->N >= kWideDirCells;
+        if (wide) run(k_cg_dir<double, 8>, bs, SZ_CELL8, s, pc != 0 ? 1 : 0);
+        else run(k_cg_dir<double, 4>, bs, SZ_CELL4, s, pc != 0 ? 1 : 0);
     }
     {
         Prof p("pcg_spmv", s);
@@ -3705,7 +3712,7 @@ void launch_pcg_iter(const BatchSet &bs, int pc, hipStream_t s)
     }
     {
         Prof p("pcg_update", s);
-        run(k_cg_update<2>, bs, SZ_CELL2, s, pc != 0 ? 1 : 0);
+        run(k_cg_update<4>, bs, SZ_CELL4, s, pc != 0 ? 1 : 0);
     }
     if (pc == 1) launch_dic_precond(bs, 0, s);
     else if (pc == 2) launch_amg_precond(bs, 0, s);
