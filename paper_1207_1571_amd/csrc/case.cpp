@@ -838,10 +838,10 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
         else if (amg) launch_amg_precond(bs, 1, s);
         const bool stab = kind == 0 && c0->o.u_solver == FVM_SOLVER_BICGSTAB;
         const int gkey = stab ? 2 : kind == 0 ? 0 : (dic ? 3 : amg ? 6 : 1);
-        st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 1, gkey, [&](hipStream_t st_, long) {
+        st = iterate_until_done(g, first, count, predicted_iters(g, kind), max_iter + 1, gkey, [&](hipStream_t st_, long k) {
             if (stab) launch_bicgstab_iter(bs, st_);
             else if (kind == 0) launch_bicg_iter(bs, st_);
-            else launch_pcg_iter(bs, pc, st_);
+            else launch_pcg_iter(bs, pc, (int)(k & 1), st_);
         }, res);
         if (st != FVM_OK) return st;
     } else if (kind == 1) {
@@ -856,7 +856,7 @@ fvm_status run_solve(Group &g, int kind, int ctl_src, const fvm_solver_ctl *ctl,
         launch_rr_start(bs, s);
         st = iterate_until_done(g, first, count, predicted_iters(g, kind), (max_iter + 2) * kReplaceEvery, 4,
                                 [&](hipStream_t st_, long k) {
-                                    launch_rr_iter(bs, st_);
+                                    launch_rr_iter(bs, (int)(k & 1), st_);
                                     if ((k + 1) % kReplaceEvery == 0) launch_rr_replace(bs, st_);
                                 }, res);
         if (st != FVM_OK) return st;
@@ -1219,7 +1219,7 @@ extern "C" fvm_status solve_pressure_static(fvm_case *c, const double *gamma, co
     const long limit = (long)ctl->max_iter + 1;
     for (long issued = 0;;) {
         const long n = std::min<long>(8, limit - issued);
-        for (long k = 0; k < n; ++k) launch_pcg_iter(bs, 0, s);
+        for (long k = 0; k < n; ++k) launch_pcg_iter(bs, 0, (int)(k & 1), s);
         issued += n;
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(&ks, h.ks + 3, sizeof(KState), hipMemcpyDeviceToHost, s));

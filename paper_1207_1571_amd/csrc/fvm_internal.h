@@ -322,7 +322,7 @@ void launch_bicg_iter(const BatchSet &bs, hipStream_t s);
 void launch_bicgstab_iter(const BatchSet &bs, hipStream_t s);
 // Krylov: pressure CG (FP64), Jacobi or DIC
 void launch_pcg_init(const BatchSet &bs, int dic, hipStream_t s);
-void launch_pcg_iter(const BatchSet &bs, int dic, hipStream_t s);
+void launch_pcg_iter(const BatchSet &bs, int dic, int parity, hipStream_t s);   // parity: iteration index & 1
 void launch_bicg_fallback(const BatchSet &bs, hipStream_t s);   // restart kStatusFallback components as FP64 BiCG
 void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s);
 void launch_dic_reset(const BatchSet &bs, hipStream_t s);
@@ -346,7 +346,7 @@ void launch_solo_piso(const BatchSet &bs, int n_steps, int n_corr, hipStream_t s
 constexpr int kSoloMaxCells = 1 << 15;
 constexpr int kSoloMaxCorr = kNumKs - 4;
 void launch_rr_start(const BatchSet &bs, hipStream_t s);
-void launch_rr_iter(const BatchSet &bs, hipStream_t s);
+void launch_rr_iter(const BatchSet &bs, int parity, hipStream_t s);
 void launch_rr_replace(const BatchSet &bs, hipStream_t s);
 
 // profiling

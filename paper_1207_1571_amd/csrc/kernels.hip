@@ -60,7 +60,14 @@ struct Blk {
     int G;     // blocks of the case
 };
 
-__device__ __forceinline__ Blk resolve(const Batch &b)
+// Blocks are dispatched in index order, round-robin over the 8 XCDs: block
+// raw runs on XCD raw % 8, so XCD x takes tiles [x G/8, (x+1) G/8) and keeps
+// the same cells in every kernel.  rev = 1 walks each XCD's tiles from the
+// last one down: a kernel that follows one walked the other way starts on
+// the cells its predecessor touched last, whose lines are the likeliest to
+// be still in the memory-side cache.  Only the time order changes: a tile
+// covers the same cells and its partial sums take the same slots.
+__device__ __forceinline__ Blk resolve(const Batch &b, int rev)
 {
     const int bid = blockIdx.x;
     int c = 0;
@@ -69,12 +76,20 @@ __device__ __forceinline__ Blk resolve(const Batch &b)
     k.d = b.dc[c];
     k.raw = bid - b.start[c];
     k.G = b.start[c + 1] - b.start[c];
-    k.lb = (k.G & 7) == 0 ? ((k.raw & 7) * (k.G >> 3) + (k.raw >> 3)) : k.raw;
+    if ((k.G & 7) == 0) {
+        const int per = k.G >> 3, r = k.raw >> 3;
+        k.lb = (k.raw & 7) * per + (rev ? per - 1 - r : r);
+    } else k.lb = rev ? k.G - 1 - k.raw : k.raw;
     return k;
 }
 
-#define CASE_OF(bt)             \
-    const Blk K = resolve(bt);  \
+#define CASE_OF(bt)                \
+    const Blk K = resolve(bt, 0);  \
+    const DevCase &d = *K.d
+
+// the same, walking the tiles in the direction rev
+#define CASE_OF_DIR(bt, rev)         \
+    const Blk K = resolve(bt, rev);  \
     const DevCase &d = *K.d
 
 struct Range {
@@ -122,6 +137,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (&lds)[NV][kWa
             for (int w = 1; w < kWaves; ++w) s += lds[k][w];
             v[k] = s;
         }
+}
+
+// Global-address-space view of a device pointer.  Accesses through it are
+// global rather than flat: a flat access also counts against the counter
+// that scalar-memory and LDS accesses share, so a wait for a scalar load or
+// an LDS value also waits for it, and a wait for one flat load is a wait for
+// all of them.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
 }
 
 // Slots hold the NaN sentinel while empty.  A device-scope release fence
@@ -1214,23 +1240,26 @@ __global__ void __launch_bounds__(kBlock) k_bs_update(Batch bt)
 
 // p = z + beta p (Jacobi z = r/diag; DIC z from the sweeps)
 template <class T, int U>
-__global__ void __launch_bounds__(kBlock) k_cg_dir(Batch bt, int dic)
+__global__ void __launch_bounds__(kBlock) k_cg_dir(Batch bt, int dic, int rev)
 {
-    CASE_OF(bt);
+    CASE_OF_DIR(bt, rev);
     const CGArr<T> v = cg_arrays<T>(d, dic);
     const KState &s = *v.ks;
     if (s.done) return;
     const bool first = s.first;
     const T beta = (T)s.beta;
     const Range rg = block_range(d.N, K);
-    T *__restrict__ p = v.p;
+    auto *__restrict__ p = gmem(v.p);
+    const auto *__restrict__ z = gmem(v.z);
+    const auto *__restrict__ r = gmem(v.r);
+    const auto *__restrict__ dg = gmem(v.diag);
     for (int base = rg.beg; base < rg.end; base += U * kBlock) {
         T zv[U], pv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = base + u * kBlock + threadIdx.x;
             if (i < rg.end) {
-                zv[u] = v.z ? (T)v.z[i] : v.r[i] / v.diag[i];
+                zv[u] = v.z ? (T)z[i] : r[i] / dg[i];
                 pv[u] = first ? (T)0 : p[i];
             }
         }
@@ -1396,9 +1425,9 @@ __device__ __forceinline__ double spmv_cell(const DevCase &d, const CGArr<T> &v,
 // count is fixed at compile time (6 on hex meshes): the loop is unrolled and
 // a slice's offsets and mirror slots are fetched together.
 template <class T, int WC>
-__global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
+__global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic, int rev)
 {
-    CASE_OF(bt);
+    CASE_OF_DIR(bt, rev);
     const CGArr<T> v = cg_arrays<T>(d, dic);
     if (v.ks->done) return;
     const Range rg = block_range(d.N, K);
@@ -1418,18 +1447,19 @@ __global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic)
 
 // FP64: x += alpha p, r -= alpha q, |r| -> stop test; Jacobi: rho, beta
 template <int U>
-__global__ void __launch_bounds__(kBlock) k_cg_update(Batch bt, int dic)
+__global__ void __launch_bounds__(kBlock) k_cg_update(Batch bt, int dic, int rev)
 {
-    CASE_OF(bt);
+    CASE_OF_DIR(bt, rev);
     const CGArr<double> v = cg_arrays<double>(d, dic);
     if (v.ks->done) return;
     const double al = v.ks->alpha;
     const Range rg = block_range(d.N, K);
     double acc[2] = {0.0, 0.0};
-    double *__restrict__ x = v.x;
-    double *__restrict__ rr = v.r;
-    const double *__restrict__ p = v.p;
-    const double *__restrict__ q = v.q;
+    auto *__restrict__ x = gmem(v.x);
+    auto *__restrict__ rr = gmem(v.r);
+    const auto *__restrict__ p = gmem((const double *)v.p);
+    const auto *__restrict__ q = gmem((const double *)v.q);
+    const auto *__restrict__ dg = gmem(v.diag);
     for (int base = rg.beg; base < rg.end; base += U * kBlock) {
         double xv[U], rv[U], pv[U], qv[U], dv[U];
 #pragma unroll
@@ -1437,7 +1467,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(Batch bt, int dic)
             const int i = base + u * kBlock + threadIdx.x;
             if (i < rg.end) {
                 xv[u] = x[i]; rv[u] = rr[i]; pv[u] = p[i]; qv[u] = q[i];
-                dv[u] = dic ? 1.0 : v.diag[i];
+                dv[u] = dic ? 1.0 : dg[i];
             }
         }
 #pragma unroll
@@ -1896,19 +1926,19 @@ __global__ void __launch_bounds__(kBlock) k_rr_start(Batch bt)
 // noise of relative size eps32, which A amplifies by up to its condition
 // number in the true residual.
 template <int U>
-__global__ void __launch_bounds__(kBlock) k_rr_update(Batch bt)
+__global__ void __launch_bounds__(kBlock) k_rr_update(Batch bt, int rev)
 {
-    CASE_OF(bt);
+    CASE_OF_DIR(bt, rev);
     if (d.ks[3].done) return;
     const double al = d.ks[3].alpha;
     const float alf = (float)al;
     const Range rg = block_range(d.N, K);
     double acc[2] = {0.0, 0.0};
-    double *__restrict__ x = d.p;
-    const float *__restrict__ p = d.f_p;
-    const float *__restrict__ q = d.f_q;
-    const float *__restrict__ dg = d.f_pdiag;
-    float *__restrict__ r = d.f_r;
+    auto *__restrict__ x = gmem(d.p);
+    const auto *__restrict__ p = gmem((const float *)d.f_p);
+    const auto *__restrict__ q = gmem((const float *)d.f_q);
+    const auto *__restrict__ dg = gmem((const float *)d.f_pdiag);
+    auto *__restrict__ r = gmem(d.f_r);
     for (int base = rg.beg; base < rg.end; base += U * kBlock) {
         double xv[U];
         float pv[U], qv[U], rv[U], dv[U];
@@ -3693,8 +3723,13 @@ void launch_dic_precond(const BatchSet &bs, int with_setup, hipStream_t s)
 
 void launch_dic_reset(const BatchSet &bs, hipStream_t s) { run(k_dic_reset, bs, SZ_CELL, s); }
 
-void launch_pcg_iter(const BatchSet &bs, int pc, hipStream_t s)
+void launch_pcg_iter(const BatchSet &bs, int pc, int parity, hipStream_t s)
 {
+    // Jacobi: the three kernels of an iteration alternate their direction,
+    // and iterations alternate which direction comes first, so each kernel
+    // walks the cells the other way from its predecessor (DIC and AMG put
+    // their own sweeps between the kernels: forward only)
+    const int rd = pc == 0 ? parity & 1 : 0, ru = pc == 0 ? 1 - rd : 0;
     {
         Prof p("pcg_dir", s);
         // 8 cells per thread pays once every case has enough blocks to fill
@@ -3702,17 +3737,17 @@ void launch_pcg_iter(const BatchSet &bs, int pc, hipStream_t s)
         // not depend on the width)
         bool wide = true;
         for (int c = 0; c < bs.n; ++c) wide = wide && bs.host[c]->N >= kWideDirCells;
-        if (wide) run(k_cg_dir<double, 8>, bs, SZ_CELL8, s, pc != 0 ? 1 : 0);
-        else run(k_cg_dir<double, 4>, bs, SZ_CELL4, s, pc != 0 ? 1 : 0);
+        if (wide) run(k_cg_dir<double, 8>, bs, SZ_CELL8, s, pc != 0 ? 1 : 0, rd);
+        else run(k_cg_dir<double, 4>, bs, SZ_CELL4, s, pc != 0 ? 1 : 0, rd);
     }
     {
         Prof p("pcg_spmv", s);
-        if (sell_w6(bs)) run(k_cg_spmv<double, 6>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0);
-        else run(k_cg_spmv<double, 0>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0);
+        if (sell_w6(bs)) run(k_cg_spmv<double, 6>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0, ru);
+        else run(k_cg_spmv<double, 0>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0, ru);
     }
     {
         Prof p("pcg_update", s);
-        run(k_cg_update<4>, bs, SZ_CELL4, s, pc != 0 ? 1 : 0);
+        run(k_cg_update<4>, bs, SZ_CELL4, s, pc != 0 ? 1 : 0, rd);
     }
     if (pc == 1) launch_dic_precond(bs, 0, s);
     else if (pc == 2) launch_amg_precond(bs, 0, s);
@@ -3749,20 +3784,22 @@ void launch_rr_start(const BatchSet &bs, hipStream_t s)
     run(k_rr_start, bs, SZ_CELL, s);
 }
 
-void launch_rr_iter(const BatchSet &bs, hipStream_t s)
+void launch_rr_iter(const BatchSet &bs, int parity, hipStream_t s)
 {
+    // directions alternate as in launch_pcg_iter
+    const int rd = parity & 1, ru = 1 - rd;
     {
         Prof p("pcg32_dir", s);
-        run(k_cg_dir<float, 4>, bs, SZ_CELL4, s, 0);
+        run(k_cg_dir<float, 4>, bs, SZ_CELL4, s, 0, rd);
     }
     {
         Prof p("pcg32_spmv", s);
-        if (sell_w6(bs)) run(k_cg_spmv<float, 6>, bs, kSpmvGrid, s, 0);
-        else run(k_cg_spmv<float, 0>, bs, kSpmvGrid, s, 0);
+        if (sell_w6(bs)) run(k_cg_spmv<float, 6>, bs, kSpmvGrid, s, 0, ru);
+        else run(k_cg_spmv<float, 0>, bs, kSpmvGrid, s, 0, ru);
     }
     {
         Prof p("pcg32_update", s);
-        run(k_rr_update<4>, bs, SZ_CELL4, s);
+        run(k_rr_update<4>, bs, SZ_CELL4, s, rd);
     }
 }
 
