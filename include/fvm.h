@@ -25,6 +25,9 @@
  *   - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
  *     it; calls that return solver information synchronise on it and return
  *     once all of their work on it is complete.
+ *   - Kernels run on the calling thread's current HIP device, which must be
+ *     the device of the case's workspace, of the device arrays and of the
+ *     stream.
  *   - All indices are in the caller's numbering: cells are never renumbered,
  *     faces are reordered internally and mapped back on output.
  *   - A handle is not thread-safe; distinct cases may run on distinct streams.
@@ -236,9 +239,11 @@ fvm_status solve_pressure(fvm_case *c, const double *d_gamma_f, const double *d_
  * Every call on a GPU shares that GPU's array: calls that overlap on one
  * GPU (other streams, other threads) race and must not be made.  The call
  * clears what must start at zero and synchronises before returning.
- * Errors: FVM_EINVAL for another preconditioner, a mixed-precision case or a
- * case too large for the array (the message gives the bytes needed);
- * FVM_EDEVICE when the array's address cannot be obtained. */
+ * Errors: FVM_EINVAL for another preconditioner, a mixed-precision case, a
+ * case too large for the array (the message gives the bytes needed) or a
+ * case whose workspace is not on the current device (the array used is the
+ * current device's); FVM_EDEVICE when the array's address cannot be
+ * obtained. */
 fvm_status solve_pressure_static(fvm_case *c, const double *d_gamma_f, const double *d_rhs, double *d_p,
                                  const fvm_solver_ctl *ctl, void *stream, fvm_solve_info *info);
 

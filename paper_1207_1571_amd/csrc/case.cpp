@@ -1190,6 +1190,11 @@ extern "C" fvm_status solve_pressure_static(fvm_case *c, const double *gamma, co
         return fvm_fail(FVM_EINVAL, "solve_pressure_static: the case needs " + std::to_string(need) +
                                         " bytes of static scratch, more than its " +
                                         std::to_string(kStaticScratchBytes) + " (about 11M cells)");
+    // the array used is the current device's: the case must live there
+    int cur = -1;
+    hipPointerAttribute_t pa{};
+    if (hipGetDevice(&cur) != hipSuccess || hipPointerGetAttributes(&pa, c->d.p) != hipSuccess || pa.device != cur)
+        return fvm_fail(FVM_EINVAL, "solve_pressure_static: the case's workspace is not on the current device");
     int herr = 0;
     unsigned char *base = static_cast<unsigned char *>(static_scratch(&herr));
     if (!base)
