@@ -175,10 +175,13 @@ fvm_status fvm_mesh_info(const fvm_mesh *mesh, int32_t *n_cells, int32_t *n_face
  * index), the entries (internal faces seen from one of their two cells) in
  * explicit slices, and the entries of regular slices read through a mirror
  * slot (their symmetric coefficient is taken from the neighbour's upper
- * slot instead of a second copy).  Measurement support: it gives the bytes a
- * product must move.  Any pointer may be NULL. */
+ * slot instead of a second copy), and the regular slices of the 7-point
+ * form (offsets -c, -b, -1, +1, +b, +c with b and c even, the three lower
+ * slots mirrored, every neighbour inside the mesh) on which the FP64
+ * product takes two cells per thread.  Measurement support: it gives the
+ * bytes a product must move.  Any pointer may be NULL. */
 fvm_status fvm_mesh_sell_info(const fvm_mesh *mesh, int32_t *w_slots, int32_t *n_slices, int32_t *n_explicit_slices,
-                              int64_t *explicit_entries, int64_t *mirrored_entries);
+                              int64_t *explicit_entries, int64_t *mirrored_entries, int32_t *n_7pt_slices);
 
 /* Exact device workspace size of a case of this mesh with these options
  * (admission control of many resident cases relies on it being exact). */

@@ -218,6 +218,7 @@ void plan(const fvm_mesh &m, const fvm_case_opts &o, Bump &b, DevCase &d, std::v
     {
         const size_t ns = (N + kBlock - 1) / kBlock, W = (size_t)m.sell_W;
         d.sell_W = m.sell_W;
+        d.sell_n7 = m.sell_n7;
         d.sell_mode = b.take<int32_t>(ns); d.sell_off = b.take<int32_t>(ns * W); d.sell_mir = b.take<int32_t>(ns * W);
         d.sell_fe = b.take<int32_t>(ns * W * kBlock); d.sell_col = b.take<int32_t>(ns * W * kBlock);
         if (mixed) d.f_sell_val = b.take<float>(ns * W * kBlock);

@@ -109,6 +109,10 @@ struct fvm_mesh {
     // every cell of the slice (upper slots, explicit slices, borders).
     int32_t sell_W = 0;
     std::vector<int32_t> sell_mode, sell_off, sell_fe, sell_col, sell_mir;
+    // regular slices of the 7-point form the FP64 product takes two cells
+    // per thread on: slots (-c, -b, -1, +1, +b, +c), b and c even, lower
+    // slots mirrored from the upper ones, every neighbour inside the mesh
+    int32_t sell_n7 = 0;
     mutable std::shared_ptr<AmgHost> amg;   // AMG hierarchy, built on first use
 };
 
@@ -208,7 +212,7 @@ struct DevCase {
     // sliced-ELL copy of the pressure matrix (structure as in fvm_mesh;
     // sell_mode 2 marks a regular slice whose diagonals the product derives
     // from the coefficients: no fixed-pressure face, no reference pin)
-    int32_t sell_W;
+    int32_t sell_W, sell_n7;
     int32_t *sell_mode, *sell_off, *sell_fe, *sell_col, *sell_mir;
     double *sell_val;                            // FP64 values (FP64 cases)
     float *f_sell_val;                           // FP32 values (mixed cases)

@@ -1445,6 +1445,182 @@ __global__ void __launch_bounds__(kBlock) k_cg_spmv(Batch bt, int dic, int rev)
     }
 }
 
+// G consecutive cells (i0 a multiple of G) of a 7-point regular slice per
+// thread: slots (-c, -b, -1, +1, +b, +c) with b and c multiples of G, the
+// three lower slots mirrored from the upper ones (5, 4, 3 for 0, 1, 2), and
+// every neighbour of the slice inside the mesh (the interior slices of a
+// lexicographic hex box).  Own slots, p, the diagonal, q and the neighbour
+// groups at offsets +-b and +-c move as single 16-byte accesses; the -1
+// neighbour of the first cell and the +1 neighbour of the last one are
+// single elements, the other +-1 neighbours are the group's own values.
+// Each cell's sum is formed exactly as spmv_cell forms it.
+template <class T, int G>
+struct Grp {
+    T e[G];
+};
+// G elements at a multiple of G, as one vector load
+template <class T, int G>
+__device__ __forceinline__ Grp<T, G> ld_grp(const __attribute__((address_space(1))) T *a)
+{
+    typedef T V __attribute__((ext_vector_type(G)));
+    const V w = *(const __attribute__((address_space(1))) V *)a;
+    Grp<T, G> r;
+#pragma unroll
+    for (int g = 0; g < G; ++g) r.e[g] = w[g];
+    return r;
+}
+
+// whether slice sl has the 7-point form above (uniform over the slice)
+template <int G>
+__device__ __forceinline__ bool slice_7pt(const SellView &sw, int sl)
+{
+    typedef const __attribute__((address_space(4))) int cint;
+    cint *op = (cint *)(sw.off + (size_t)sl * 6);
+    cint *mp = (cint *)(sw.mir + (size_t)sl * 6);
+    // every entry is loaded, then the tests are combined without branches
+    int o[6], m[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        o[k] = op[k];
+        m[k] = mp[k];
+    }
+    const int c = o[5], b = o[4];
+    return (o[2] == -1) & (o[3] == 1) & (o[1] == -b) & (o[0] == -c) & (b > 1) & (c > b) & (((b | c) & (G - 1)) == 0) &
+           (m[0] == 5) & (m[1] == 4) & (m[2] == 3) & (m[3] < 0) & (m[4] < 0) & (m[5] < 0) &
+           (sl * kBlock - c >= 0) & (sl * kBlock + kBlock - 1 + c <= sw.N - 1);
+}
+
+template <class T, int G>
+__device__ __forceinline__ double spmv_group(const SellView &sw, const CGArr<T> &v, int sl, int i0, int mode)
+{
+    typedef const __attribute__((address_space(4))) int cint;
+    typedef const __attribute__((address_space(1))) T gT;
+    constexpr int W = 6;
+    constexpr bool kDiff = sizeof(T) == 4;
+    gT *__restrict__ sv = (gT *)v.sval;
+    gT *__restrict__ val = sv + (size_t)sl * W * kBlock + (i0 & (kBlock - 1));
+    gT *__restrict__ p = (gT *)v.p;
+    cint *off = (cint *)(sw.off + (size_t)sl * W);
+    const int c = off[5], b = off[4];
+    // loads, all issued before the first use
+    const Grp<T, G> pp = ld_grp<T, G>(p + i0);
+    const Grp<T, G> o3 = ld_grp<T, G>(val + 3 * kBlock), o4 = ld_grp<T, G>(val + 4 * kBlock),
+                    o5 = ld_grp<T, G>(val + 5 * kBlock);
+    const int jc = i0 - c, jb = i0 - b, j1 = i0 - 1;
+    const Grp<T, G> m0 = ld_grp<T, G>(sv + ((size_t)(jc / kBlock) * W + 5) * kBlock + (jc & (kBlock - 1)));
+    const Grp<T, G> m1 = ld_grp<T, G>(sv + ((size_t)(jb / kBlock) * W + 4) * kBlock + (jb & (kBlock - 1)));
+    const T m2 = sv[((size_t)(j1 / kBlock) * W + 3) * kBlock + (j1 & (kBlock - 1))];
+    const Grp<T, G> xc = ld_grp<T, G>(p + jc), xb = ld_grp<T, G>(p + jb), yb = ld_grp<T, G>(p + i0 + b),
+                    yc = ld_grp<T, G>(p + i0 + c);
+    const T xm = p[j1], yp = p[i0 + G];
+    Grp<T, G> dg{}, ex{};
+    if (!kDiff && mode != 2) dg = ld_grp<T, G>((gT *)v.diag + i0);
+    if (kDiff && mode != 2) ex = ld_grp<T, G>((gT *)v.exc + i0);
+    // slot k: coefficient and neighbour value of cell i0 + g
+    T a[G][W], x[G][W];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        a[g][0] = m0.e[g];
+        a[g][1] = m1.e[g];
+        a[g][2] = g == 0 ? m2 : o3.e[g > 0 ? g - 1 : 0];
+        a[g][3] = o3.e[g];
+        a[g][4] = o4.e[g];
+        a[g][5] = o5.e[g];
+        x[g][0] = xc.e[g];
+        x[g][1] = xb.e[g];
+        x[g][2] = g == 0 ? xm : pp.e[g > 0 ? g - 1 : 0];
+        x[g][3] = g == G - 1 ? yp : pp.e[g < G - 1 ? g + 1 : 0];
+        x[g][4] = yb.e[g];
+        x[g][5] = yc.e[g];
+    }
+    double q[G], so[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        so[g] = 0.0;
+        if (kDiff) q[g] = 0.0;
+        else if (mode == 2) {
+            // upper slots (3, 4, 5), then lower ones (0, 1, 2)
+            double d = 0.0;
+#pragma unroll
+            for (int k = 3; k < W; ++k) d += -(double)a[g][k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d += -(double)a[g][k];
+            q[g] = d * (double)pp.e[g];
+        } else q[g] = (double)dg.e[g] * (double)pp.e[g];
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            q[g] += (double)a[g][k] * (double)x[g][k];
+            if (kDiff) so[g] += (double)a[g][k];
+        }
+    typedef T V __attribute__((ext_vector_type(G)));
+    V w;
+    double part = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double pi = (double)pp.e[g];
+        const T r = kDiff ? (T)(q[g] + ((mode != 2 ? (double)ex.e[g] : 0.0) - so[g]) * pi) : (T)q[g];
+        w[g] = r;
+        part += pi * (double)r;
+    }
+    *(__attribute__((address_space(1))) V *)(v.q + i0) = w;
+    return part;
+}
+
+// q = A p on slot count 6 with G cells per thread (16-byte groups): the
+// block's threads split into G parts, each taking every G-th slice of the
+// block's range; slices not of the 7-point form (explicit, partial,
+// boundary planes, other stencils) go cell by cell.  A case with fewer than
+// half of its slices of that form (random or RCM numbering, small boxes)
+// runs one cell per thread throughout (G cells of a thread would be G
+// lanes apart in its fallback).  FP64 takes pairs; the
+// FP32 product stays one cell per thread (groups of 2 or 4 floats measured
+// 3% and 12% slower: more registers per cell, fewer resident waves).
+template <class T, int G>
+__global__ void __launch_bounds__(kBlock) k_cg_spmv_grp(Batch bt, int dic, int rev)
+{
+    typedef const __attribute__((address_space(4))) int cint;
+    CASE_OF_DIR(bt, rev);
+    const CGArr<T> v = cg_arrays<T>(d, dic);
+    if (v.ks->done) return;
+    const Range rg = block_range(d.N, K);
+    const SellView sw = sell_view(d);
+    double acc[1] = {0.0};
+    if (2L * d.sell_n7 < (d.N + kBlock - 1) / kBlock) {
+        // most slices are not of the 7-point form: one cell per thread, as
+        // in k_cg_spmv (the choice is the case's own, so a case computes the
+        // same bits alone and in any batch)
+        for (int base = rg.beg; base < rg.end; base += kBlock) {
+            const int i = base + threadIdx.x;
+            if (i < rg.end) acc[0] += spmv_cell<T, 6>(sw, v, base / kBlock, i);
+        }
+    } else if (rg.beg < rg.end) {
+        constexpr int per = kBlock / G;   // threads per slice (whole waves)
+        const int sl_end = (rg.end + kBlock - 1) / kBlock;
+        const int u0 = G * (threadIdx.x & (per - 1));
+        const int sub = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / per));
+        for (int sl = rg.beg / kBlock + sub; sl < sl_end; sl += G) {
+            const int i0 = sl * kBlock + u0;
+            const int mode = ((cint *)sw.mode)[sl];
+            if (mode != 1 && (sl + 1) * kBlock <= rg.end && slice_7pt<G>(sw, sl))
+                acc[0] += spmv_group<T, G>(sw, v, sl, i0, mode);
+            else {
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    if (i0 + g < rg.end) acc[0] += spmv_cell<T, 6>(sw, v, sl, i0 + g);
+            }
+        }
+    }
+    __shared__ double tot[1];
+    if (reduce_last<1>(acc, d, K, tot) && threadIdx.x == 0) {
+        KState &s = *v.ks;
+        if (!(tot[0] > 0.0) || !isfinite(tot[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
+        else s.alpha = s.rho / tot[0];
+    }
+}
+
 // FP64: x += alpha p, r -= alpha q, |r| -> stop test; Jacobi: rho, beta
 template <int U>
 __global__ void __launch_bounds__(kBlock) k_cg_update(Batch bt, int dic, int rev)
@@ -3742,7 +3918,7 @@ void launch_pcg_iter(const BatchSet &bs, int pc, int parity, hipStream_t s)
     }
     {
         Prof p("pcg_spmv", s);
-        if (sell_w6(bs)) run(k_cg_spmv<double, 6>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0, ru);
+        if (sell_w6(bs)) run(k_cg_spmv_grp<double, 2>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0, ru);
         else run(k_cg_spmv<double, 0>, bs, kSpmvGrid, s, pc != 0 ? 1 : 0, ru);
     }
     {

@@ -115,6 +115,20 @@ void build_sell(fvm_mesh *m)
             if (ok) m->sell_mir[(size_t)s * W + k] = ka;
         }
     }
+    // slices of the 7-point form (the test the paired product makes per
+    // slice on the device)
+    m->sell_n7 = 0;
+    if (W == 6)
+        for (int32_t s = 0; s < ns; ++s) {
+            if (m->sell_mode[s] != 0) continue;
+            const int32_t *o = &m->sell_off[(size_t)s * 6], *mr = &m->sell_mir[(size_t)s * 6];
+            const int32_t b = o[4], c = o[5];
+            const int64_t lo = (int64_t)s * kBlock;
+            const bool ok = o[2] == -1 && o[3] == 1 && o[1] == -b && o[0] == -c && b > 1 && c > b &&
+                            ((b | c) & 1) == 0 && mr[0] == 5 && mr[1] == 4 && mr[2] == 3 && mr[3] < 0 && mr[4] < 0 &&
+                            mr[5] < 0 && lo - c >= 0 && lo + kBlock - 1 + c <= (int64_t)N - 1;
+            m->sell_n7 += ok ? 1 : 0;
+        }
 }
 
 }  // namespace
@@ -586,7 +600,7 @@ extern "C" fvm_status fvm_mesh_info(const fvm_mesh *m, int32_t *n_cells, int32_t
 
 extern "C" fvm_status fvm_mesh_sell_info(const fvm_mesh *m, int32_t *w_slots, int32_t *n_slices,
                                          int32_t *n_explicit_slices, int64_t *explicit_entries,
-                                         int64_t *mirrored_entries)
+                                         int64_t *mirrored_entries, int32_t *n_7pt_slices)
 {
     if (!m) return fvm_fail(FVM_EINVAL, "mesh: null handle");
     const int32_t W = m->sell_W, ns = (int32_t)m->sell_mode.size();
@@ -607,5 +621,6 @@ extern "C" fvm_status fvm_mesh_sell_info(const fvm_mesh *m, int32_t *w_slots, in
     if (n_explicit_slices) *n_explicit_slices = nx;
     if (explicit_entries) *explicit_entries = ex;
     if (mirrored_entries) *mirrored_entries = mir;
+    if (n_7pt_slices) *n_7pt_slices = m->sell_n7;
     return FVM_OK;
 }

@@ -121,7 +121,7 @@ def lib():
         L.fvm_case_operator.argtypes = [vp, ct.c_int32, vp, vp, vp]
         L.fvm_mesh_amg.argtypes = [vp, ct.c_int32, i32p, i32p, i32p, i32p, i32p, i32p]
         i64p = ct.POINTER(ct.c_int64)
-        L.fvm_mesh_sell_info.argtypes = [vp, i32p, i32p, i32p, i64p, i64p]
+        L.fvm_mesh_sell_info.argtypes = [vp, i32p, i32p, i32p, i64p, i64p, i32p]
         for name in ("fvm_mesh_create", "fvm_mesh_info", "fvm_case_workspace_bytes", "fvm_case_create",
                      "fvm_case_set_state", "fvm_case_get_state", "fvm_case_set_patch_value", "piso_step",
                      "simple_iterate", "solve_pressure", "solve_pressure_static", "fvm_dic_apply", "piso_step_batch",
@@ -283,11 +283,12 @@ class Case:
 
 def mesh_sell_info(mesh: Mesh) -> dict:
     """Structure of the sliced-ELL copy the CG's product reads."""
-    w, ns, nx = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    w, ns, nx, n7 = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32()
     ex, mir = ct.c_int64(), ct.c_int64()
-    _check(lib().fvm_mesh_sell_info(mesh.handle, ct.byref(w), ct.byref(ns), ct.byref(nx), ct.byref(ex), ct.byref(mir)))
+    _check(lib().fvm_mesh_sell_info(mesh.handle, ct.byref(w), ct.byref(ns), ct.byref(nx), ct.byref(ex), ct.byref(mir),
+                                    ct.byref(n7)))
     return dict(w_slots=w.value, n_slices=ns.value, n_explicit_slices=nx.value, explicit_entries=ex.value,
-                mirrored_entries=mir.value)
+                mirrored_entries=mir.value, n_7pt_slices=n7.value)
 
 
 def mesh_amg(mesh: Mesh):

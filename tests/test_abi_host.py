@@ -59,18 +59,22 @@ def test_sell_info_regular_and_explicit_slices():
     other slots than the interior slices' (-256, -16, -1, 1, 16, 256): its
     own in-layer lower entries (no lower slice at all) and slice 1's -1 and
     -16 entries (whose neighbours span slices 0 and 1) keep their own copies,
-    2 x 2 x 240 entries; every other internal face is read once.  A randomly
-    renumbered box stores explicit columns in every slice: two entries per
-    internal face."""
+    2 x 2 x 240 entries; every other internal face is read once.  The
+    7-point slices (all six offsets, the three lower slots mirrored, both
+    neighbouring layers inside the box) are therefore layers 2 to 14: layer
+    15 has no layer above it, and layer 1 reads its lower entries from layer
+    0, whose slots differ.  A randomly renumbered box stores explicit columns
+    in every slice: two entries per internal face, no 7-point slice."""
     m = _mesh(wl.cavity((16, 16, 16), Re=10.0, dt=0.01))
     si = fvm.mesh_sell_info(m)
     assert si["w_slots"] == 6 and si["n_slices"] == 16 and si["n_explicit_slices"] == 0
     assert si["explicit_entries"] == 0
     assert si["mirrored_entries"] == m.n_internal - 4 * 240
+    assert si["n_7pt_slices"] == 13
     r = _mesh(wl.cavity((16, 16, 16), Re=10.0, dt=0.01, perm_seed=3))
     si = fvm.mesh_sell_info(r)
     assert si["n_explicit_slices"] == 16 and si["explicit_entries"] == 2 * r.n_internal
-    assert si["mirrored_entries"] == 0
+    assert si["mirrored_entries"] == 0 and si["n_7pt_slices"] == 0
 
 
 def test_mesh_info_counts():
