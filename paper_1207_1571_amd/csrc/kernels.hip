@@ -1771,8 +1771,11 @@ __device__ __forceinline__ void dic_put(double *a, int i, double v)
 {
     unsigned long long b = (unsigned long long)__double_as_longlong(v);
     if (b == kSentinel) b = kQNaN;
-    __hip_atomic_store(reinterpret_cast<unsigned long long *>(a + i), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_store((gword *)(a + i), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+// the NaN sentinel through a global-space store
+__device__ __forceinline__ void clear_slot(double *a, long i) { *(gword *)(a + i) = kSentinel; }
 
 // hardware XCD (XCC) id of the executing wave
 __device__ __forceinline__ unsigned int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u; }
@@ -1833,11 +1836,19 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     const int q = chunk * kChunk + lane;          // processing position
     const bool live = q < n;
     const int fq = live ? (MODE == 2 ? n - 1 - q : q) : 0;   // level position
-    const int i = live ? d.lvl_cells[fq] : 0;
+    const int i = live ? gmem(d.lvl_cells)[fq] : 0;
     const int W = MODE == 2 ? d.dW_hi : d.dW_lo;
-    const int *__restrict__ DP = MODE == 2 ? d.du_pos : d.dl_pos;
-    const double *__restrict__ DV = MODE == 2 ? d.du_val : d.dl_val;
+    const auto *__restrict__ DP = gmem(MODE == 2 ? (const int *)d.du_pos : (const int *)d.dl_pos);
+    const auto *__restrict__ DV = gmem(MODE == 2 ? (const double *)d.du_val : (const double *)d.dl_val);
     double *const src = MODE == 0 ? d.dq : (MODE == 1 ? d.yq : d.zq);
+    // everything the publication needs is read from the case descriptor
+    // now: the descriptor lives in memory that the stores below could
+    // alias, so a field read after them would be a load between a value
+    // becoming ready and its publication
+    double *const dq = d.dq, *const yq = d.yq, *const zq = d.zq;
+    auto *const dstar = gmem(d.dstar);
+    auto *const zout = gmem(d.z);
+    unsigned int *const ticket = d.ticket;
     // all slots are loaded at once (independent loads); a cell's
     // dependencies fill slots 0..nd-1
     const bool fast = W <= D;
@@ -1858,6 +1869,13 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     } else if (live) {
         while (nd < W && DP[nd * N + fq] >= 0) ++nd;
     }
+    // the cell's own inputs (the diagonal or r, D*_i, y_i; r_i for r.z),
+    // produced by earlier launches, are read before any wait
+    double acc = 0.0;
+    if (live && MODE != 2) acc = MODE == 0 ? gmem(d.pdiag)[i] : gmem(d.r)[i];
+    const double dsi = (MODE != 0 && live) ? gmem(dq)[fq] : 1.0;
+    const double yi = (MODE == 2 && live) ? gmem(yq)[fq] : 0.0;
+    const double ri = (MODE == 2 && live) ? gmem(d.r)[i] : 0.0;
     // a wave whose lanes all depend only on positions inside the chunk (or on
     // nothing) has no reason to wait; the test is a max over the wave's lanes
     // (this form schedules better than a ballot).  Waves of the streaming
@@ -1885,11 +1903,6 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
     // past the gate the wave is near the completion front: it takes issue
     // priority over the waves still waiting at their gates
     __builtin_amdgcn_s_setprio(2);
-    double acc = 0.0;
-    if (live && MODE != 2) acc = MODE == 0 ? d.pdiag[i] : d.r[i];
-    const double dsi = (MODE != 0 && live) ? d.dq[fq] : 1.0;
-    const double yi = (MODE == 2 && live) ? d.yq[fq] : 0.0;
-    const double ri = (MODE == 2 && live) ? d.r[i] : 0.0;   // for r.z, loaded before the wait
     unsigned int missing = fast ? (nd >= 32 ? 0xffffffffu : ((1u << nd) - 1u)) : 0u;
     int k = 0;                // streaming path cursor
     double part = 0.0;
@@ -1938,24 +1951,24 @@ __device__ __forceinline__ double dic_chunk(const DevCase &d, int chunk)
                 }
             }
             if (ready) {
-                if (MODE == 0) { dic_put(d.dq, fq, acc); d.dstar[i] = acc; }
-                else if (MODE == 1) { dic_put(d.yq, fq, acc / dsi); clear_word(d.zq, fq); }
+                if (MODE == 0) { dic_put(dq, fq, acc); dstar[i] = acc; }
+                else if (MODE == 1) { dic_put(yq, fq, acc / dsi); clear_slot(zq, fq); }
                 else {
                     const double zi = yi - acc / dsi;
-                    dic_put(d.zq, fq, zi);
-                    d.z[i] = zi;
-                    clear_word(d.yq, fq);
+                    dic_put(zq, fq, zi);
+                    zout[i] = zi;
+                    clear_slot(yq, fq);
                     part = ri * zi;
                 }
                 fin = true;
             } else if (++spins > kSpinLimit) {
                 dic_put(src, fq, __longlong_as_double((long long)kQNaN));
-                if (MODE == 0) d.dstar[i] = __longlong_as_double((long long)kQNaN);
+                if (MODE == 0) dstar[i] = __longlong_as_double((long long)kQNaN);
                 if (MODE == 2) {
-                    d.z[i] = __longlong_as_double((long long)kQNaN);
+                    zout[i] = __longlong_as_double((long long)kQNaN);
                     part = __longlong_as_double((long long)kQNaN);
                 }
-                d.ticket[8] = 1u;
+                ticket[8] = 1u;
                 fin = true;
             }
         }
