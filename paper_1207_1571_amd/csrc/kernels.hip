@@ -2879,8 +2879,19 @@ __device__ __forceinline__ void worst_status(int32_t &acc, int32_t s)
 __global__ void __launch_bounds__(kSolo) k_solo_piso(Batch bt, int n_steps, int n_corr)
 {
     __shared__ SoloShared sh;
+    __shared__ DevCase sdc;
     if ((int)blockIdx.x >= bt.n) return;
-    const DevCase &d = *bt.dc[blockIdx.x];
+    // the case descriptor in LDS: the step reads its fields after its own
+    // stores throughout (the descriptor's memory could alias them), and from
+    // LDS such a re-read is an LDS access instead of a memory round trip
+    {
+        static_assert(sizeof(DevCase) % 4 == 0, "the descriptor is copied in words");
+        const unsigned int *src = reinterpret_cast<const unsigned int *>(bt.dc[blockIdx.x]);
+        unsigned int *dst = reinterpret_cast<unsigned int *>(&sdc);
+        for (int t = (int)threadIdx.x; t < (int)(sizeof(DevCase) / 4); t += kSolo) dst[t] = src[t];
+        __syncthreads();
+    }
+    const DevCase &d = sdc;
     const bool mixed = d.f_x != nullptr;
     const long N = d.N, F = d.F;
     int32_t worst = FVM_OK;
