@@ -1321,8 +1321,14 @@ __device__ __forceinline__ SellView sell_view(const DevCase &d)
     return SellView{d.sell_mode, d.sell_off, d.sell_mir, d.sell_col, d.N, d.sell_W};
 }
 
+// one row of the product: q_i (not stored) and p_i q_i
+template <class T>
+struct Row {
+    T q;
+    double pq;
+};
 template <class T, int WC>
-__device__ __forceinline__ double spmv_cell(const SellView &sw, const CGArr<T> &v, int sl, int i)
+__device__ __forceinline__ Row<T> spmv_row(const SellView &sw, const CGArr<T> &v, int sl, int i)
 {
     // per-slice tables are read as uniform scalar loads, coefficients and
     // gathers as global-space vector loads (no flat-load waits)
@@ -1409,8 +1415,15 @@ __device__ __forceinline__ double spmv_cell(const SellView &sw, const CGArr<T> &
     }
     const double exc = kDiff && mode != 2 ? (double)((gT *)v.exc)[i] : 0.0;
     const T q = kDiff ? (T)(qa + (exc - so) * pi) : (T)qa;
-    v.q[i] = q;
-    return pi * (double)q;
+    return Row<T>{q, pi * (double)q};
+}
+
+template <class T, int WC>
+__device__ __forceinline__ double spmv_cell(const SellView &sw, const CGArr<T> &v, int sl, int i)
+{
+    const Row<T> r = spmv_row<T, WC>(sw, v, sl, i);
+    v.q[i] = r.q;
+    return r.pq;
 }
 
 template <class T, int WC>
@@ -2683,10 +2696,19 @@ __device__ void solo_momentum(const DevCase &d, SoloShared &sh, bool mixed)
 // ---- pressure: Jacobi CG (k_cg_*, k_pcg_init; mixed: k_rr_*) -----------
 
 template <class T>
-__device__ __forceinline__ double solo_spmv_cell(const DevCase &d, const CGArr<T> &v, int i)
+__device__ __forceinline__ Row<T> solo_spmv_row(const DevCase &d, const CGArr<T> &v, int i)
 {
-    return d.sell_W == 6 ? spmv_cell<T, 6>(d, v, i / kBlock, i) : spmv_cell<T, 0>(d, v, i / kBlock, i);
+    const SellView sw = sell_view(d);
+    return d.sell_W == 6 ? spmv_row<T, 6>(sw, v, i / kBlock, i) : spmv_row<T, 0>(sw, v, i / kBlock, i);
 }
+
+// Cells per thread per round of the whole-step kernel's CG passes: a round
+// issues the loads of all its cells before the first store (the arrays are
+// not known to be distinct, so a store keeps later loads behind it, and one
+// cell at a time would pay a memory round trip per cell).  A thread still
+// takes cells i = tid, tid + kSolo, ... in that order, so the sums are
+// formed as before.
+constexpr int kSoloU = 4;
 
 // one FP64 or FP32 CG iteration on state s (dir, product, update of the
 // launched kernels); mixed: the FP32 recurrence with the FP64 solution
@@ -2696,13 +2718,45 @@ __device__ void solo_cg_iteration(const DevCase &d, SoloShared &sh, const CGArr<
     constexpr bool kMixed = sizeof(T) == 4;
     const bool first = s.first;
     const T beta = (T)s.beta;
-    SOLO_FOR(i, d.N) {
-        const T z = v.r[i] / v.diag[i];
-        v.p[i] = first ? z : z + beta * v.p[i];
+    const int N = d.N;
+    for (int b = (int)threadIdx.x; b < N; b += kSolo * kSoloU) {
+        T rv[kSoloU], dv[kSoloU], pv[kSoloU];
+#pragma unroll
+        for (int u = 0; u < kSoloU; ++u) {
+            const int i = b + u * kSolo;
+            if (i < N) {
+                rv[u] = v.r[i];
+                dv[u] = v.diag[i];
+                pv[u] = first ? (T)0 : v.p[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSoloU; ++u) {
+            const int i = b + u * kSolo;
+            if (i < N) {
+                const T z = rv[u] / dv[u];
+                v.p[i] = first ? z : z + beta * pv[u];
+            }
+        }
     }
     __syncthreads();
     double pq[1] = {0.0};
-    SOLO_FOR(i, d.N) pq[0] += solo_spmv_cell<T>(d, v, i);
+    for (int b = (int)threadIdx.x; b < N; b += kSolo * 2) {
+        Row<T> rw[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = b + u * kSolo;
+            if (i < N) rw[u] = solo_spmv_row<T>(d, v, i);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = b + u * kSolo;
+            if (i < N) {
+                v.q[i] = rw[u].q;
+                pq[0] += rw[u].pq;
+            }
+        }
+    }
     solo_sum<1>(pq, sh);
     if (threadIdx.x == 0) {
         if (!(pq[0] > 0.0) || !isfinite(pq[0])) { set_done(s, FVM_ENUMERIC); s.iters += 1; }
@@ -2712,22 +2766,36 @@ __device__ void solo_cg_iteration(const DevCase &d, SoloShared &sh, const CGArr<
     if (s.done) return;
     const double al = s.alpha;
     double acc[2] = {0.0, 0.0};
-    if (!kMixed) {
-        SOLO_FOR(i, d.N) {
-            d.p[i] += al * (double)v.p[i];
-            const double r = (double)v.r[i] - al * (double)v.q[i];
-            v.r[i] = (T)r;
-            acc[0] += fabs(r);
-            acc[1] += r * (r / (double)v.diag[i]);
+    for (int b = (int)threadIdx.x; b < N; b += kSolo * kSoloU) {
+        double xv[kSoloU];
+        T pv[kSoloU], rv[kSoloU], qv[kSoloU], dv[kSoloU];
+#pragma unroll
+        for (int u = 0; u < kSoloU; ++u) {
+            const int i = b + u * kSolo;
+            if (i < N) {
+                xv[u] = d.p[i];
+                pv[u] = v.p[i];
+                rv[u] = v.r[i];
+                qv[u] = v.q[i];
+                dv[u] = v.diag[i];
+            }
         }
-    } else {
-        const float alf = (float)al;
-        SOLO_FOR(i, d.N) {
-            d.p[i] = d.p[i] + al * (double)v.p[i];
-            const float ri = (float)v.r[i] - alf * (float)v.q[i];
-            v.r[i] = (T)ri;
-            acc[0] += fabs((double)ri);
-            acc[1] += (double)ri * (double)(ri / (float)v.diag[i]);
+#pragma unroll
+        for (int u = 0; u < kSoloU; ++u) {
+            const int i = b + u * kSolo;
+            if (i >= N) continue;
+            d.p[i] = xv[u] + al * (double)pv[u];
+            if (!kMixed) {
+                const double r = (double)rv[u] - al * (double)qv[u];
+                v.r[i] = (T)r;
+                acc[0] += fabs(r);
+                acc[1] += r * (r / (double)dv[u]);
+            } else {
+                const float ri = (float)rv[u] - (float)al * (float)qv[u];
+                v.r[i] = (T)ri;
+                acc[0] += fabs((double)ri);
+                acc[1] += (double)ri * (double)(ri / (float)dv[u]);
+            }
         }
     }
     solo_sum<2>(acc, sh);
