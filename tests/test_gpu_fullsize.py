@@ -6,7 +6,10 @@ compared element by element (same protocol as tests/test_gpu_parity.py).
 The 8M-cell cavity is checked through properties that hold at any size:
 the corrected flux is divergence-free to solver tolerance, the flow is
 mirror-symmetric about the mid-plane normal to the lid's side walls, and the
-mixed-precision result agrees with the FP64 one within 1e-6.
+mixed-precision result agrees with the FP64 one within 1e-6; its pressure
+CG, the path the benchmark times, is also compared value by value with the
+oracle over 8 iterations of a seeded system (the oracle takes seconds for
+that).
 """
 import sys
 
@@ -84,6 +87,44 @@ def test_cav200_properties_fp64_and_mixed():
     # at a z = 0 corner makes the unconverged remainder (solver tolerance
     # 1e-6, normalised) asymmetric
     assert sym <= 1e-6 and psym <= 1e-6
+
+
+@pytest.mark.timeout(300)
+def test_cav200_pressure_solve_against_oracle():
+    """The headline path itself at full size: the Jacobi pressure CG on the
+    8M-cell cavity (every product on the paired 7-point kernel, except the
+    slices of the first and last planes), 8 iterations from a seeded start
+    on a seeded system, against the oracle's 8 iterations: every one of the
+    8M values within the parity protocol's 1e-9 (relative L2) and the same
+    stopping status."""
+    import torch
+    from oracle import oracle as orc
+    from paper_1207_1571_amd import fvm
+    case = wl.cav200(n=200, n_steps=1)
+    m = case.mesh
+    mesh = fvm.Mesh(m, case.bcs)
+    si = fvm.mesh_sell_info(mesh)
+    assert 2 * si["n_7pt_slices"] >= si["n_slices"]
+    rng = np.random.default_rng(4)
+    gamma = rng.uniform(0.5, 2.0, m.n_faces)
+    rhs = rng.normal(size=m.n_cells)
+    rhs -= rhs.mean()
+    p0 = rng.normal(size=m.n_cells) * 0.1
+    _say("[cav200 solve] oracle, 8 CG iterations")
+    po = p0.copy()
+    st_o, info_o = orc.OracleCase(case).solve_pressure(gamma, rhs, po, 0.0, max_iter=8)
+    _say("[cav200 solve] GPU, 8 CG iterations")
+    c = fvm.Case(case, mesh=mesh)
+    pg = torch.from_numpy(p0.copy()).cuda()
+    st_g, info_g = c.solve_pressure(torch.from_numpy(gamma).cuda(), torch.from_numpy(rhs).cuda(), pg, 0.0,
+                                    max_iter=8)
+    pg = pg.cpu().numpy()
+    c.close()
+    err = _rel(pg, po)
+    _say(f"  status gpu {st_g} oracle {st_o}; iters {info_g['iters']} {info_o['iters']}; relL2 {err:.2e}, "
+         f"max |diff| {np.abs(pg - po).max():.2e}")
+    assert st_g == st_o and info_g["iters"] == info_o["iters"] == 8
+    assert err <= 1e-9
 
 
 @pytest.mark.timeout(300)
