@@ -641,3 +641,82 @@ def test_O12_normaliser_is_scale_and_shift_invariant():
     assert r0 == pytest.approx(np.abs(b - Ax).sum() / (np.abs(Ax).sum() + np.abs(b).sum()), rel=1e-13)
     assert orc.nres(own, nei, diag, off, off, b, x + 7.5) == pytest.approx(r0, rel=1e-11)
     assert orc.nres(own, nei, 3 * diag, 3 * off, 3 * off, 3 * b, x) == pytest.approx(r0, rel=1e-13)
+
+
+def _couette_startup(n, nu, dt, permute=None):
+    """Fluid at rest between a wall at y = 0 and a wall at y = 1 that starts
+    moving with U = (1, 0, 0): one cell across x and z, whose faces take no
+    part (EMPTY), so the PISO step reduces to the time-implicit diffusion of
+    u_x and the pressure stays at its reference level."""
+    m = mg.box_mesh(1, n, 1, lengths=(1.0 / n, 1.0, 1.0 / n))
+    if permute is not None:
+        m = mg.random_permutation(m, permute)
+    bcs = []
+    for side in m.patch_names:
+        if side == "ymin":
+            bcs.append(wl.PatchBC(wl.FIXED, wl.ZERO_GRAD))
+        elif side == "ymax":
+            bcs.append(wl.PatchBC(wl.FIXED, wl.ZERO_GRAD, (1.0, 0.0, 0.0)))
+        else:
+            bcs.append(wl.PatchBC(wl.EMPTY, wl.EMPTY))
+    return wl.CaseSpec(name="couette", mesh=m, bcs=bcs, nu=nu, dt=dt, p_ctl=wl.SolverCtl(1e-14),
+                       u_ctl=wl.SolverCtl(1e-14))
+
+
+@pytest.mark.parametrize("permute", [None, 5])
+def test_T18_impulsive_couette_is_implicit_euler_diffusion(permute):
+    """The time term and the wall diffusion (paper §3, PISO with Euler
+    implicit time steps): on the start-up Couette flow every step solves
+    (h/dt)(u' - u) = nu [(u'_(j+1) - u'_j) - (u'_j - u'_(j-1))]/h, the wall
+    neighbours at half a cell (u = 0 below, u = 1 above).  That tridiagonal
+    system is solved here with scipy's banded solver, step by step; the
+    oracle's velocity must equal it to rounding, with v, w and p zero."""
+    from scipy.linalg import solve_banded
+    n, nu, dt, K = 16, 0.3, 0.01, 12
+    spec = _couette_startup(n, nu, dt, permute)
+    oc = orc.OracleCase(spec)
+    st, _ = oc.piso(K)
+    assert st == 0
+    h = 1.0 / n
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -nu / h
+    ab[2, :-1] = -nu / h
+    ab[1] = h / dt + 2 * nu / h
+    ab[1, 0] += nu / h        # wall at half a cell: 2 nu / h towards it instead of nu / h
+    ab[1, -1] += nu / h
+    v = np.zeros(n)
+    for _ in range(K):
+        rhs = h / dt * v
+        rhs[-1] += 2 * nu / h * 1.0
+        v = solve_banded((1, 1), ab, rhs)
+    order = np.argsort(spec.mesh.C[:, 1], kind="stable")
+    assert np.abs(oc.U[order, 0] - v).max() <= 1e-13
+    assert np.abs(oc.U[:, 1:]).max() == 0.0 and np.abs(oc.p).max() == 0.0
+
+
+def test_T18_couette_startup_converges_to_the_series_solution():
+    """Against the exact start-up solution u = y + sum_m 2 (-1)^m /(m pi)
+    sin(m pi y) exp(-nu m^2 pi^2 t): halving h and quartering dt (second order
+    in space, first in time) divides the error at t = 0.05 by about 4; and
+    long after the start the discrete profile is the linear Couette profile
+    u = y exactly (the two-point flux with half-cell wall distances is exact
+    for a linear field)."""
+    nu, T = 1.0, 0.05
+
+    def exact(y, t):
+        m = np.arange(1, 400)[:, None]
+        return y + np.sum(2 * (-1.0) ** m / (m * np.pi) * np.sin(m * np.pi * y) * np.exp(-nu * (m * np.pi) ** 2 * t),
+                          axis=0)
+
+    errs = []
+    for n, steps in ((16, 10), (32, 40)):
+        spec = _couette_startup(n, nu, T / steps)
+        oc = orc.OracleCase(spec)
+        assert oc.piso(steps)[0] == 0
+        y = spec.mesh.C[:, 1]
+        errs.append(np.abs(oc.U[:, 0] - exact(y, T)).max())
+    assert 3.0 <= errs[0] / errs[1] <= 5.0, errs
+    spec = _couette_startup(16, nu, 0.05)
+    oc = orc.OracleCase(spec)
+    assert oc.piso(200)[0] == 0
+    assert np.abs(oc.U[:, 0] - spec.mesh.C[:, 1]).max() <= 1e-12
