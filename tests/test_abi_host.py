@@ -216,3 +216,26 @@ def test_dic_workspace_is_per_cell():
         expect = 5 * 8 * N + 4 * N + 6 * (4 + 4 + 8) * N
         # each of the 12 arrays is aligned on 256 bytes
         assert expect <= dic - base <= expect + 12 * 256
+
+
+def test_binding_arity_matches_the_header():
+    """Every exported call's parameter count in include/fvm.h equals the
+    number of argument types the ctypes binding declares for it (a call
+    whose signature changed on one side only would pass garbage)."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "include", "fvm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    L = fvm.lib()
+    checked = 0
+    for name in fvm.EXPORTS:
+        m = re.search(r"\b" + name + r"\s*\(([^;]*?)\)\s*;", text, flags=re.S)
+        assert m, name
+        params = [p for p in m.group(1).split(",") if p.strip()]
+        n = 0 if params == ["void"] or [p.strip() for p in params] == ["void"] else len(params)
+        argtypes = getattr(L, name).argtypes
+        if argtypes is None:
+            assert n == 0, name
+            continue
+        assert len(argtypes) == n, (name, n, len(argtypes))
+        checked += 1
+    assert checked >= len(fvm.EXPORTS) - 1
